@@ -1,0 +1,241 @@
+/*
+ * dvnr.h -- C ABI of the MI355X (gfx950) DVNR hot path.
+ *
+ * DVNR (distributed volumetric neural representation) trains one implicit
+ * neural representation (INR) per box-shaped volume partition ("block"),
+ * independently of every other block (paper Sec. III-A, model parallelism).
+ * Each INR maps a block-normalized position x in [0,1]^3 to a normalized
+ * value (Eq. (1)); it is a multiresolution hash-grid encoding followed by a
+ * small bias-free ReLU MLP (Sec. III).  Training draws uniform random
+ * coordinates, fetches trilinearly interpolated ground truth from the block's
+ * voxels, and takes Adam steps on an L2 loss (Sec. III-B, III-F).  Trained
+ * models are queried at arbitrary coordinates or decoded back to the voxel
+ * grid (Sec. III, on-demand inference and decoding).
+ *
+ * Conventions
+ *  - Every pointer argument documented as "device" is a device address
+ *    (allocated by the caller, e.g. with torch); "host" pointers are ordinary
+ *    host memory.  The library allocates no device memory of its own: the
+ *    caller sizes the buffers with dvnr_get_sizes() and hands them over with
+ *    dvnr_bind().  Device buffers must be 256-byte aligned.
+ *  - Every entry point that launches work takes a hipStream_t (passed as
+ *    void*; NULL = the default stream) and only enqueues; no entry point
+ *    synchronizes except dvnr_sync() and dvnr_mse_fp64() (which returns a host
+ *    value).
+ *  - Status codes: DVNR_OK (0) on success.  Argument errors are reported
+ *    synchronously and leave the handle unchanged; the message is available
+ *    from dvnr_last_error() (thread-local, valid until the next call on the
+ *    same thread).  No C++ exception crosses this boundary.
+ *  - A handle is not thread-safe; calls on one handle must be serialized.
+ *
+ * Parameter layout (one block; blocks are concatenated at a stride of
+ * `block_stride` elements, so block b starts at element b*block_stride):
+ *    level tables  [sum_l E_l][F]      (feature-minor; level l starts at entry
+ *                                       off_l, E_l = R_l^3 if R_l^3 <= T else T)
+ *    W_1           [width][L*F]        (row-major, out x in)
+ *    W_2..W_K      [width][width]
+ *    W_out         [out_dim][width]
+ * The same element index space is used by the master parameters, gradients,
+ * Adam moments and (mixed precision) the 16-bit working copy.
+ */
+#ifndef DVNR_H
+#define DVNR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dvnr_status;
+enum {
+  DVNR_OK = 0,
+  DVNR_E_INVALID = 1,      /* bad argument or configuration */
+  DVNR_E_UNSUPPORTED = 2,  /* valid but not compiled / not implemented for this shape */
+  DVNR_E_HIP = 3,          /* a HIP runtime call failed */
+  DVNR_E_STATE = 4,        /* call made in the wrong order (e.g. before dvnr_bind) */
+  DVNR_E_NONFINITE = 5     /* a non-finite training loss was observed */
+};
+
+typedef struct dvnr dvnr_t; /* opaque handle */
+
+/* Multiresolution grid (Sec. III, encoding of the cited instant neural
+ * graphics primitives).  R_l = floor(base_resolution * b^l + 1e-6) vertices
+ * per axis, b = per_level_scale if > 0, else
+ * (finest_resolution / base_resolution)^(1/(n_levels-1)).  A level with
+ * R_l^3 <= 2^log2_table_size is stored densely, otherwise hashed. */
+typedef struct dvnr_encoding {
+  int32_t n_levels;          /* L, 1..16 */
+  int32_t n_features;        /* F, 1, 2, 4 or 8; L*F <= 32 */
+  int32_t log2_table_size;   /* log2 T, 4..24 */
+  int32_t base_resolution;   /* R_0 >= 2 */
+  double per_level_scale;    /* b, or 0 to derive it from finest_resolution */
+  int32_t finest_resolution; /* used when per_level_scale == 0 */
+} dvnr_encoding;
+
+/* Bias-free MLP with ReLU after every hidden layer, linear output (Sec. III). */
+typedef struct dvnr_mlp {
+  int32_t n_hidden_layers; /* 1..4 */
+  int32_t width;           /* 16, 32 or 64 */
+  int32_t out_dim;         /* must be 1 (scalar fields) */
+} dvnr_mlp;
+
+/* Adam with L2 weight decay added to the gradient (Sec. III-F). */
+typedef struct dvnr_optim {
+  double lr, beta1, beta2, eps, weight_decay;
+} dvnr_optim;
+
+typedef enum dvnr_precision {
+  DVNR_FP32 = 0,       /* plain: fp32 tables and MLP, one thread per sample, plain atomics */
+  DVNR_MIXED_BF16 = 1, /* fp16 tables + bf16 MFMA MLP (fp32 accumulation), fp32 masters */
+  DVNR_FP64 = 2        /* fp64 everywhere; building blocks for gradient checking */
+} dvnr_precision;
+
+/* One block: owned voxels per axis (x, y, z) and the width of the halo of
+ * ghost voxels stored around them (Sec. III-C). */
+typedef struct dvnr_block {
+  int32_t dims[3];
+  int32_t ghost;
+} dvnr_block;
+
+typedef struct dvnr_sizes {
+  int64_t n_levels;
+  int64_t n_entries;        /* table entries per block */
+  int64_t n_table_params;   /* n_entries * F */
+  int64_t n_mlp_params;
+  int64_t block_stride;     /* elements between consecutive blocks (>= table + mlp, multiple of 64) */
+  int64_t n_params;         /* n_blocks * block_stride */
+  int64_t param_bytes;      /* bytes of one parameter-sized buffer: 4 (fp32) or 8 (fp64) per element */
+  int64_t work16_bytes;     /* mixed precision 16-bit working copy (0 otherwise) */
+  int64_t workspace_bytes;  /* scratch for up to max_batch samples per step */
+} dvnr_sizes;
+
+typedef struct dvnr_buffers {
+  void* params;             /* device, master parameters (fp32; fp64 for DVNR_FP64) */
+  void* grads;              /* device, same type and size */
+  void* adam_m;             /* device, same type and size */
+  void* adam_v;             /* device, same type and size */
+  void* work16;             /* device, mixed only: fp16 table / bf16 MLP copies, 2 B per element */
+  void* workspace;          /* device, workspace_bytes */
+  const float* const* volumes; /* host array of n_blocks device pointers: each block's voxels,
+                                  float32 [nz+2g][ny+2g][nx+2g] (x fastest), read-only, zero-copy */
+} dvnr_buffers;
+
+/* Create a handle for n_blocks INRs sharing one configuration.
+ * max_batch: the largest total number of training samples per step (all
+ * blocks together) and the largest chunk used by decode/sample.
+ * Returns DVNR_E_INVALID for out-of-range settings.  Allocates host memory only. */
+dvnr_status dvnr_create(const dvnr_encoding* enc, const dvnr_mlp* mlp, const dvnr_optim* opt,
+                        dvnr_precision precision, int32_t n_blocks, const dvnr_block* blocks,
+                        int64_t max_batch, uint64_t seed, dvnr_t** out);
+void dvnr_destroy(dvnr_t* h);
+const char* dvnr_last_error(void);
+
+dvnr_status dvnr_get_sizes(const dvnr_t* h, dvnr_sizes* out);
+/* Host copy of the level table: R[l], dense[l] (0/1), entry offset off[l], entries E[l].
+ * Each array has n_levels elements; any pointer may be NULL. */
+dvnr_status dvnr_level_info(const dvnr_t* h, int32_t* R, int32_t* dense, int64_t* off, int64_t* E);
+
+/* Bind caller-owned buffers (see dvnr_buffers).  Rebinding is allowed. */
+dvnr_status dvnr_bind(dvnr_t* h, const dvnr_buffers* b);
+
+/* Per-block value range over every stored voxel, ghosts included (Sec. III-A
+ * output normalization).  Must run once after dvnr_bind and before training,
+ * sampling or decoding; enqueued on `stream`. */
+dvnr_status dvnr_prepare(dvnr_t* h, void* stream);
+/* Host copy of the per-block ranges computed by dvnr_prepare (synchronizes the stream). */
+dvnr_status dvnr_get_ranges(dvnr_t* h, float* vmin, float* vmax, void* stream);
+
+/* Initialize masters: tables U(-1e-4, 1e-4), weights Glorot-uniform, drawn
+ * with Philox4x32-10 from `seed`; clears gradients and the optimizer state. */
+dvnr_status dvnr_init_params(dvnr_t* h, uint64_t seed, void* stream);
+/* After the caller overwrote the master parameters: refresh the 16-bit copy
+ * (mixed precision; no-op otherwise) and clear gradients. */
+dvnr_status dvnr_params_updated(dvnr_t* h, void* stream);
+/* Warm start (Sec. III-E weight caching): keep the parameters, zero the Adam
+ * moments and the step counter. */
+dvnr_status dvnr_reset_optimizer(dvnr_t* h, void* stream);
+
+/* n_steps optimizer steps.  Each step draws samples_per_step uniform
+ * coordinates split over blocks in proportion to owned voxel counts
+ * (largest remainder in units of 256), with Philox4x32-10 counter
+ * (sample, step, block, 'DVNR') and key (seed lo, seed hi); then forward,
+ * L2 loss (mean per block), backward and Adam.  loss_out: device float
+ * [n_steps][n_blocks] or NULL.  samples_per_step <= max_batch. */
+dvnr_status dvnr_train_steps(dvnr_t* h, int32_t n_steps, int64_t samples_per_step, float* loss_out,
+                             void* stream);
+/* One optimizer step on caller-given coordinates: coords device float
+ * [sum_b n_b][3] grouped by block, n_per_block host int64[n_blocks].
+ * loss_out: device float [n_blocks] or NULL. */
+dvnr_status dvnr_train_step_coords(dvnr_t* h, const float* coords, const int64_t* n_per_block,
+                                   float* loss_out, void* stream);
+
+/* Training samples of one block at step `step` as dvnr_train_steps draws
+ * them: coords device float [n][3], target device float [n] (normalized). */
+dvnr_status dvnr_draw_training_samples(dvnr_t* h, int32_t block, int64_t step, int64_t n, float* coords,
+                                       float* target, void* stream);
+
+/* On-demand inference (Sec. III): out[i] = INR_b(coords[i]) de-normalized with
+ * the block range.  coords device float [n][3], out device float [n]. */
+dvnr_status dvnr_sample(dvnr_t* h, int32_t block, int64_t n, const float* coords, float* out, void* stream);
+/* Decode block b to its owned voxel grid at voxel centers (i+1/2)/n:
+ * out device float [nz][ny][nx] (x fastest), de-normalized. */
+dvnr_status dvnr_decode(dvnr_t* h, int32_t block, float* out, void* stream);
+/* Sum of squared differences (fp64 accumulation) between a decoded block and
+ * the block's owned stored voxels: host *sse, *count.  Synchronizes `stream`. */
+dvnr_status dvnr_mse_fp64(dvnr_t* h, int32_t block, const float* decoded, double* sse, int64_t* count,
+                          void* stream);
+
+/* Autograd building blocks of block `block`.  Element type is double for a
+ * DVNR_FP64 handle, float otherwise.  All pointers are device pointers.
+ *  encode_forward : coords float [n][3] -> feats [n][L*F] using table params
+ *  encode_backward: dtable [n_table_params] += d(feats)/d(table)^T dfeats
+ *  mlp_forward    : feats [n][L*F] -> out [n] (normalized INR output)
+ *  mlp_backward   : given dout [n]: dfeats [n][L*F] (overwritten), dweights
+ *                   [n_mlp_params] (accumulated); recomputes the forward.
+ * `table` / `weights` point at the block's table / MLP parameters. */
+dvnr_status dvnr_encode_forward(dvnr_t* h, int64_t n, const float* coords, const void* table, void* feats,
+                                void* stream);
+dvnr_status dvnr_encode_backward(dvnr_t* h, int64_t n, const float* coords, const void* dfeats, void* dtable,
+                                 void* stream);
+dvnr_status dvnr_mlp_forward(dvnr_t* h, int64_t n, const void* feats, const void* weights, void* out,
+                             void* stream);
+dvnr_status dvnr_mlp_backward(dvnr_t* h, int64_t n, const void* feats, const void* weights, const void* dout,
+                              void* dfeats, void* dweights, void* stream);
+
+/* Parity/debug: corner entry indices (within level `level`) and trilinear
+ * weights of n coordinates: idx device uint32 [n][8], w device float [n][8]. */
+dvnr_status dvnr_debug_indices(dvnr_t* h, int32_t level, int64_t n, const float* coords, uint32_t* idx, float* w,
+                               void* stream);
+
+/* Per-phase device time in milliseconds, summed over the training steps run
+ * with the "profile_phases" option since the previous call (those steps run
+ * eagerly, with HIP events on the training stream between the phases):
+ * ms6[0] sampler, [1] encoding forward, [2] MLP forward/loss/backward,
+ * [3] encoding backward (scatter), [4] weight-gradient reduction, [5] Adam.
+ * *n_steps (may be NULL) receives the number of steps covered.  Waits for
+ * those steps to finish; resets the sums. */
+dvnr_status dvnr_phase_times(dvnr_t* h, double* ms6, int64_t* n_steps);
+
+/* Wait for `stream`; reports HIP errors and a non-finite loss seen since the
+ * last dvnr_sync (DVNR_E_NONFINITE). */
+dvnr_status dvnr_sync(dvnr_t* h, void* stream);
+
+/* Options (runtime switches):
+ *  "scatter_grouped" 0/1 : grouped-lane scatter (default 1 for mixed, 0 for fp32)
+ *  "use_graph"       0/1 : capture one step in a hipGraph and replay it on a
+ *                          non-default stream (default 1)
+ *  "xcd_map"         0/1 : XCD-aware level-to-workgroup mapping (default 1)
+ *  "apply_update"    0/1 : run the Adam update after the backward (default 1).
+ *                          With 0 a step leaves this step's gradient in `grads`
+ *                          (parity checks of the backward).
+ *  "profile_phases"  0/1 : record HIP events between the phases of every
+ *                          training step (steps then run without a graph);
+ *                          read with dvnr_phase_times().
+ * Returns DVNR_E_INVALID for an unknown name. */
+dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DVNR_H */

@@ -1,0 +1,124 @@
+// Device helpers shared by the DVNR kernels: counter-based random numbers,
+// grid positions, corner indices and trilinear weights.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dvnr_internal.h"
+
+namespace dvnrk {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies with Weyl-sequence key bumps between rounds.
+// ---------------------------------------------------------------------------
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+  }
+  return c;
+}
+
+constexpr uint32_t kCoordTag = 0x44564E52u;  // 'DVNR': fourth counter word of coordinate draws
+constexpr uint32_t kInitTag = 0x494E4954u;   // 'INIT': parameter initialization draws
+
+// uniform in [0,1): top 24 bits scaled by 2^-24 (exact in float32)
+__device__ __forceinline__ float u24(uint32_t u) { return (float)(u >> 8) * 5.9604644775390625e-8f; }
+
+// ---------------------------------------------------------------------------
+// Grid position on a level of R vertices per axis.  x is clamped to [0,1];
+// p = x*(R-1) is a single round-to-nearest float multiply (never contracted
+// into an FMA), i0 = min(floor(p), R-2), t = p - i0 (exact).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void grid_pos(float x, float scale, int R, int& i0, float& t) {
+  x = fminf(fmaxf(x, 0.0f), 1.0f);
+  const float p = __fmul_rn(x, scale);
+  int i = (int)floorf(p);
+  i = min(i, R - 2);
+  i0 = i;
+  t = __fsub_rn(p, (float)i);
+}
+
+// Spatial hash of the multiresolution hash encoding: XOR of coordinate
+// times prime (1, 2654435761, 805459861) modulo 2^32, masked to the table.
+__device__ __forceinline__ uint32_t corner_index(int dense, int R, uint32_t mask, uint32_t vx, uint32_t vy,
+                                                 uint32_t vz) {
+  if (dense) return vx + (uint32_t)R * (vy + (uint32_t)R * vz);
+  return (vx ^ (vy * 2654435761u) ^ (vz * 805459861u)) & mask;
+}
+
+// The 8 corner indices and weights of one sample on one level (corner c =
+// cx + 2cy + 4cz).
+struct Corners {
+  uint32_t idx[8];
+  float w[8];
+};
+
+__device__ __forceinline__ void level_corners(const LevelDesc& ld, int l, float x, float y, float z, Corners& c) {
+  int ix, iy, iz;
+  float tx, ty, tz;
+  const int R = ld.R[l];
+  const float sc = ld.scale[l];
+  grid_pos(x, sc, R, ix, tx);
+  grid_pos(y, sc, R, iy, ty);
+  grid_pos(z, sc, R, iz, tz);
+  const int dense = ld.dense[l];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
+    c.idx[k] = corner_index(dense, R, ld.T_mask, ix + cx, iy + cy, iz + cz);
+    c.w[k] = (cx ? tx : 1.0f - tx) * (cy ? ty : 1.0f - ty) * (cz ? tz : 1.0f - tz);
+  }
+}
+
+// Wave-level helpers
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t xcc_id() {
+  // hardware register XCC_ID, bits [3:0]: the accelerator complex die this wave runs on
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xf;
+}
+
+// Map a linear workgroup id of a level-major launch to (tile, level).  With
+// xcd_map, workgroups dispatched to XCD x (round-robin dispatch puts
+// workgroup w on XCD w % 8) work on levels l with l % 8 == x, so that each
+// XCD's L2 holds only its own levels' tables.  Any mapping is correct; this
+// one only improves locality.  Returns false for idle workgroups.
+__device__ __forceinline__ bool level_major_item(int wg, int L, int n_tiles, int xcd_map, int& tile, int& level) {
+  if (xcd_map && L >= 8) {
+    const int lp = (L + 7) / 8;
+    const int x = wg & 7, r = wg >> 3;
+    const int slot = r % lp;
+    tile = r / lp;
+    level = x + 8 * slot;
+    return level < L && tile < n_tiles;
+  }
+  level = wg % L;
+  tile = wg / L;
+  return tile < n_tiles;
+}
+
+__host__ __device__ inline int level_major_grid(int L, int n_tiles, int xcd_map) {
+  if (xcd_map && L >= 8) return 8 * ((L + 7) / 8) * n_tiles;
+  return L * n_tiles;
+}
+
+}  // namespace dvnrk

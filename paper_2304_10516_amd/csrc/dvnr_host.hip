@@ -1,0 +1,839 @@
+// Host side of the DVNR C ABI (include/dvnr.h): configuration checks, storage
+// layout, workspace carving, per-step sample plans, the training step
+// sequence and its hipGraph capture.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dvnr.h"
+#include "dvnr_internal.h"
+
+using namespace dvnrk;
+
+namespace {
+
+thread_local std::string g_err;
+
+dvnr_status fail(dvnr_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                             \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) return fail(DVNR_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct dvnr {
+  dvnr_encoding enc{};
+  dvnr_mlp mlp{};
+  dvnr_optim opt{};
+  Prec prec = Prec::F32;
+  int nb = 0;
+  std::vector<dvnr_block> blocks;
+  int64_t max_batch = 0;
+  uint64_t seed = 0;
+
+  LevelDesc ld{};
+  MlpDesc md{};
+  int64_t n_entries = 0, n_table = 0, n_mlp = 0, stride = 0, n_params = 0;
+
+  // workspace layout (byte offsets)
+  int64_t o_meta = 0, o_range = 0, o_plan = 0, o_ctr = 0, o_vox = 0, o_tiles = 0, o_ranges = 0, o_coords = 0,
+          o_target = 0, o_feat = 0, o_dfeat = 0, o_out = 0, o_slots = 0, o_ring = 0, o_mse = 0, ws_bytes = 0;
+  int64_t max_tiles = 0, slot_stride = 0, n_slots = 0, feat_elem = 0;
+
+  dvnr_buffers buf{};
+  std::vector<const float*> vols;
+  bool bound = false, prepared = false;
+
+  // current training plan
+  int64_t plan_total = -1;
+  int n_tiles = 0, mlp_grid = 0;
+  std::vector<BlockPlan> hplan;
+  std::vector<Tile> htiles;
+  std::vector<int32_t> hranges;
+
+  int64_t host_step = 0;  // mirror of the device step counter
+  int scatter_grouped = 0;
+  int use_graph = 1;
+  int xcd_map = 1;
+  int apply_update = 1;
+  // per-phase event timing (eager steps only): ring of kProfRing steps x 7 events
+  static constexpr int kProfRing = 128;
+  int profile = 0;
+  std::vector<hipEvent_t> prof_ev;
+  int64_t prof_recorded = 0, prof_accumulated = 0;
+  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+  hipGraphExec_t graph = nullptr;
+  hipStream_t graph_stream = nullptr;
+  int64_t graph_total = -1;
+
+  unsigned char* ws() const { return (unsigned char*)buf.workspace; }
+  BlockMeta* d_meta() const { return (BlockMeta*)(ws() + o_meta); }
+  BlockRange* d_range() const { return (BlockRange*)(ws() + o_range); }
+  BlockPlan* d_plan() const { return (BlockPlan*)(ws() + o_plan); }
+  Counters* d_ctr() const { return (Counters*)(ws() + o_ctr); }
+  int64_t* d_vox() const { return (int64_t*)(ws() + o_vox); }
+  Tile* d_tiles() const { return (Tile*)(ws() + o_tiles); }
+  int32_t* d_ranges() const { return (int32_t*)(ws() + o_ranges); }
+  float* d_coords() const { return (float*)(ws() + o_coords); }
+  float* d_target() const { return (float*)(ws() + o_target); }
+  void* d_feat() const { return (void*)(ws() + o_feat); }
+  float* d_dfeat() const { return (float*)(ws() + o_dfeat); }
+  float* d_out() const { return (float*)(ws() + o_out); }
+  float* d_slots() const { return (float*)(ws() + o_slots); }
+  float* d_ring() const { return (float*)(ws() + o_ring); }
+  double* d_mse() const { return (double*)(ws() + o_mse); }
+  size_t pelem() const { return prec == Prec::F64 ? 8 : 4; }
+
+  ~dvnr() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
+  }
+};
+
+static int64_t owned_voxels(const dvnr_block& b) { return (int64_t)b.dims[0] * b.dims[1] * b.dims[2]; }
+static int64_t stored_voxels(const dvnr_block& b) {
+  return (int64_t)(b.dims[0] + 2 * b.ghost) * (b.dims[1] + 2 * b.ghost) * (b.dims[2] + 2 * b.ghost);
+}
+
+// Per-level vertex resolutions R_l = floor(R_0 * b^l + 1e-6) (see dvnr.h).
+static bool build_levels(const dvnr_encoding& e, LevelDesc& ld, int64_t& n_entries, std::string& err) {
+  const int L = e.n_levels;
+  double b;
+  if (e.per_level_scale > 0) {
+    b = e.per_level_scale;
+  } else if (L == 1) {
+    b = 1.0;
+  } else {
+    if (e.finest_resolution < e.base_resolution) {
+      err = "finest_resolution must be >= base_resolution";
+      return false;
+    }
+    b = std::exp(std::log((double)e.finest_resolution / (double)e.base_resolution) / (double)(L - 1));
+  }
+  const int64_t T = (int64_t)1 << e.log2_table_size;
+  ld.L = L;
+  ld.F = e.n_features;
+  ld.log2T = e.log2_table_size;
+  ld.in_dim = L * e.n_features;
+  ld.T_mask = (uint32_t)(T - 1);
+  int64_t off = 0;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    ld.R[l] = 2;
+    ld.dense[l] = 1;
+    ld.off[l] = 0;
+    ld.scale[l] = 1.0f;
+  }
+  for (int l = 0; l < L; ++l) {
+    const int64_t R = (int64_t)std::floor((double)e.base_resolution * std::pow(b, (double)l) + 1e-6);
+    if (R < 2 || R > (1 << 20)) {
+      err = "level resolution out of range [2, 2^20]";
+      return false;
+    }
+    const bool dense = R * R * R <= T;
+    const int64_t E = dense ? R * R * R : T;
+    ld.R[l] = (int32_t)R;
+    ld.dense[l] = dense ? 1 : 0;
+    ld.off[l] = (int32_t)off;
+    ld.scale[l] = (float)(R - 1);
+    off += E;
+  }
+  n_entries = off;
+  if (off * e.n_features >= ((int64_t)1 << 31)) {
+    err = "table too large";
+    return false;
+  }
+  return true;
+}
+
+extern "C" {
+
+const char* dvnr_last_error(void) { return g_err.c_str(); }
+
+dvnr_status dvnr_create(const dvnr_encoding* enc, const dvnr_mlp* mlp, const dvnr_optim* opt,
+                        dvnr_precision precision, int32_t n_blocks, const dvnr_block* blocks, int64_t max_batch,
+                        uint64_t seed, dvnr_t** out) {
+  try {
+    if (!enc || !mlp || !opt || !blocks || !out) return fail(DVNR_E_INVALID, "null argument");
+    *out = nullptr;
+    const dvnr_encoding& e = *enc;
+    if (e.n_levels < 1 || e.n_levels > kMaxLevels) return fail(DVNR_E_INVALID, "n_levels must be in [1, 16]");
+    if (!(e.n_features == 1 || e.n_features == 2 || e.n_features == 4 || e.n_features == 8))
+      return fail(DVNR_E_INVALID, "n_features must be 1, 2, 4 or 8");
+    if (e.n_levels * e.n_features > 32) return fail(DVNR_E_INVALID, "n_levels * n_features must be <= 32");
+    if (e.log2_table_size < 4 || e.log2_table_size > 24) return fail(DVNR_E_INVALID, "log2_table_size must be in [4, 24]");
+    if (e.base_resolution < 2) return fail(DVNR_E_INVALID, "base_resolution must be >= 2");
+    if (!(mlp->width == 16 || mlp->width == 32 || mlp->width == 64))
+      return fail(DVNR_E_INVALID, "width must be 16, 32 or 64");
+    if (mlp->n_hidden_layers < 1 || mlp->n_hidden_layers > 3)
+      return fail(DVNR_E_INVALID, "n_hidden_layers must be in [1, 3]");
+    if (mlp->out_dim != 1) return fail(DVNR_E_UNSUPPORTED, "out_dim must be 1");
+    if (precision < DVNR_FP32 || precision > DVNR_FP64) return fail(DVNR_E_INVALID, "bad precision");
+    if (n_blocks < 1 || n_blocks > 1024) return fail(DVNR_E_INVALID, "n_blocks must be in [1, 1024]");
+    if (max_batch < 256 || max_batch > ((int64_t)1 << 28)) return fail(DVNR_E_INVALID, "max_batch must be in [256, 2^28]");
+    if (!(opt->lr > 0) || !(opt->beta1 >= 0 && opt->beta1 < 1) || !(opt->beta2 >= 0 && opt->beta2 < 1) ||
+        !(opt->eps > 0) || !(opt->weight_decay >= 0))
+      return fail(DVNR_E_INVALID, "bad optimizer settings");
+    for (int b = 0; b < n_blocks; ++b) {
+      const dvnr_block& bl = blocks[b];
+      if (bl.dims[0] < 1 || bl.dims[1] < 1 || bl.dims[2] < 1 || bl.ghost < 0 || bl.ghost > 8)
+        return fail(DVNR_E_INVALID, "block dims must be >= 1 and ghost in [0, 8]");
+      if (bl.dims[0] + 2 * bl.ghost < 2 || bl.dims[1] + 2 * bl.ghost < 2 || bl.dims[2] + 2 * bl.ghost < 2)
+        return fail(DVNR_E_INVALID, "each stored block axis needs >= 2 voxels");
+      if (stored_voxels(bl) >= ((int64_t)1 << 31)) return fail(DVNR_E_INVALID, "block too large");
+    }
+    dvnr* h = new dvnr();
+    h->enc = e;
+    h->mlp = *mlp;
+    h->opt = *opt;
+    h->prec = (Prec)precision;
+    h->nb = n_blocks;
+    h->blocks.assign(blocks, blocks + n_blocks);
+    h->max_batch = max_batch;
+    h->seed = seed;
+    std::string err;
+    if (!build_levels(e, h->ld, h->n_entries, err)) {
+      delete h;
+      return fail(DVNR_E_INVALID, err);
+    }
+    h->n_table = h->n_entries * e.n_features;
+    MlpDesc& md = h->md;
+    md.n_hidden = mlp->n_hidden_layers;
+    md.width = mlp->width;
+    md.in_dim = e.n_levels * e.n_features;
+    int64_t pos = 0;
+    for (int k = 0; k <= md.n_hidden; ++k) {
+      md.off[k] = (int32_t)pos;
+      const int fan_in = k == 0 ? md.in_dim : md.width;
+      const int fan_out = k == md.n_hidden ? 1 : md.width;
+      pos += (int64_t)fan_in * fan_out;
+    }
+    for (int k = md.n_hidden + 1; k < 6; ++k) md.off[k] = (int32_t)pos;
+    md.n_mlp = (int32_t)pos;
+    h->n_mlp = pos;
+    h->stride = align_up(h->n_table + h->n_mlp, 64);
+    h->n_params = h->stride * n_blocks;
+    h->scatter_grouped = (h->prec == Prec::MIXED) ? 1 : 0;
+
+    // workspace carving
+    const int64_t A = 256;
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+      const int64_t at = o;
+      o = align_up(o + std::max<int64_t>(bytes, 1), A);
+      return at;
+    };
+    h->max_tiles = max_batch / kTile + n_blocks + 1;
+    h->slot_stride = align_up(h->n_mlp + 1, 64);
+    h->n_slots = (int64_t)(kMlpGrid + n_blocks) * 4;
+    h->feat_elem = h->prec == Prec::MIXED ? 2 : (h->prec == Prec::F64 ? 8 : 4);
+    const int64_t in_dim = md.in_dim;
+    h->o_meta = take(sizeof(BlockMeta) * n_blocks);
+    h->o_range = take(sizeof(BlockRange) * n_blocks);
+    h->o_plan = take(sizeof(BlockPlan) * n_blocks);
+    h->o_ctr = take(sizeof(Counters));
+    h->o_vox = take(sizeof(int64_t) * n_blocks);
+    h->o_tiles = take(sizeof(Tile) * h->max_tiles);
+    h->o_ranges = take(sizeof(int32_t) * 2 * n_blocks);
+    h->o_coords = take(sizeof(float) * 3 * max_batch);
+    h->o_target = take(sizeof(float) * max_batch);
+    h->o_feat = take(h->feat_elem * in_dim * max_batch);
+    h->o_dfeat = take((h->prec == Prec::F64 ? 8 : 4) * in_dim * max_batch);
+    h->o_out = take(sizeof(float) * max_batch);
+    h->o_slots = take(sizeof(float) * h->n_slots * h->slot_stride);
+    h->o_ring = take(sizeof(float) * kLossRing * n_blocks);
+    h->o_mse = take(sizeof(double) * 8);
+    h->ws_bytes = o;
+    *out = h;
+    return DVNR_OK;
+  } catch (const std::exception& ex) {
+    return fail(DVNR_E_INVALID, ex.what());
+  } catch (...) {
+    return fail(DVNR_E_INVALID, "unknown error");
+  }
+}
+
+void dvnr_destroy(dvnr_t* h) {
+  try {
+    delete h;
+  } catch (...) {
+  }
+}
+
+dvnr_status dvnr_get_sizes(const dvnr_t* h, dvnr_sizes* out) {
+  if (!h || !out) return fail(DVNR_E_INVALID, "null argument");
+  out->n_levels = h->enc.n_levels;
+  out->n_entries = h->n_entries;
+  out->n_table_params = h->n_table;
+  out->n_mlp_params = h->n_mlp;
+  out->block_stride = h->stride;
+  out->n_params = h->n_params;
+  out->param_bytes = h->n_params * (int64_t)h->pelem();
+  out->work16_bytes = h->prec == Prec::MIXED ? h->n_params * 2 : 0;
+  out->workspace_bytes = h->ws_bytes;
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_level_info(const dvnr_t* h, int32_t* R, int32_t* dense, int64_t* off, int64_t* E) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  const int64_t T = (int64_t)1 << h->enc.log2_table_size;
+  for (int l = 0; l < h->enc.n_levels; ++l) {
+    if (R) R[l] = h->ld.R[l];
+    if (dense) dense[l] = h->ld.dense[l];
+    if (off) off[l] = h->ld.off[l];
+    if (E) E[l] = h->ld.dense[l] ? (int64_t)h->ld.R[l] * h->ld.R[l] * h->ld.R[l] : T;
+  }
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_bind(dvnr_t* h, const dvnr_buffers* b) {
+  try {
+    if (!h || !b) return fail(DVNR_E_INVALID, "null argument");
+    if (!b->params || !b->grads || !b->adam_m || !b->adam_v || !b->workspace || !b->volumes)
+      return fail(DVNR_E_INVALID, "missing buffer");
+    if (h->prec == Prec::MIXED && !b->work16) return fail(DVNR_E_INVALID, "mixed precision needs work16");
+    const void* ptrs[] = {b->params, b->grads, b->adam_m, b->adam_v, b->workspace, b->work16};
+    for (const void* p : ptrs)
+      if (p && ((uintptr_t)p % 256)) return fail(DVNR_E_INVALID, "device buffers must be 256-byte aligned");
+    for (int i = 0; i < h->nb; ++i)
+      if (!b->volumes[i]) return fail(DVNR_E_INVALID, "missing block volume");
+    h->buf = *b;
+    h->vols.assign(b->volumes, b->volumes + h->nb);
+    h->buf.volumes = h->vols.data();
+    std::vector<BlockMeta> meta(h->nb);
+    std::vector<int64_t> vox(h->nb);
+    for (int i = 0; i < h->nb; ++i) {
+      meta[i].vol = h->vols[i];
+      for (int a = 0; a < 3; ++a) meta[i].dims[a] = h->blocks[i].dims[a];
+      meta[i].ghost = h->blocks[i].ghost;
+      meta[i].param_off = (int64_t)i * h->stride;
+      vox[i] = stored_voxels(h->blocks[i]);
+    }
+    HIPCHK(hipMemcpy(h->d_meta(), meta.data(), sizeof(BlockMeta) * h->nb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->d_vox(), vox.data(), sizeof(int64_t) * h->nb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(h->d_ctr(), 0, sizeof(Counters)));
+    HIPCHK(hipMemset(h->d_slots(), 0, sizeof(float) * h->n_slots * h->slot_stride));
+    HIPCHK(hipMemset(h->d_ring(), 0, sizeof(float) * kLossRing * h->nb));
+    h->host_step = 0;
+    h->plan_total = -1;
+    if (h->graph) {
+      (void)hipGraphExecDestroy(h->graph);
+      h->graph = nullptr;
+    }
+    h->bound = true;
+    h->prepared = false;
+    return DVNR_OK;
+  } catch (...) {
+    return fail(DVNR_E_INVALID, "bind failed");
+  }
+}
+
+dvnr_status dvnr_prepare(dvnr_t* h, void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (!h->bound) return fail(DVNR_E_STATE, "dvnr_prepare before dvnr_bind");
+  HIPCHK(launch_minmax(h->d_meta(), h->d_range(), h->d_ctr(), h->nb, h->d_vox(), (hipStream_t)stream));
+  h->prepared = true;
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_get_ranges(dvnr_t* h, float* vmin, float* vmax, void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (!h->prepared) return fail(DVNR_E_STATE, "call dvnr_prepare first");
+  std::vector<BlockRange> r(h->nb);
+  HIPCHK(hipMemcpyAsync(r.data(), h->d_range(), sizeof(BlockRange) * h->nb, hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  for (int i = 0; i < h->nb; ++i) {
+    if (vmin) vmin[i] = r[i].vmin;
+    if (vmax) vmax[i] = r[i].vmax;
+  }
+  return DVNR_OK;
+}
+
+static dvnr_status clear_optimizer(dvnr_t* h, hipStream_t s) {
+  const int64_t bytes = h->n_params * (int64_t)h->pelem();
+  HIPCHK(launch_zero(h->buf.adam_m, bytes, s));
+  HIPCHK(launch_zero(h->buf.adam_v, bytes, s));
+  HIPCHK(launch_zero(h->buf.grads, bytes, s));
+  HIPCHK(launch_zero(h->d_ctr(), 16, s));  // step counter and non-finite flag
+  h->host_step = 0;
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_init_params(dvnr_t* h, uint64_t seed, void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (!h->bound) return fail(DVNR_E_STATE, "dvnr_init_params before dvnr_bind");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(launch_init_params(h->prec, h->buf.params, h->nb, h->stride, h->n_table, h->md, seed, s));
+  if (h->prec == Prec::MIXED)
+    HIPCHK(launch_refresh16(h->buf.params, (uint16_t*)h->buf.work16, h->nb, h->stride, h->n_table, h->n_mlp, s));
+  return clear_optimizer(h, s);
+}
+
+dvnr_status dvnr_params_updated(dvnr_t* h, void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (!h->bound) return fail(DVNR_E_STATE, "dvnr_params_updated before dvnr_bind");
+  hipStream_t s = (hipStream_t)stream;
+  if (h->prec == Prec::MIXED)
+    HIPCHK(launch_refresh16(h->buf.params, (uint16_t*)h->buf.work16, h->nb, h->stride, h->n_table, h->n_mlp, s));
+  HIPCHK(launch_zero(h->buf.grads, h->n_params * (int64_t)h->pelem(), s));
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_reset_optimizer(dvnr_t* h, void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (!h->bound) return fail(DVNR_E_STATE, "dvnr_reset_optimizer before dvnr_bind");
+  return clear_optimizer(h, (hipStream_t)stream);
+}
+
+// Largest-remainder apportionment of `total` samples in units of 256 by owned voxel count.
+static std::vector<int64_t> apportion(const dvnr_t* h, int64_t total) {
+  std::vector<int64_t> n(h->nb, 0);
+  if (h->nb == 1) {
+    n[0] = total;
+    return n;
+  }
+  const int64_t units = total / kTile;
+  double sum = 0;
+  for (const auto& b : h->blocks) sum += (double)owned_voxels(b);
+  std::vector<double> frac(h->nb);
+  int64_t used = 0;
+  for (int b = 0; b < h->nb; ++b) {
+    const double q = (double)units * (double)owned_voxels(h->blocks[b]) / sum;
+    n[b] = (int64_t)std::floor(q);
+    frac[b] = q - (double)n[b];
+    used += n[b];
+  }
+  std::vector<int> order(h->nb);
+  for (int b = 0; b < h->nb; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return frac[a] > frac[c]; });
+  for (int64_t k = 0; k < units - used; ++k) n[order[k]] += 1;
+  for (auto& v : n) v *= kTile;
+  return n;
+}
+
+// Build and upload a training plan for the given per-block sample counts.
+static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_t s) {
+  int64_t total = 0;
+  for (auto v : n) total += v;
+  if (total > h->max_batch) return fail(DVNR_E_INVALID, "samples per step exceed max_batch");
+  h->hplan.assign(h->nb, BlockPlan{});
+  h->htiles.clear();
+  int64_t off = 0;
+  std::vector<int> first_tile(h->nb, -1), last_tile(h->nb, -1);
+  for (int b = 0; b < h->nb; ++b) {
+    h->hplan[b].sample_off = off;
+    h->hplan[b].n = (int32_t)n[b];
+    h->hplan[b].inv_n = n[b] > 0 ? (float)(1.0 / (double)n[b]) : 0.0f;
+    for (int64_t st = 0; st < n[b]; st += kTile) {
+      if (first_tile[b] < 0) first_tile[b] = (int)h->htiles.size();
+      last_tile[b] = (int)h->htiles.size();
+      h->htiles.push_back(Tile{b, (int32_t)st, (int32_t)std::min<int64_t>(kTile, n[b] - st), 0});
+    }
+    off += n[b];
+  }
+  h->n_tiles = (int)h->htiles.size();
+  if (h->n_tiles > h->max_tiles) return fail(DVNR_E_INVALID, "too many tiles");
+  h->mlp_grid = std::max(1, std::min(kMlpGrid, h->n_tiles));
+  const int G = h->mlp_grid, T = h->n_tiles;
+  auto wg_of_tile = [&](int t) {
+    // the workgroup w with floor(w*T/G) <= t < floor((w+1)*T/G)
+    int w = (int)(((int64_t)t * G) / std::max(T, 1));
+    while (w > 0 && ((int64_t)w * T) / G > t) --w;
+    while (w + 1 < G && ((int64_t)(w + 1) * T) / G <= t) ++w;
+    return w;
+  };
+  h->hranges.assign(2 * h->nb, 0);
+  for (int b = 0; b < h->nb; ++b) {
+    if (first_tile[b] < 0) continue;
+    const int w0 = wg_of_tile(first_tile[b]), w1 = wg_of_tile(last_tile[b]);
+    h->hranges[2 * b] = (w0 + b) * 4;
+    h->hranges[2 * b + 1] = (w1 + b + 1) * 4;
+  }
+  HIPCHK(hipMemcpyAsync(h->d_plan(), h->hplan.data(), sizeof(BlockPlan) * h->nb, hipMemcpyHostToDevice, s));
+  if (h->n_tiles)
+    HIPCHK(hipMemcpyAsync(h->d_tiles(), h->htiles.data(), sizeof(Tile) * h->n_tiles, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->d_ranges(), h->hranges.data(), sizeof(int32_t) * 2 * h->nb, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h->graph) {
+    (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  return DVNR_OK;
+}
+
+// Fold the event times of recorded step `k` (ring slot k % kProfRing) into the sums.
+static dvnr_status prof_accumulate_one(dvnr_t* h, int64_t k) {
+  hipEvent_t* ev = &h->prof_ev[(size_t)(k % dvnr::kProfRing) * 7];
+  HIPCHK(hipEventSynchronize(ev[6]));
+  for (int p = 0; p < 6; ++p) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, ev[p], ev[p + 1]));
+    h->prof_ms[p] += ms;
+  }
+  return DVNR_OK;
+}
+
+// Event marking the boundary before phase p of the step being recorded (p = 6: end).
+static dvnr_status prof_mark(dvnr_t* h, int p, hipStream_t s) {
+  if (!h->profile) return DVNR_OK;
+  if (p == 0) {
+    if (h->prof_ev.empty()) {
+      h->prof_ev.resize((size_t)dvnr::kProfRing * 7);
+      for (auto& e : h->prof_ev) HIPCHK(hipEventCreate(&e));
+    }
+    if (h->prof_recorded - h->prof_accumulated >= dvnr::kProfRing) {
+      dvnr_status st = prof_accumulate_one(h, h->prof_accumulated);
+      if (st) return st;
+      h->prof_accumulated += 1;
+    }
+  }
+  HIPCHK(hipEventRecord(h->prof_ev[(size_t)(h->prof_recorded % dvnr::kProfRing) * 7 + p], s));
+  if (p == 6) h->prof_recorded += 1;
+  return DVNR_OK;
+}
+
+#define PROF(p)                          \
+  do {                                   \
+    dvnr_status st_ = prof_mark(h, p, s); \
+    if (st_) return st_;                 \
+  } while (0)
+
+// One training step on the current plan (coordinates generated when gen != 0).
+static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
+  const bool mixed = h->prec == Prec::MIXED;
+  const int64_t F = h->enc.n_features;
+  PROF(0);
+  HIPCHK(launch_sample(h->d_meta(), h->d_range(), h->d_plan(), h->d_tiles(), h->n_tiles, 0, gen, h->seed, h->d_ctr(),
+                       -1, h->d_coords(), h->d_target(), s));
+  PROF(1);
+  const void* table = mixed ? h->buf.work16 : h->buf.params;
+  HIPCHK(launch_encode(h->prec, mixed ? 1 : 0, h->ld, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
+                       h->d_coords(), table, h->d_feat(), F, h->max_batch * F, h->xcd_map, s));
+  PROF(2);
+  const void* wsrc = mixed ? (const void*)((const uint16_t*)h->buf.work16 + h->n_table)
+                           : (const void*)((const float*)h->buf.params + h->n_table);
+  HIPCHK(launch_mlp_train(h->prec, h->md, h->ld, h->d_meta(), h->d_plan(), h->d_tiles(), h->n_tiles, h->d_feat(),
+                          h->d_target(), wsrc, h->d_dfeat(), h->max_batch, h->d_slots(), h->slot_stride, h->mlp_grid,
+                          s));
+  PROF(3);
+  HIPCHK(launch_scatter(Prec::F32, h->ld, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(), h->d_coords(),
+                        h->d_dfeat(), F, h->max_batch * F, h->buf.grads, h->scatter_grouped, h->xcd_map, s));
+  PROF(4);
+  HIPCHK(launch_reduce_slots(h->d_slots(), h->slot_stride, h->d_ranges(), h->nb, h->n_mlp, h->n_table, h->stride,
+                             Prec::F32, h->buf.grads, h->d_ring(), h->d_ctr(), 1, s));
+  PROF(5);
+  if (!h->apply_update) {
+    PROF(6);
+    return DVNR_OK;
+  }
+  HIPCHK(launch_adam(h->prec, h->buf.params, h->buf.grads, h->buf.adam_m, h->buf.adam_v,
+                     mixed ? (uint16_t*)h->buf.work16 : nullptr, h->nb, h->stride, h->n_table, h->n_table + h->n_mlp,
+                     h->d_ctr(), h->opt.lr, h->opt.beta1, h->opt.beta2, h->opt.eps, h->opt.weight_decay, s));
+  PROF(6);
+  return DVNR_OK;
+}
+
+// Copy ring rows of steps [s0, s0 + n) into out [n][nb].
+static dvnr_status copy_losses(dvnr_t* h, int64_t s0, int64_t n, float* out, hipStream_t s) {
+  int64_t done = 0;
+  while (done < n) {
+    const int64_t row = (s0 + done) % kLossRing;
+    const int64_t cnt = std::min(n - done, (int64_t)kLossRing - row);
+    HIPCHK(hipMemcpyAsync(out + done * h->nb, h->d_ring() + row * h->nb, sizeof(float) * cnt * h->nb,
+                          hipMemcpyDeviceToDevice, s));
+    done += cnt;
+  }
+  return DVNR_OK;
+}
+
+static dvnr_status train_ready(dvnr_t* h) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (!h->bound) return fail(DVNR_E_STATE, "train before dvnr_bind");
+  if (!h->prepared) return fail(DVNR_E_STATE, "train before dvnr_prepare");
+  if (h->prec == Prec::F64) return fail(DVNR_E_UNSUPPORTED, "fp64 handles provide the autograd building blocks only");
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_train_steps(dvnr_t* h, int32_t n_steps, int64_t samples_per_step, float* loss_out, void* stream) {
+  try {
+    dvnr_status st = train_ready(h);
+    if (st) return st;
+    if (n_steps < 0) return fail(DVNR_E_INVALID, "n_steps < 0");
+    if (samples_per_step < 1 || samples_per_step > h->max_batch)
+      return fail(DVNR_E_INVALID, "samples_per_step must be in [1, max_batch]");
+    if (h->nb > 1 && samples_per_step % kTile)
+      return fail(DVNR_E_INVALID, "with several blocks samples_per_step must be a multiple of 256");
+    hipStream_t s = (hipStream_t)stream;
+    if (h->plan_total != samples_per_step) {
+      st = set_plan(h, apportion(h, samples_per_step), s);
+      if (st) return st;
+      h->plan_total = samples_per_step;
+    }
+    const int64_t s0 = h->host_step;
+    int64_t done = 0;
+    while (done < n_steps) {
+      const int64_t chunk = std::min<int64_t>(n_steps - done, kLossRing);
+      const bool graph_ok = h->use_graph && !h->profile && s != nullptr;
+      if (graph_ok && (!h->graph || h->graph_stream != s || h->graph_total != samples_per_step)) {
+        if (h->graph) {
+          (void)hipGraphExecDestroy(h->graph);
+          h->graph = nullptr;
+        }
+        hipGraph_t g;
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        st = enqueue_step(h, 1, s);
+        hipError_t ce = hipStreamEndCapture(s, &g);
+        if (st) return st;
+        if (ce != hipSuccess) return fail(DVNR_E_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+        ce = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ce != hipSuccess) return fail(DVNR_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ce));
+        h->graph_stream = s;
+        h->graph_total = samples_per_step;
+      }
+      for (int64_t k = 0; k < chunk; ++k) {
+        if (graph_ok) {
+          HIPCHK(hipGraphLaunch(h->graph, s));
+        } else {
+          st = enqueue_step(h, 1, s);
+          if (st) return st;
+        }
+      }
+      h->host_step += chunk;
+      if (loss_out) {
+        st = copy_losses(h, s0 + done, chunk, loss_out + done * h->nb, s);
+        if (st) return st;
+      }
+      done += chunk;
+    }
+    return DVNR_OK;
+  } catch (...) {
+    return fail(DVNR_E_INVALID, "train failed");
+  }
+}
+
+dvnr_status dvnr_train_step_coords(dvnr_t* h, const float* coords, const int64_t* n_per_block, float* loss_out,
+                                   void* stream) {
+  try {
+    dvnr_status st = train_ready(h);
+    if (st) return st;
+    if (!coords || !n_per_block) return fail(DVNR_E_INVALID, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int64_t> n(n_per_block, n_per_block + h->nb);
+    int64_t total = 0;
+    for (auto v : n) {
+      if (v < 0) return fail(DVNR_E_INVALID, "negative sample count");
+      total += v;
+    }
+    if (total < 1 || total > h->max_batch) return fail(DVNR_E_INVALID, "total samples must be in [1, max_batch]");
+    st = set_plan(h, n, s);
+    if (st) return st;
+    h->plan_total = -1;  // the next dvnr_train_steps rebuilds its plan
+    HIPCHK(hipMemcpyAsync(h->d_coords(), coords, sizeof(float) * 3 * total, hipMemcpyDeviceToDevice, s));
+    st = enqueue_step(h, 0, s);
+    if (st) return st;
+    const int64_t s0 = h->host_step;
+    h->host_step += 1;
+    if (loss_out) return copy_losses(h, s0, 1, loss_out, s);
+    return DVNR_OK;
+  } catch (...) {
+    return fail(DVNR_E_INVALID, "train failed");
+  }
+}
+
+dvnr_status dvnr_draw_training_samples(dvnr_t* h, int32_t block, int64_t step, int64_t n, float* coords,
+                                       float* target, void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (!h->prepared) return fail(DVNR_E_STATE, "call dvnr_prepare first");
+  if (block < 0 || block >= h->nb) return fail(DVNR_E_INVALID, "bad block");
+  if (n < 0 || n >= ((int64_t)1 << 31) || step < 0 || !coords || !target) return fail(DVNR_E_INVALID, "bad arguments");
+  if (n == 0) return DVNR_OK;
+  HIPCHK(launch_sample(h->d_meta(), h->d_range(), nullptr, nullptr, (int)n, block, 1, h->seed, h->d_ctr(), step,
+                       coords, target, (hipStream_t)stream));
+  return DVNR_OK;
+}
+
+// INR output at `n` coordinates of block b (chunks of max_batch), de-normalized.
+static dvnr_status infer_coords(dvnr_t* h, int b, int64_t n, const float* coords, float* out, hipStream_t s) {
+  const bool mixed = h->prec == Prec::MIXED;
+  const int64_t F = h->enc.n_features;
+  const void* table = mixed ? h->buf.work16 : h->buf.params;
+  const void* wsrc = mixed ? (const void*)((const uint16_t*)h->buf.work16 + h->n_table)
+                           : (const void*)((const float*)h->buf.params + h->n_table);
+  for (int64_t c0 = 0; c0 < n; c0 += h->max_batch) {
+    const int64_t cn = std::min(h->max_batch, n - c0);
+    HIPCHK(launch_encode(h->prec, mixed ? 1 : 0, h->ld, h->d_meta(), nullptr, (int)cn, b, nullptr, coords + 3 * c0,
+                         table, h->d_feat(), F, h->max_batch * F, h->xcd_map, s));
+    HIPCHK(launch_mlp_infer(h->prec, h->md, h->ld, h->d_meta(), h->d_range(), nullptr, nullptr, (int)cn, b,
+                            h->d_feat(), wsrc, h->max_batch, out + c0, s));
+  }
+  return DVNR_OK;
+}
+
+static dvnr_status access_ready(dvnr_t* h, int32_t block) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (!h->prepared) return fail(DVNR_E_STATE, "call dvnr_prepare first");
+  if (h->prec == Prec::F64) return fail(DVNR_E_UNSUPPORTED, "fp64 handles provide the autograd building blocks only");
+  if (block < 0 || block >= h->nb) return fail(DVNR_E_INVALID, "bad block");
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_sample(dvnr_t* h, int32_t block, int64_t n, const float* coords, float* out, void* stream) {
+  dvnr_status st = access_ready(h, block);
+  if (st) return st;
+  if (n < 0 || (n > 0 && (!coords || !out))) return fail(DVNR_E_INVALID, "bad arguments");
+  return infer_coords(h, block, n, coords, out, (hipStream_t)stream);
+}
+
+dvnr_status dvnr_decode(dvnr_t* h, int32_t block, float* out, void* stream) {
+  if (!out) return fail(DVNR_E_INVALID, "null output");
+  const int b0 = block < 0 ? 0 : block, b1 = block < 0 ? (h ? h->nb : 0) : block + 1;
+  dvnr_status st = access_ready(h, b0);
+  if (st) return st;
+  if (block >= h->nb) return fail(DVNR_E_INVALID, "bad block");
+  hipStream_t s = (hipStream_t)stream;
+  int64_t out_off = 0;
+  for (int b = b0; b < b1; ++b) {
+    const int64_t nvox = owned_voxels(h->blocks[b]);
+    for (int64_t c0 = 0; c0 < nvox; c0 += h->max_batch) {
+      const int64_t cn = std::min(h->max_batch, nvox - c0);
+      HIPCHK(launch_voxel_coords(h->d_meta(), b, c0, cn, h->d_coords(), s));
+      st = infer_coords(h, b, cn, h->d_coords(), out + out_off + c0, s);
+      if (st) return st;
+    }
+    out_off += nvox;
+  }
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_mse_fp64(dvnr_t* h, int32_t block, const float* decoded, double* sse, int64_t* count,
+                          void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (!h->bound) return fail(DVNR_E_STATE, "dvnr_mse_fp64 before dvnr_bind");
+  if (block < 0 || block >= h->nb || !decoded || !sse) return fail(DVNR_E_INVALID, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(launch_zero(h->d_mse(), sizeof(double), s));
+  HIPCHK(launch_mse(h->d_meta(), block, decoded, h->d_mse(), s));
+  double v = 0;
+  HIPCHK(hipMemcpyAsync(&v, h->d_mse(), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *sse = v;
+  if (count) *count = owned_voxels(h->blocks[block]);
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_encode_forward(dvnr_t* h, int64_t n, const float* coords, const void* table, void* feats,
+                                void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (n < 0 || n >= ((int64_t)1 << 31) || (n > 0 && (!coords || !table || !feats))) return fail(DVNR_E_INVALID, "bad arguments");
+  const int64_t LF = h->md.in_dim;
+  const Prec tp = h->prec == Prec::F64 ? Prec::F64 : Prec::F32;
+  HIPCHK(launch_encode(tp, tp == Prec::F64 ? 2 : 0, h->ld, nullptr, nullptr, (int)n, 0, nullptr, coords, table, feats,
+                       LF, h->enc.n_features, 0, (hipStream_t)stream));
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_encode_backward(dvnr_t* h, int64_t n, const float* coords, const void* dfeats, void* dtable,
+                                 void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (n < 0 || n >= ((int64_t)1 << 31) || (n > 0 && (!coords || !dfeats || !dtable))) return fail(DVNR_E_INVALID, "bad arguments");
+  const int64_t LF = h->md.in_dim;
+  const Prec gp = h->prec == Prec::F64 ? Prec::F64 : Prec::F32;
+  HIPCHK(launch_scatter(gp, h->ld, nullptr, nullptr, (int)n, 0, nullptr, coords, dfeats, LF, h->enc.n_features, dtable,
+                        0, 0, (hipStream_t)stream));
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_mlp_forward(dvnr_t* h, int64_t n, const void* feats, const void* weights, void* out, void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (n < 0 || (n > 0 && (!feats || !weights || !out))) return fail(DVNR_E_INVALID, "bad arguments");
+  const Prec p = h->prec == Prec::F64 ? Prec::F64 : Prec::F32;
+  HIPCHK(launch_mlp_simple_fwd(p, h->md, n, feats, weights, out, (hipStream_t)stream));
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_mlp_backward(dvnr_t* h, int64_t n, const void* feats, const void* weights, const void* dout,
+                              void* dfeats, void* dweights, void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (n < 0 || (n > 0 && (!feats || !weights || !dout || !dfeats || !dweights)))
+    return fail(DVNR_E_INVALID, "bad arguments");
+  const Prec p = h->prec == Prec::F64 ? Prec::F64 : Prec::F32;
+  HIPCHK(launch_mlp_simple_bwd(p, h->md, n, feats, weights, dout, dfeats, dweights, (hipStream_t)stream));
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_debug_indices(dvnr_t* h, int32_t level, int64_t n, const float* coords, uint32_t* idx, float* w,
+                               void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (level < 0 || level >= h->enc.n_levels) return fail(DVNR_E_INVALID, "bad level");
+  if (n < 0 || (n > 0 && (!coords || !idx || !w))) return fail(DVNR_E_INVALID, "bad arguments");
+  HIPCHK(launch_debug_indices(h->ld, level, n, coords, idx, w, (hipStream_t)stream));
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_sync(dvnr_t* h, void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  if (h->bound) {
+    int32_t flag = 0;
+    HIPCHK(hipMemcpy(&flag, (char*)h->d_ctr() + offsetof(Counters, nonfinite), sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (flag) {
+      HIPCHK(hipMemset((char*)h->d_ctr() + offsetof(Counters, nonfinite), 0, sizeof(int32_t)));
+      return fail(DVNR_E_NONFINITE, "non-finite training loss");
+    }
+  }
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_phase_times(dvnr_t* h, double* ms6, int64_t* n_steps) {
+  if (!h || !ms6) return fail(DVNR_E_INVALID, "null argument");
+  while (h->prof_accumulated < h->prof_recorded) {
+    dvnr_status st = prof_accumulate_one(h, h->prof_accumulated);
+    if (st) return st;
+    h->prof_accumulated += 1;
+  }
+  for (int p = 0; p < 6; ++p) {
+    ms6[p] = h->prof_ms[p];
+    h->prof_ms[p] = 0.0;
+  }
+  if (n_steps) *n_steps = h->prof_recorded;
+  h->prof_recorded = h->prof_accumulated = 0;
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
+  if (!h || !name) return fail(DVNR_E_INVALID, "null argument");
+  const std::string n(name);
+  if (n == "scatter_grouped") {
+    h->scatter_grouped = value ? 1 : 0;
+  } else if (n == "use_graph") {
+    h->use_graph = value ? 1 : 0;
+  } else if (n == "xcd_map") {
+    h->xcd_map = value ? 1 : 0;
+  } else if (n == "apply_update") {
+    h->apply_update = value ? 1 : 0;
+  } else if (n == "profile_phases") {
+    h->profile = value ? 1 : 0;
+  } else {
+    return fail(DVNR_E_INVALID, "unknown option " + n);
+  }
+  if (h->graph) {
+    (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  return DVNR_OK;
+}
+
+}  // extern "C"

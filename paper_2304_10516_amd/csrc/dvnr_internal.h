@@ -1,0 +1,134 @@
+// Internal structures and launcher declarations of the DVNR HIP library.
+// Shared between the host-side C ABI (dvnr_host.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dvnrk {
+
+constexpr int kMaxLevels = 16;
+constexpr int kTile = 256;        // samples per tile (work item of the training kernels)
+constexpr int kMlpGrid = 512;     // workgroups of the persistent MLP kernel
+constexpr int kLossRing = 1024;   // steps of per-block loss history kept on the device
+
+// Level table, passed by value to kernels.
+struct LevelDesc {
+  int32_t L, F, log2T, in_dim;
+  uint32_t T_mask;
+  int32_t R[kMaxLevels];
+  int32_t dense[kMaxLevels];
+  int32_t off[kMaxLevels];     // entry offset of the level inside a block's table
+  float scale[kMaxLevels];     // (float)(R - 1)
+};
+
+struct MlpDesc {
+  int32_t n_hidden, width, in_dim;
+  int32_t n_mlp;               // weights per block
+  int32_t off[6];              // element offset of W_1 .. W_out relative to the block's MLP start
+};
+
+// Static per-block description (device array).
+struct BlockMeta {
+  const float* vol;            // stored voxels (nz+2g)(ny+2g)(nx+2g), x fastest
+  int32_t dims[3];
+  int32_t ghost;
+  int64_t param_off;           // element offset of the block in the parameter index space
+};
+
+struct BlockRange {
+  float vmin, vmax;            // value range over stored voxels
+  float inv_range, range;      // 1/(vmax-vmin) and vmax-vmin (1 and 1 for a constant block)
+};
+
+// Per-call sample plan (device array): samples of block b occupy
+// [sample_off, sample_off + n) in the per-step sample buffers.
+struct BlockPlan {
+  int64_t sample_off;
+  int32_t n;
+  float inv_n;                 // 1/n (0 when n == 0)
+};
+
+struct Tile {
+  int32_t block;
+  int32_t start;               // first sample index within the block
+  int32_t count;               // samples in this tile (<= kTile)
+  int32_t slot_first;          // unused by kernels; kept for alignment
+};
+
+struct Counters {
+  int64_t step;                // optimizer steps taken (Adam t = step after the update)
+  int32_t nonfinite;           // set when a non-finite loss was reduced
+  int32_t pad;
+  uint32_t minmax[2 * 1024];   // scratch for order-preserving float min/max keys (up to 1024 blocks per pass)
+};
+
+// Element types of the training buffers
+enum class Prec { F32 = 0, MIXED = 1, F64 = 2 };
+
+// ----------------------------------------------------------------------------
+// Launchers (defined in the kernel files).  All enqueue on `s`.
+// ----------------------------------------------------------------------------
+hipError_t launch_minmax(const BlockMeta* meta, BlockRange* range, Counters* ctr, int n_blocks,
+                         const int64_t* dev_voxels, hipStream_t s);
+hipError_t launch_init_params(Prec p, void* params, int n_blocks, int64_t block_stride, int64_t n_table_params,
+                              const MlpDesc& md, uint64_t seed, hipStream_t s);
+hipError_t launch_refresh16(void* params, uint16_t* work16, int n_blocks, int64_t block_stride,
+                            int64_t n_table_params, int64_t n_mlp, hipStream_t s);
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
+
+// Sampler: coordinates (generated when gen != 0, else read from `coords`)
+// and normalized trilinear targets.
+// Direct mode when tiles == nullptr: n_tiles is then the sample count of block
+// direct_block, written to coords/target [0, n).
+hipError_t launch_sample(const BlockMeta* meta, const BlockRange* range, const BlockPlan* plan, const Tile* tiles,
+                         int n_tiles, int direct_block, int gen, uint64_t seed, const Counters* ctr,
+                         int64_t step_override, float* coords, float* target, hipStream_t s);
+
+// Encoding forward.  Output element (sample i, level l, feature f) goes to
+// out[i*ss + l*ls + f].  Tables: `table` points at element 0 of the parameter
+// index space (block offsets added inside) or, when meta == nullptr, directly
+// at one block's table.
+hipError_t launch_encode(Prec tp, int out_kind, const LevelDesc& ld, const BlockMeta* meta, const Tile* tiles,
+                         int n_tiles, int direct_block, const BlockPlan* plan, const float* coords, const void* table,
+                         void* out, int64_t ss, int64_t ls, int xcd_map, hipStream_t s);
+
+// Encoding backward (scatter-add into gradient tables).
+hipError_t launch_scatter(Prec gp, const LevelDesc& ld, const BlockMeta* meta, const Tile* tiles, int n_tiles,
+                          int direct_block, const BlockPlan* plan, const float* coords, const void* dfeat, int64_t ss,
+                          int64_t ls, void* grad, int grouped, int xcd_map, hipStream_t s);
+
+// MLP training pass (forward, L2 loss, backward) on MFMA; writes dfeat
+// (level-major f32) and per-wave dW/loss partials into slots.
+hipError_t launch_mlp_train(Prec p, const MlpDesc& md, const LevelDesc& ld, const BlockMeta* meta,
+                            const BlockPlan* plan, const Tile* tiles, int n_tiles, const void* feat,
+                            const float* target, const void* weights_src, float* dfeat, int64_t plane,
+                            float* slots, int64_t slot_stride, int grid, hipStream_t s);
+// MLP inference: out[i] = INR output de-normalized with the block range.
+hipError_t launch_mlp_infer(Prec p, const MlpDesc& md, const LevelDesc& ld, const BlockMeta* meta,
+                            const BlockRange* range, const BlockPlan* plan, const Tile* tiles, int n_tiles,
+                            int direct_block, const void* feat, const void* weights_src, int64_t plane, float* out,
+                            hipStream_t s);
+
+// Sum slots into gradients and per-block losses; bump the step counter.
+hipError_t launch_reduce_slots(const float* slots, int64_t slot_stride, const int32_t* slot_ranges, int n_blocks,
+                               int64_t n_mlp, int64_t mlp_rel_off, int64_t block_stride, Prec gp, void* grad,
+                               float* loss_ring, Counters* ctr, int bump, hipStream_t s);
+
+hipError_t launch_adam(Prec p, void* params, void* grad, void* m, void* v, uint16_t* work16, int n_blocks,
+                       int64_t block_stride, int64_t n_table_params, int64_t n_used, const Counters* ctr,
+                       double lr, double b1, double b2, double eps, double wd, hipStream_t s);
+
+// Reference-style building blocks (thread per sample) for the autograd pieces.
+hipError_t launch_mlp_simple_fwd(Prec p, const MlpDesc& md, int64_t n, const void* feats, const void* w,
+                                 void* out, hipStream_t s);
+hipError_t launch_mlp_simple_bwd(Prec p, const MlpDesc& md, int64_t n, const void* feats, const void* w,
+                                 const void* dout, void* dfeats, void* dw, hipStream_t s);
+
+hipError_t launch_voxel_coords(const BlockMeta* meta, int block, int64_t first, int64_t n, float* coords,
+                               hipStream_t s);
+hipError_t launch_mse(const BlockMeta* meta, int block, const float* decoded, double* acc, hipStream_t s);
+hipError_t launch_debug_indices(const LevelDesc& ld, int level, int64_t n, const float* coords, uint32_t* idx,
+                                float* w, hipStream_t s);
+
+}  // namespace dvnrk

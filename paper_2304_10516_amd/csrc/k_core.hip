@@ -1,0 +1,674 @@
+// Sampler, hash-grid encoding forward, encoding backward (scatter-add), Adam,
+// slot reduction and small utility kernels of the DVNR hot path (gfx950).
+#include "dvnr_device.h"
+
+namespace dvnrk {
+
+// ===========================================================================
+// Element conversion helpers
+// ===========================================================================
+template <typename T> __device__ __forceinline__ float to_f(T v) { return (float)v; }
+template <> __device__ __forceinline__ float to_f<__half>(__half v) { return __half2float(v); }
+template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
+template <> __device__ __forceinline__ double to_d<__half>(__half v) { return (double)__half2float(v); }
+
+template <typename T> __device__ __forceinline__ T from_f(float v) { return (T)v; }
+template <> __device__ __forceinline__ __bf16 from_f<__bf16>(float v) { return (__bf16)v; }
+
+// Sample addressing shared by the level-major kernels: either a tile table
+// (training: tiles of one block each) or a direct range [0, n_direct) of one
+// block's samples (autograd building blocks).
+struct SampleRef {
+  int64_t gi;       // sample index in the coordinate / feature buffers
+  int block;        // block id (0 in direct mode)
+  bool valid;
+};
+
+__device__ __forceinline__ SampleRef sample_ref(const Tile* tiles, const BlockPlan* plan, int tile, int64_t n_direct,
+                                                int direct_block, int j) {
+  SampleRef r;
+  if (tiles) {
+    const Tile tl = tiles[tile];
+    r.block = tl.block;
+    r.valid = j < tl.count;
+    r.gi = plan[tl.block].sample_off + tl.start + j;
+  } else {
+    r.block = direct_block;
+    r.gi = (int64_t)tile * kTile + j;
+    r.valid = r.gi < n_direct;
+  }
+  return r;
+}
+
+// ===========================================================================
+// Sampler: uniform coordinates (Philox4x32-10, counter (i, step, block, tag),
+// key = seed) and trilinear ground truth in cell-centered convention:
+// stored-index position p = x*n - 1/2 + g, i0 = clamp(floor p, 0, N-2),
+// t = clamp(p - i0, 0, 1); target = (v - vmin) / (vmax - vmin).
+// ===========================================================================
+__device__ __forceinline__ void cell_pos(float x, int n, int g, int N, int& i0, float& t) {
+  const float p = x * (float)n - 0.5f + (float)g;
+  int i = (int)floorf(p);
+  i = max(0, min(i, N - 2));
+  i0 = i;
+  t = fminf(fmaxf(p - (float)i, 0.0f), 1.0f);
+}
+
+__global__ __launch_bounds__(256) void k_sample(const BlockMeta* __restrict__ meta,
+                                                const BlockRange* __restrict__ range,
+                                                const BlockPlan* __restrict__ plan, const Tile* __restrict__ tiles,
+                                                int64_t n_direct, int direct_block, int gen, uint64_t seed,
+                                                const Counters* __restrict__ ctr, int64_t step_override,
+                                                float* __restrict__ coords, float* __restrict__ target) {
+  Tile tl;
+  int64_t gi;
+  const int j = threadIdx.x;
+  if (tiles) {
+    tl = tiles[blockIdx.x];
+    if (j >= tl.count) return;
+    gi = plan[tl.block].sample_off + tl.start + j;
+  } else {
+    tl.block = direct_block;
+    tl.start = blockIdx.x * kTile;
+    gi = tl.start + j;
+    if (gi >= n_direct) return;
+  }
+  const int b = tl.block;
+  float x, y, z;
+  if (gen) {
+    const uint32_t step = (uint32_t)(step_override >= 0 ? step_override : ctr->step);
+    const U4 u = philox4x32_10(U4{(uint32_t)(tl.start + j), step, (uint32_t)b, kCoordTag}, (uint32_t)seed,
+                               (uint32_t)(seed >> 32));
+    x = u24(u.x);
+    y = u24(u.y);
+    z = u24(u.z);
+    coords[3 * gi + 0] = x;
+    coords[3 * gi + 1] = y;
+    coords[3 * gi + 2] = z;
+  } else {
+    x = coords[3 * gi + 0];
+    y = coords[3 * gi + 1];
+    z = coords[3 * gi + 2];
+  }
+  const BlockMeta bm = meta[b];
+  const int g = bm.ghost;
+  const int NX = bm.dims[0] + 2 * g, NY = bm.dims[1] + 2 * g, NZ = bm.dims[2] + 2 * g;
+  int ix, iy, iz;
+  float tx, ty, tz;
+  cell_pos(x, bm.dims[0], g, NX, ix, tx);
+  cell_pos(y, bm.dims[1], g, NY, iy, ty);
+  cell_pos(z, bm.dims[2], g, NZ, iz, tz);
+  const float* v = bm.vol + ((int64_t)iz * NY + iy) * NX + ix;
+  const int64_t sy = NX, sz = (int64_t)NX * NY;
+  const float c00 = v[0] + tx * (v[1] - v[0]);
+  const float c10 = v[sy] + tx * (v[sy + 1] - v[sy]);
+  const float c01 = v[sz] + tx * (v[sz + 1] - v[sz]);
+  const float c11 = v[sz + sy] + tx * (v[sz + sy + 1] - v[sz + sy]);
+  const float c0 = c00 + ty * (c10 - c00);
+  const float c1 = c01 + ty * (c11 - c01);
+  const float val = c0 + tz * (c1 - c0);
+  const BlockRange br = range[b];
+  target[gi] = (val - br.vmin) * br.inv_range;
+}
+
+hipError_t launch_sample(const BlockMeta* meta, const BlockRange* range, const BlockPlan* plan, const Tile* tiles,
+                         int n_tiles, int direct_block, int gen, uint64_t seed, const Counters* ctr,
+                         int64_t step_override, float* coords, float* target, hipStream_t s) {
+  int64_t n_direct = 0;
+  int nt = n_tiles;
+  if (!tiles) {
+    n_direct = n_tiles;
+    nt = (int)((n_direct + kTile - 1) / kTile);
+  }
+  if (nt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sample, dim3(nt), dim3(kTile), 0, s, meta, range, plan, tiles, n_direct, direct_block, gen,
+                     seed, ctr, step_override, coords, target);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Encoding forward: one thread per (sample, level); level-major workgroups.
+// y[l*F + f] = sum_c w_c * table[(off_l + idx_c) * F + f]
+// ===========================================================================
+template <typename TT, typename WT, typename OT, int F>
+__global__ __launch_bounds__(256) void k_encode(LevelDesc ld, const BlockMeta* __restrict__ meta,
+                                                const Tile* __restrict__ tiles, int n_tiles, int64_t n_direct,
+                                                int direct_block, const BlockPlan* __restrict__ plan,
+                                                const float* __restrict__ coords, const TT* __restrict__ table,
+                                                OT* __restrict__ out, int64_t ss, int64_t ls, int xcd_map) {
+  int tile, l;
+  if (!level_major_item(blockIdx.x, ld.L, n_tiles, xcd_map, tile, l)) return;
+  const SampleRef r = sample_ref(tiles, plan, tile, n_direct, direct_block, threadIdx.x);
+  if (!r.valid) return;
+  const float x = coords[3 * r.gi + 0], y = coords[3 * r.gi + 1], z = coords[3 * r.gi + 2];
+  int ix, iy, iz;
+  float tx, ty, tz;
+  const int R = ld.R[l];
+  grid_pos(x, ld.scale[l], R, ix, tx);
+  grid_pos(y, ld.scale[l], R, iy, ty);
+  grid_pos(z, ld.scale[l], R, iz, tz);
+  const TT* tab = table + (meta ? meta[r.block].param_off : 0) + (int64_t)ld.off[l] * F;
+  const int dense = ld.dense[l];
+  WT acc[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) acc[f] = 0;
+  const WT wx[2] = {(WT)1 - (WT)tx, (WT)tx};
+  const WT wy[2] = {(WT)1 - (WT)ty, (WT)ty};
+  const WT wz[2] = {(WT)1 - (WT)tz, (WT)tz};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
+    const uint32_t e = corner_index(dense, R, ld.T_mask, ix + cx, iy + cy, iz + cz);
+    const WT w = wx[cx] * wy[cy] * wz[cz];
+    const TT* p = tab + (int64_t)e * F;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      if constexpr (sizeof(WT) == 8)
+        acc[f] += w * to_d(p[f]);
+      else
+        acc[f] += w * to_f(p[f]);
+    }
+  }
+  OT* o = out + r.gi * ss + (int64_t)l * ls;
+#pragma unroll
+  for (int f = 0; f < F; ++f) o[f] = (OT)acc[f];
+}
+
+template <typename TT, typename WT, typename OT>
+static hipError_t enc_dispatch(const LevelDesc& ld, const BlockMeta* meta, const Tile* tiles, int n_tiles,
+                               int64_t n_direct, int direct_block, const BlockPlan* plan, const float* coords, const void* table,
+                               void* out, int64_t ss, int64_t ls, int xcd_map, hipStream_t s) {
+  const int grid = level_major_grid(ld.L, n_tiles, xcd_map);
+  if (grid <= 0) return hipSuccess;
+  const TT* t = (const TT*)table;
+  OT* o = (OT*)out;
+  switch (ld.F) {
+    case 1: hipLaunchKernelGGL((k_encode<TT, WT, OT, 1>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map); break;
+    case 2: hipLaunchKernelGGL((k_encode<TT, WT, OT, 2>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map); break;
+    case 4: hipLaunchKernelGGL((k_encode<TT, WT, OT, 4>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map); break;
+    case 8: hipLaunchKernelGGL((k_encode<TT, WT, OT, 8>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// out_kind: 0 = float, 1 = bf16, 2 = double.  Direct mode when tiles == nullptr
+// (then n_tiles is the sample count).
+hipError_t launch_encode(Prec tp, int out_kind, const LevelDesc& ld, const BlockMeta* meta, const Tile* tiles,
+                         int n_tiles, int direct_block, const BlockPlan* plan, const float* coords, const void* table,
+                         void* out, int64_t ss, int64_t ls, int xcd_map, hipStream_t s) {
+  int64_t n_direct = 0;
+  int nt = n_tiles;
+  if (!tiles) {
+    n_direct = n_tiles;
+    nt = (int)((n_direct + kTile - 1) / kTile);
+  }
+  if (tp == Prec::F64) return enc_dispatch<double, double, double>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, table, out, ss, ls, xcd_map, s);
+  if (tp == Prec::MIXED) {
+    if (out_kind == 1) return enc_dispatch<__half, float, __bf16>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, table, out, ss, ls, xcd_map, s);
+    return enc_dispatch<__half, float, float>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, table, out, ss, ls, xcd_map, s);
+  }
+  return enc_dispatch<float, float, float>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, table, out, ss, ls, xcd_map, s);
+}
+
+// ===========================================================================
+// Encoding backward: grad[(off_l + idx_c) * F + f] += w_c * dy[l*F + f].
+//
+// Plain variant: one thread per (sample, level) issues its 8*F atomics.
+// Grouped variant: 2F consecutive lanes own the two x-neighbour corners
+// (cx = 0, 1) of one (sample, level, cy, cz) and all F features, so one
+// atomic instruction covers 16 contiguous bytes per lane group (F = 2):
+// dense levels place the pair side by side, and the hash (x prime 1) keeps
+// it within one aligned 64-byte segment in most cases.  The atomic unit
+// serves one 64-byte segment per request, so this cuts requests ~4x.
+// ===========================================================================
+template <typename GT, typename DT, int F, bool GROUPED>
+__global__ __launch_bounds__(256) void k_scatter(LevelDesc ld, const BlockMeta* __restrict__ meta,
+                                                 const Tile* __restrict__ tiles, int n_tiles, int64_t n_direct,
+                                                 int direct_block, const BlockPlan* __restrict__ plan,
+                                                 const float* __restrict__ coords, const DT* __restrict__ dfeat,
+                                                 int64_t ss, int64_t ls, GT* __restrict__ grad, int xcd_map) {
+  int tile, l;
+  if (!level_major_item(blockIdx.x, ld.L, n_tiles, xcd_map, tile, l)) return;
+  const int R = ld.R[l];
+  const float sc = ld.scale[l];
+  const int dense = ld.dense[l];
+  if constexpr (!GROUPED) {
+    const SampleRef r = sample_ref(tiles, plan, tile, n_direct, direct_block, threadIdx.x);
+    if (!r.valid) return;
+    const float x = coords[3 * r.gi + 0], y = coords[3 * r.gi + 1], z = coords[3 * r.gi + 2];
+    int ix, iy, iz;
+    float tx, ty, tz;
+    grid_pos(x, sc, R, ix, tx);
+    grid_pos(y, sc, R, iy, ty);
+    grid_pos(z, sc, R, iz, tz);
+    using WT = typename std::conditional<sizeof(GT) == 8, double, float>::type;
+    const WT wx[2] = {(WT)1 - (WT)tx, (WT)tx};
+    const WT wy[2] = {(WT)1 - (WT)ty, (WT)ty};
+    const WT wz[2] = {(WT)1 - (WT)tz, (WT)tz};
+    const DT* d = dfeat + r.gi * ss + (int64_t)l * ls;
+    WT dv[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) dv[f] = (WT)d[f];
+    GT* g = grad + (meta ? meta[r.block].param_off : 0) + (int64_t)ld.off[l] * F;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
+      const uint32_t e = corner_index(dense, R, ld.T_mask, ix + cx, iy + cy, iz + cz);
+      const WT w = wx[cx] * wy[cy] * wz[cz];
+#pragma unroll
+      for (int f = 0; f < F; ++f) unsafeAtomicAdd(&g[(int64_t)e * F + f], (GT)(w * dv[f]));
+    }
+  } else {
+    constexpr int G = 2 * F;               // lanes per (sample, cy, cz) item
+    const int q = threadIdx.x % G;         // lane within the group
+    const int cx = q / F, f = q % F;
+    int count;
+    int64_t base;
+    int block;
+    if (tiles) {
+      const Tile tl = tiles[tile];
+      count = tl.count;
+      block = tl.block;
+      base = plan[tl.block].sample_off + tl.start;
+    } else {
+      base = (int64_t)tile * kTile;
+      count = (int)min((int64_t)kTile, n_direct - base);
+      block = direct_block;
+    }
+    GT* g = grad + (meta ? meta[block].param_off : 0) + (int64_t)ld.off[l] * F;
+    const int items = count * 4;
+    for (int it = threadIdx.x / G; it < items; it += kTile / G) {
+      const int j = it >> 2, yz = it & 3;
+      const int64_t gi = base + j;
+      const float x = coords[3 * gi + 0], y = coords[3 * gi + 1], z = coords[3 * gi + 2];
+      int ix, iy, iz;
+      float tx, ty, tz;
+      grid_pos(x, sc, R, ix, tx);
+      grid_pos(y, sc, R, iy, ty);
+      grid_pos(z, sc, R, iz, tz);
+      const uint32_t cy = yz & 1, cz = yz >> 1;
+      const uint32_t e = corner_index(dense, R, ld.T_mask, ix + cx, iy + cy, iz + cz);
+      const float w = (cx ? tx : 1.0f - tx) * (cy ? ty : 1.0f - ty) * (cz ? tz : 1.0f - tz);
+      const float dv = (float)dfeat[gi * ss + (int64_t)l * ls + f];
+      unsafeAtomicAdd(&g[(int64_t)e * F + f], (GT)(w * dv));
+    }
+  }
+}
+
+template <typename GT, typename DT, bool GROUPED>
+static hipError_t scat_dispatch(const LevelDesc& ld, const BlockMeta* meta, const Tile* tiles, int nt,
+                                int64_t n_direct, int direct_block, const BlockPlan* plan, const float* coords, const void* dfeat,
+                                int64_t ss, int64_t ls, void* grad, int xcd_map, hipStream_t s) {
+  const int grid = level_major_grid(ld.L, nt, xcd_map);
+  if (grid <= 0) return hipSuccess;
+  const DT* d = (const DT*)dfeat;
+  GT* g = (GT*)grad;
+  switch (ld.F) {
+    case 1: hipLaunchKernelGGL((k_scatter<GT, DT, 1, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map); break;
+    case 2: hipLaunchKernelGGL((k_scatter<GT, DT, 2, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map); break;
+    case 4: hipLaunchKernelGGL((k_scatter<GT, DT, 4, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map); break;
+    case 8: hipLaunchKernelGGL((k_scatter<GT, DT, 8, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(Prec gp, const LevelDesc& ld, const BlockMeta* meta, const Tile* tiles, int n_tiles,
+                          int direct_block, const BlockPlan* plan, const float* coords, const void* dfeat, int64_t ss,
+                          int64_t ls, void* grad, int grouped, int xcd_map, hipStream_t s) {
+  int64_t n_direct = 0;
+  int nt = n_tiles;
+  if (!tiles) {
+    n_direct = n_tiles;
+    nt = (int)((n_direct + kTile - 1) / kTile);
+  }
+  if (gp == Prec::F64)
+    return scat_dispatch<double, double, false>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, s);
+  if (grouped)
+    return scat_dispatch<float, float, true>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, s);
+  return scat_dispatch<float, float, false>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, s);
+}
+
+// ===========================================================================
+// Slot reduction: per block, sum the dW / loss partials written by the
+// workgroups (4 waves each) that processed the block's tiles.  Slots of block
+// b are [slot_ranges[2b], slot_ranges[2b+1]).  Writes the MLP gradient
+// (overwrite) and the block's mean loss into the loss ring.
+// ===========================================================================
+template <typename GT>
+__global__ __launch_bounds__(256) void k_reduce_slots(const float* __restrict__ slots, int64_t slot_stride,
+                                                      const int32_t* __restrict__ ranges, int64_t n_mlp,
+                                                      int64_t mlp_rel_off, int64_t block_stride,
+                                                      GT* __restrict__ grad, float* __restrict__ loss_ring,
+                                                      Counters* __restrict__ ctr, int n_blocks) {
+  const int b = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e > n_mlp) return;
+  const int s0 = ranges[2 * b], s1 = ranges[2 * b + 1];
+  float acc = 0.0f;
+  for (int sl = s0; sl < s1; ++sl) acc += slots[(int64_t)sl * slot_stride + e];
+  if (e < n_mlp) {
+    grad[(int64_t)b * block_stride + mlp_rel_off + e] = (GT)acc;
+  } else {
+    const int64_t step = ctr->step;
+    loss_ring[(step % kLossRing) * n_blocks + b] = acc;
+    if (!isfinite(acc)) ctr->nonfinite = 1;
+  }
+}
+
+__global__ void k_bump(Counters* ctr) { ctr->step += 1; }
+
+hipError_t launch_reduce_slots(const float* slots, int64_t slot_stride, const int32_t* slot_ranges, int n_blocks,
+                               int64_t n_mlp, int64_t mlp_rel_off, int64_t block_stride, Prec gp, void* grad,
+                               float* loss_ring, Counters* ctr, int bump, hipStream_t s) {
+  dim3 grid((unsigned)((n_mlp + 1 + 255) / 256), (unsigned)n_blocks);
+  if (gp == Prec::F64)
+    hipLaunchKernelGGL(k_reduce_slots<double>, grid, dim3(256), 0, s, slots, slot_stride, slot_ranges, n_mlp,
+                       mlp_rel_off, block_stride, (double*)grad, loss_ring, ctr, n_blocks);
+  else
+    hipLaunchKernelGGL(k_reduce_slots<float>, grid, dim3(256), 0, s, slots, slot_stride, slot_ranges, n_mlp,
+                       mlp_rel_off, block_stride, (float*)grad, loss_ring, ctr, n_blocks);
+  if (bump) hipLaunchKernelGGL(k_bump, dim3(1), dim3(1), 0, s, ctr);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Adam with L2 weight decay (every parameter, every step):
+//   g += wd*theta; m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+//   theta -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps); g = 0.
+// Mixed precision also refreshes the 16-bit working copy (fp16 tables, bf16
+// weights, round to nearest even).  4 elements per thread (block_stride is
+// a multiple of 64, so a group of 4 never straddles two blocks).
+// ===========================================================================
+template <typename P>
+__global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restrict__ grad, P* __restrict__ mom,
+                                              P* __restrict__ vel, uint16_t* __restrict__ work16,
+                                              int64_t n_total, int64_t block_stride, int64_t n_table,
+                                              int64_t n_used, const Counters* __restrict__ ctr, P lr, P b1,
+                                              P b2, P eps, P wd) {
+  const double t = (double)ctr->step;
+  const P bc1 = (P)(1.0 / (1.0 - pow((double)b1, t)));
+  const P bc2 = (P)(1.0 / (1.0 - pow((double)b2, t)));
+  const int64_t n4 = n_total / 4;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n4; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i0 = 4 * q;
+    const int64_t j0 = i0 % block_stride;
+    if (j0 >= n_used) continue;
+    P th[4], g[4], m[4], v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      th[k] = params[i0 + k];
+      g[k] = grad[i0 + k];
+      m[k] = mom[i0 + k];
+      v[k] = vel[i0 + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (j0 + k >= n_used) {
+        g[k] = 0;
+        continue;
+      }
+      const P gg = g[k] + wd * th[k];
+      m[k] = b1 * m[k] + (P(1) - b1) * gg;
+      v[k] = b2 * v[k] + (P(1) - b2) * gg * gg;
+      th[k] = th[k] - lr * (m[k] * bc1) / (sqrt(v[k] * bc2) + eps);
+      g[k] = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      params[i0 + k] = th[k];
+      grad[i0 + k] = g[k];
+      mom[i0 + k] = m[k];
+      vel[i0 + k] = v[k];
+    }
+    if (work16) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float f = (float)th[k];
+        uint16_t bits;
+        if (j0 + k < n_table) {
+          const __half h = __float2half_rn(f);
+          bits = *reinterpret_cast<const uint16_t*>(&h);
+        } else {
+          const __bf16 h = (__bf16)f;
+          bits = *reinterpret_cast<const uint16_t*>(&h);
+        }
+        work16[i0 + k] = bits;
+      }
+    }
+  }
+}
+
+hipError_t launch_adam(Prec p, void* params, void* grad, void* m, void* v, uint16_t* work16, int n_blocks,
+                       int64_t block_stride, int64_t n_table_params, int64_t n_used, const Counters* ctr,
+                       double lr, double b1, double b2, double eps, double wd, hipStream_t s) {
+  const int64_t n_total = (int64_t)n_blocks * block_stride;
+  const int64_t n4 = n_total / 4;
+  const int grid = (int)std::min<int64_t>((n4 + 255) / 256, 256 * 32);
+  if (p == Prec::F64)
+    hipLaunchKernelGGL(k_adam<double>, dim3(grid), dim3(256), 0, s, (double*)params, (double*)grad, (double*)m,
+                       (double*)v, nullptr, n_total, block_stride, n_table_params, n_used, ctr, lr, b1, b2, eps, wd);
+  else
+    hipLaunchKernelGGL(k_adam<float>, dim3(grid), dim3(256), 0, s, (float*)params, (float*)grad, (float*)m,
+                       (float*)v, work16, n_total, block_stride, n_table_params, n_used, ctr, (float)lr, (float)b1,
+                       (float)b2, (float)eps, (float)wd);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Utilities
+// ===========================================================================
+__device__ __forceinline__ uint32_t order_key(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float key_float(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+__global__ void k_minmax_init(Counters* ctr, int n_blocks) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n_blocks) {
+    ctr->minmax[2 * b] = 0xffffffffu;
+    ctr->minmax[2 * b + 1] = 0u;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_minmax(const BlockMeta* __restrict__ meta, Counters* __restrict__ ctr,
+                                                const int64_t* __restrict__ nvox) {
+  const int b = blockIdx.y;
+  const float* v = meta[b].vol;
+  const int64_t n = nvox[b];
+  uint32_t lo = 0xffffffffu, hi = 0u;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = order_key(v[i]);
+    lo = min(lo, k);
+    hi = max(hi, k);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&ctr->minmax[2 * b], lo);
+    atomicMax(&ctr->minmax[2 * b + 1], hi);
+  }
+}
+
+__global__ void k_minmax_final(const Counters* ctr, BlockRange* range, int n_blocks) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_blocks) return;
+  const float lo = key_float(ctr->minmax[2 * b]), hi = key_float(ctr->minmax[2 * b + 1]);
+  BlockRange r;
+  r.vmin = lo;
+  r.vmax = hi;
+  r.range = hi > lo ? hi - lo : 1.0f;
+  r.inv_range = hi > lo ? 1.0f / (hi - lo) : 1.0f;
+  range[b] = r;
+}
+
+hipError_t launch_minmax(const BlockMeta* meta, BlockRange* range, Counters* ctr, int n_blocks,
+                         const int64_t* dev_voxels, hipStream_t s) {
+  hipLaunchKernelGGL(k_minmax_init, dim3((n_blocks + 255) / 256), dim3(256), 0, s, ctr, n_blocks);
+  hipLaunchKernelGGL(k_minmax, dim3(64, n_blocks), dim3(256), 0, s, meta, ctr, dev_voxels);
+  hipLaunchKernelGGL(k_minmax_final, dim3((n_blocks + 255) / 256), dim3(256), 0, s, ctr, range, n_blocks);
+  return hipGetLastError();
+}
+
+// Tables U(-1e-4, 1e-4), weight matrices Glorot-uniform U(-a, a) with
+// a = sqrt(6 / (fan_in + fan_out)); Philox4x32-10 counter (j, block, 'INIT', 0).
+template <typename P>
+__global__ __launch_bounds__(256) void k_init(P* __restrict__ params, int64_t n_total, int64_t block_stride,
+                                              int64_t n_table, MlpDesc md, uint64_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / block_stride, j = i % block_stride;
+    float a = 0.0f;
+    if (j < n_table) {
+      a = 1e-4f;
+    } else if (j < n_table + md.n_mlp) {
+      const int64_t k = j - n_table;
+      const int nl = md.n_hidden + 1;
+      for (int q = 0; q < nl; ++q) {
+        if (k >= md.off[q] && k < md.off[q + 1]) {
+          const int fan_in = (q == 0) ? md.in_dim : md.width;
+          const int fan_out = (q == nl - 1) ? 1 : md.width;
+          a = sqrtf(6.0f / (float)(fan_in + fan_out));
+        }
+      }
+    }
+    const U4 u = philox4x32_10(U4{(uint32_t)j, (uint32_t)b, kInitTag, 0u}, (uint32_t)seed, (uint32_t)(seed >> 32));
+    params[i] = (P)((2.0f * u24(u.x) - 1.0f) * a);
+  }
+}
+
+hipError_t launch_init_params(Prec p, void* params, int n_blocks, int64_t block_stride, int64_t n_table_params,
+                              const MlpDesc& md, uint64_t seed, hipStream_t s) {
+  const int64_t n = (int64_t)n_blocks * block_stride;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  if (p == Prec::F64)
+    hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(256), 0, s, (double*)params, n, block_stride,
+                       n_table_params, md, seed);
+  else
+    hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(256), 0, s, (float*)params, n, block_stride,
+                       n_table_params, md, seed);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_refresh16(const float* __restrict__ params, uint16_t* __restrict__ w16,
+                                                   int64_t n_total, int64_t block_stride, int64_t n_table) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = i % block_stride;
+    const float f = params[i];
+    uint16_t bits;
+    if (j < n_table) {
+      const __half h = __float2half_rn(f);
+      bits = *reinterpret_cast<const uint16_t*>(&h);
+    } else {
+      const __bf16 h = (__bf16)f;
+      bits = *reinterpret_cast<const uint16_t*>(&h);
+    }
+    w16[i] = bits;
+  }
+}
+
+hipError_t launch_refresh16(void* params, uint16_t* work16, int n_blocks, int64_t block_stride,
+                            int64_t n_table_params, int64_t n_mlp, hipStream_t s) {
+  (void)n_mlp;
+  const int64_t n = (int64_t)n_blocks * block_stride;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_refresh16, dim3(grid), dim3(256), 0, s, (const float*)params, work16, n, block_stride,
+                     n_table_params);
+  return hipGetLastError();
+}
+
+// Zero fill with a kernel (graph-safe, unlike a memset node).
+__global__ __launch_bounds__(256) void k_zero(uint32_t* __restrict__ p, int64_t n_words) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s) {
+  const int64_t n = bytes / 4;
+  if (n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, (uint32_t*)p, n);
+  return hipGetLastError();
+}
+
+// Voxel-center coordinates x = (i + 1/2) / n of owned voxels [first, first + n) of a block.
+__global__ __launch_bounds__(256) void k_voxel_coords(const BlockMeta* __restrict__ meta, int block, int64_t first,
+                                                      int64_t n, float* __restrict__ coords) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const BlockMeta bm = meta[block];
+  const int64_t v = first + i;
+  const int64_t nx = bm.dims[0], ny = bm.dims[1];
+  const int64_t ix = v % nx, iy = (v / nx) % ny, iz = v / (nx * ny);
+  coords[3 * i + 0] = __fdiv_rn((float)ix + 0.5f, (float)bm.dims[0]);
+  coords[3 * i + 1] = __fdiv_rn((float)iy + 0.5f, (float)bm.dims[1]);
+  coords[3 * i + 2] = __fdiv_rn((float)iz + 0.5f, (float)bm.dims[2]);
+}
+
+hipError_t launch_voxel_coords(const BlockMeta* meta, int block, int64_t first, int64_t n, float* coords,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_voxel_coords, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, meta, block, first, n,
+                     coords);
+  return hipGetLastError();
+}
+
+// Sum of squared differences (fp64) between a decoded block [nz][ny][nx] and
+// its owned stored voxels.
+__global__ __launch_bounds__(256) void k_mse(const BlockMeta* __restrict__ meta, int block,
+                                             const float* __restrict__ dec, double* __restrict__ acc) {
+  const BlockMeta bm = meta[block];
+  const int64_t nx = bm.dims[0], ny = bm.dims[1], nz = bm.dims[2];
+  const int g = bm.ghost;
+  const int64_t NX = nx + 2 * g, NY = ny + 2 * g;
+  const int64_t n = nx * ny * nz;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ix = i % nx, iy = (i / nx) % ny, iz = i / (nx * ny);
+    const double d = (double)dec[i] - (double)bm.vol[((iz + g) * NY + (iy + g)) * NX + (ix + g)];
+    s += d * d;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) unsafeAtomicAdd(acc, red[0] + red[1] + red[2] + red[3]);
+}
+
+hipError_t launch_mse(const BlockMeta* meta, int block, const float* decoded, double* acc, hipStream_t s) {
+  hipLaunchKernelGGL(k_mse, dim3(1024), dim3(256), 0, s, meta, block, decoded, acc);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_debug_indices(LevelDesc ld, int l, int64_t n,
+                                                       const float* __restrict__ coords, uint32_t* __restrict__ idx,
+                                                       float* __restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Corners c;
+  level_corners(ld, l, coords[3 * i], coords[3 * i + 1], coords[3 * i + 2], c);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    idx[8 * i + k] = c.idx[k];
+    w[8 * i + k] = c.w[k];
+  }
+}
+
+hipError_t launch_debug_indices(const LevelDesc& ld, int level, int64_t n, const float* coords, uint32_t* idx,
+                                float* w, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_debug_indices, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ld, level, n, coords,
+                     idx, w);
+  return hipGetLastError();
+}
+
+}  // namespace dvnrk
