@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="mixed,fp32")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB elementwise copy kernel (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the DVNR hot path trains independent per-block models with no "
@@ -155,6 +157,13 @@ def main():
     log("[bench] generating the 256^3 k^-5/3 field")
     vol = kolmogorov_field(N, seed=2)
     vol_dev = torch.tensor(vol, device="cuda")
+    if args.calibrate_copy:
+        a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)  # reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        del a, b
     results = {}
     for prec in args.precisions.split(","):
         results[prec] = run_precision(torch, DVNR, cfg, vol_dev, prec, args.steps, args.warmup)

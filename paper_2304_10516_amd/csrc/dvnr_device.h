@@ -102,16 +102,20 @@ __device__ __forceinline__ uint32_t xcc_id() {
 // workgroup w on XCD w % 8) work on levels l with l % 8 == x, so that each
 // XCD's L2 holds only its own levels' tables.  Any mapping is correct; this
 // one only improves locality.  Returns false for idle workgroups.
-__device__ __forceinline__ bool level_major_item(int wg, int L, int n_tiles, int xcd_map, int& tile, int& level) {
+// Levels handled by one launch are [l0, l0 + L).
+__device__ __forceinline__ bool level_major_item(int wg, int l0, int L, int n_tiles, int xcd_map, int& tile,
+                                                 int& level) {
   if (xcd_map && L >= 8) {
     const int lp = (L + 7) / 8;
     const int x = wg & 7, r = wg >> 3;
     const int slot = r % lp;
     tile = r / lp;
     level = x + 8 * slot;
-    return level < L && tile < n_tiles;
+    const bool ok = level < L && tile < n_tiles;
+    level += l0;
+    return ok;
   }
-  level = wg % L;
+  level = l0 + wg % L;
   tile = wg / L;
   return tile < n_tiles;
 }

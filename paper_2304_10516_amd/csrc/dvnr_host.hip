@@ -67,6 +67,13 @@ struct dvnr {
   int use_graph = 1;
   int xcd_map = 1;
   int apply_update = 1;
+  // spatially ordered sampling and bin-privatized scatter of the coarse levels
+  int spatial_sort = 0;
+  int priv_levels = -1;  // -1: chosen per plan
+  int sort_B = 0, priv_L = 0, n_groups = 0;
+  std::vector<Tile> hgroups;
+  std::vector<int32_t> hgrange;
+  int64_t o_groups = 0, o_grange = 0, o_counts = 0, o_binstart = 0, max_groups = 0;
   // per-phase event timing (eager steps only): ring of kProfRing steps x 7 events
   static constexpr int kProfRing = 128;
   int profile = 0;
@@ -93,6 +100,10 @@ struct dvnr {
   float* d_slots() const { return (float*)(ws() + o_slots); }
   float* d_ring() const { return (float*)(ws() + o_ring); }
   double* d_mse() const { return (double*)(ws() + o_mse); }
+  Tile* d_groups() const { return (Tile*)(ws() + o_groups); }
+  int32_t* d_grange() const { return (int32_t*)(ws() + o_grange); }
+  uint32_t* d_counts() const { return (uint32_t*)(ws() + o_counts); }
+  int32_t* d_binstart() const { return (int32_t*)(ws() + o_binstart); }
   size_t pelem() const { return prec == Prec::F64 ? 8 : 4; }
 
   ~dvnr() {
@@ -253,6 +264,12 @@ dvnr_status dvnr_create(const dvnr_encoding* enc, const dvnr_mlp* mlp, const dvn
     h->o_slots = take(sizeof(float) * h->n_slots * h->slot_stride);
     h->o_ring = take(sizeof(float) * kLossRing * n_blocks);
     h->o_mse = take(sizeof(double) * 8);
+    h->max_groups = max_batch / kSortGroup + n_blocks + 1;
+    h->o_groups = take(sizeof(Tile) * h->max_groups);
+    h->o_grange = take(sizeof(int32_t) * 2 * n_blocks);
+    h->o_counts = take(sizeof(uint32_t) * kMaxBins * h->max_groups);
+    h->o_binstart = take(sizeof(int32_t) * (kMaxBins + 1) * n_blocks);
+    h->spatial_sort = (h->prec == Prec::MIXED) ? 1 : 0;
     h->ws_bytes = o;
     *out = h;
     return DVNR_OK;
@@ -452,17 +469,47 @@ static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_
     while (w + 1 < G && ((int64_t)(w + 1) * T) / G <= t) ++w;
     return w;
   };
+  // the MLP kernel's workgroup w writes block b's partials into slot w + b
   h->hranges.assign(2 * h->nb, 0);
   for (int b = 0; b < h->nb; ++b) {
     if (first_tile[b] < 0) continue;
     const int w0 = wg_of_tile(first_tile[b]), w1 = wg_of_tile(last_tile[b]);
-    h->hranges[2 * b] = (w0 + b) * 4;
-    h->hranges[2 * b + 1] = (w1 + b + 1) * 4;
+    h->hranges[2 * b] = w0 + b;
+    h->hranges[2 * b + 1] = w1 + b + 1;
   }
+  // ordered sampling: counting-sort groups, bins per axis and privatized levels
+  h->hgroups.clear();
+  h->hgrange.assign(2 * h->nb, 0);
+  int64_t min_n = INT64_MAX;
+  for (int b = 0; b < h->nb; ++b) {
+    h->hgrange[2 * b] = (int32_t)h->hgroups.size();
+    for (int64_t st = 0; st < n[b]; st += kSortGroup)
+      h->hgroups.push_back(Tile{b, (int32_t)st, (int32_t)std::min<int64_t>(kSortGroup, n[b] - st), 0});
+    h->hgrange[2 * b + 1] = (int32_t)h->hgroups.size();
+    if (n[b] > 0) min_n = std::min(min_n, n[b]);
+  }
+  h->n_groups = (int)h->hgroups.size();
+  if (h->n_groups > h->max_groups) return fail(DVNR_E_INVALID, "too many sort groups");
+  // about 512 samples per bin
+  int B = 1;
+  while (B < 8 && (int64_t)(B + 1) * (B + 1) * (B + 1) * 512 <= min_n) ++B;
+  h->sort_B = B;
+  const double per_bin = (double)min_n / (double)(B * B * B);
+  int pl = 0;
+  for (int l = 0; l < h->enc.n_levels; ++l) {
+    const double side = (double)(h->ld.R[l] - 1) / (double)B + 2.0;  // vertices per axis of a bin's box
+    const double box = side * side * side;
+    if (box * h->enc.n_features > 0.75 * 16384 || box > 2.0 * 8.0 * per_bin) break;
+    pl = l + 1;
+  }
+  h->priv_L = h->priv_levels >= 0 ? std::min(h->priv_levels, h->enc.n_levels) : pl;
   HIPCHK(hipMemcpyAsync(h->d_plan(), h->hplan.data(), sizeof(BlockPlan) * h->nb, hipMemcpyHostToDevice, s));
   if (h->n_tiles)
     HIPCHK(hipMemcpyAsync(h->d_tiles(), h->htiles.data(), sizeof(Tile) * h->n_tiles, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(h->d_ranges(), h->hranges.data(), sizeof(int32_t) * 2 * h->nb, hipMemcpyHostToDevice, s));
+  if (h->n_groups)
+    HIPCHK(hipMemcpyAsync(h->d_groups(), h->hgroups.data(), sizeof(Tile) * h->n_groups, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->d_grange(), h->hgrange.data(), sizeof(int32_t) * 2 * h->nb, hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   if (h->graph) {
     (void)hipGraphExecDestroy(h->graph);
@@ -512,9 +559,16 @@ static dvnr_status prof_mark(dvnr_t* h, int p, hipStream_t s) {
 static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   const bool mixed = h->prec == Prec::MIXED;
   const int64_t F = h->enc.n_features;
+  const bool sorted = gen && h->spatial_sort && h->n_groups > 0;
   PROF(0);
-  HIPCHK(launch_sample(h->d_meta(), h->d_range(), h->d_plan(), h->d_tiles(), h->n_tiles, 0, gen, h->seed, h->d_ctr(),
-                       -1, h->d_coords(), h->d_target(), s));
+  if (sorted) {
+    HIPCHK(launch_sorted_sample(h->d_groups(), h->n_groups, h->d_grange(), h->nb, h->sort_B, h->seed, h->d_ctr(),
+                                h->d_counts(), h->d_binstart(), h->d_meta(), h->d_range(), h->d_plan(), h->d_coords(),
+                                h->d_target(), s));
+  } else {
+    HIPCHK(launch_sample(h->d_meta(), h->d_range(), h->d_plan(), h->d_tiles(), h->n_tiles, 0, gen, h->seed,
+                         h->d_ctr(), -1, h->d_coords(), h->d_target(), s));
+  }
   PROF(1);
   const void* table = mixed ? h->buf.work16 : h->buf.params;
   HIPCHK(launch_encode(h->prec, mixed ? 1 : 0, h->ld, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
@@ -526,8 +580,13 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
                           h->d_target(), wsrc, h->d_dfeat(), h->max_batch, h->d_slots(), h->slot_stride, h->mlp_grid,
                           s));
   PROF(3);
-  HIPCHK(launch_scatter(Prec::F32, h->ld, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(), h->d_coords(),
-                        h->d_dfeat(), F, h->max_batch * F, h->buf.grads, h->scatter_grouped, h->xcd_map, s));
+  const int lp = sorted ? h->priv_L : 0;
+  if (lp > 0)
+    HIPCHK(launch_scatter_priv(h->ld, 0, lp, h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(),
+                               h->d_coords(), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, s));
+  HIPCHK(launch_scatter(Prec::F32, h->ld, lp, h->enc.n_levels, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
+                        h->d_coords(), h->d_dfeat(), F, h->max_batch * F, h->buf.grads, h->scatter_grouped,
+                        h->xcd_map, s));
   PROF(4);
   HIPCHK(launch_reduce_slots(h->d_slots(), h->slot_stride, h->d_ranges(), h->nb, h->n_mlp, h->n_table, h->stride,
                              Prec::F32, h->buf.grads, h->d_ring(), h->d_ctr(), 1, s));
@@ -749,7 +808,8 @@ dvnr_status dvnr_encode_backward(dvnr_t* h, int64_t n, const float* coords, cons
   if (n < 0 || n >= ((int64_t)1 << 31) || (n > 0 && (!coords || !dfeats || !dtable))) return fail(DVNR_E_INVALID, "bad arguments");
   const int64_t LF = h->md.in_dim;
   const Prec gp = h->prec == Prec::F64 ? Prec::F64 : Prec::F32;
-  HIPCHK(launch_scatter(gp, h->ld, nullptr, nullptr, (int)n, 0, nullptr, coords, dfeats, LF, h->enc.n_features, dtable,
+  HIPCHK(launch_scatter(gp, h->ld, 0, h->enc.n_levels, nullptr, nullptr, (int)n, 0, nullptr, coords, dfeats, LF,
+                        h->enc.n_features, dtable,
                         0, 0, (hipStream_t)stream));
   return DVNR_OK;
 }
@@ -824,6 +884,11 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
     h->xcd_map = value ? 1 : 0;
   } else if (n == "apply_update") {
     h->apply_update = value ? 1 : 0;
+  } else if (n == "spatial_sort") {
+    h->spatial_sort = value ? 1 : 0;
+  } else if (n == "priv_levels") {
+    h->priv_levels = (int)std::max<int64_t>(-1, std::min<int64_t>(value, kMaxLevels));
+    h->plan_total = -1;  // recompute the plan's privatized level count
   } else if (n == "profile_phases") {
     h->profile = value ? 1 : 0;
   } else {

@@ -11,6 +11,8 @@ constexpr int kMaxLevels = 16;
 constexpr int kTile = 256;        // samples per tile (work item of the training kernels)
 constexpr int kMlpGrid = 512;     // workgroups of the persistent MLP kernel
 constexpr int kLossRing = 1024;   // steps of per-block loss history kept on the device
+constexpr int kMaxBins = 512;     // spatial bins per block (B^3, B <= 8) of the ordered sampler
+constexpr int kSortGroup = 4096;  // samples per counting-sort group
 
 // Level table, passed by value to kernels.
 struct LevelDesc {
@@ -93,10 +95,22 @@ hipError_t launch_encode(Prec tp, int out_kind, const LevelDesc& ld, const Block
                          int n_tiles, int direct_block, const BlockPlan* plan, const float* coords, const void* table,
                          void* out, int64_t ss, int64_t ls, int xcd_map, hipStream_t s);
 
-// Encoding backward (scatter-add into gradient tables).
-hipError_t launch_scatter(Prec gp, const LevelDesc& ld, const BlockMeta* meta, const Tile* tiles, int n_tiles,
-                          int direct_block, const BlockPlan* plan, const float* coords, const void* dfeat, int64_t ss,
-                          int64_t ls, void* grad, int grouped, int xcd_map, hipStream_t s);
+// Encoding backward (scatter-add into gradient tables) of levels [l0, l1).
+hipError_t launch_scatter(Prec gp, const LevelDesc& ld, int l0, int l1, const BlockMeta* meta, const Tile* tiles,
+                          int n_tiles, int direct_block, const BlockPlan* plan, const float* coords, const void* dfeat,
+                          int64_t ss, int64_t ls, void* grad, int grouped, int xcd_map, hipStream_t s);
+
+// Spatially ordered sampler: Philox draws of every group (<= kSortGroup
+// samples of one block) stored grouped by B^3 spatial bins; bin_start
+// [n_blocks][kMaxBins + 1] receives each bin's first sample (within the block).
+hipError_t launch_sorted_sample(const Tile* groups, int n_groups, const int32_t* group_range, int n_blocks, int B,
+                                uint64_t seed, const Counters* ctr, uint32_t* counts, int32_t* bin_start,
+                                const BlockMeta* meta, const BlockRange* range, const BlockPlan* plan, float* coords,
+                                float* target, hipStream_t s);
+// Bin-privatized encoding backward of levels [l0, l1) (needs the ordered sampler).
+hipError_t launch_scatter_priv(const LevelDesc& ld, int l0, int l1, int B, int n_blocks, const BlockMeta* meta,
+                               const BlockPlan* plan, const int32_t* bin_start, const float* coords,
+                               const float* dfeat, int64_t ls, float* grad, hipStream_t s);
 
 // MLP training pass (forward, L2 loss, backward) on MFMA; writes dfeat
 // (level-major f32) and per-wave dW/loss partials into slots.

@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void k_encode(LevelDesc ld, const BlockMeta* _
                                                 const float* __restrict__ coords, const TT* __restrict__ table,
                                                 OT* __restrict__ out, int64_t ss, int64_t ls, int xcd_map) {
   int tile, l;
-  if (!level_major_item(blockIdx.x, ld.L, n_tiles, xcd_map, tile, l)) return;
+  if (!level_major_item(blockIdx.x, 0, ld.L, n_tiles, xcd_map, tile, l)) return;
   const SampleRef r = sample_ref(tiles, plan, tile, n_direct, direct_block, threadIdx.x);
   if (!r.valid) return;
   const float x = coords[3 * r.gi + 0], y = coords[3 * r.gi + 1], z = coords[3 * r.gi + 2];
@@ -227,9 +227,10 @@ __global__ __launch_bounds__(256) void k_scatter(LevelDesc ld, const BlockMeta* 
                                                  const Tile* __restrict__ tiles, int n_tiles, int64_t n_direct,
                                                  int direct_block, const BlockPlan* __restrict__ plan,
                                                  const float* __restrict__ coords, const DT* __restrict__ dfeat,
-                                                 int64_t ss, int64_t ls, GT* __restrict__ grad, int xcd_map) {
+                                                 int64_t ss, int64_t ls, GT* __restrict__ grad, int xcd_map,
+                                                 int l0, int nl) {
   int tile, l;
-  if (!level_major_item(blockIdx.x, ld.L, n_tiles, xcd_map, tile, l)) return;
+  if (!level_major_item(blockIdx.x, l0, nl, n_tiles, xcd_map, tile, l)) return;
   const int R = ld.R[l];
   const float sc = ld.scale[l];
   const int dense = ld.dense[l];
@@ -297,37 +298,38 @@ __global__ __launch_bounds__(256) void k_scatter(LevelDesc ld, const BlockMeta* 
 }
 
 template <typename GT, typename DT, bool GROUPED>
-static hipError_t scat_dispatch(const LevelDesc& ld, const BlockMeta* meta, const Tile* tiles, int nt,
-                                int64_t n_direct, int direct_block, const BlockPlan* plan, const float* coords, const void* dfeat,
-                                int64_t ss, int64_t ls, void* grad, int xcd_map, hipStream_t s) {
-  const int grid = level_major_grid(ld.L, nt, xcd_map);
-  if (grid <= 0) return hipSuccess;
+static hipError_t scat_dispatch(const LevelDesc& ld, int l0, int nl, const BlockMeta* meta, const Tile* tiles, int nt,
+                                int64_t n_direct, int direct_block, const BlockPlan* plan, const float* coords,
+                                const void* dfeat, int64_t ss, int64_t ls, void* grad, int xcd_map, hipStream_t s) {
+  const int grid = level_major_grid(nl, nt, xcd_map);
+  if (grid <= 0 || nl <= 0) return hipSuccess;
   const DT* d = (const DT*)dfeat;
   GT* g = (GT*)grad;
   switch (ld.F) {
-    case 1: hipLaunchKernelGGL((k_scatter<GT, DT, 1, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map); break;
-    case 2: hipLaunchKernelGGL((k_scatter<GT, DT, 2, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map); break;
-    case 4: hipLaunchKernelGGL((k_scatter<GT, DT, 4, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map); break;
-    case 8: hipLaunchKernelGGL((k_scatter<GT, DT, 8, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map); break;
+    case 1: hipLaunchKernelGGL((k_scatter<GT, DT, 1, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map, l0, nl); break;
+    case 2: hipLaunchKernelGGL((k_scatter<GT, DT, 2, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map, l0, nl); break;
+    case 4: hipLaunchKernelGGL((k_scatter<GT, DT, 4, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map, l0, nl); break;
+    case 8: hipLaunchKernelGGL((k_scatter<GT, DT, 8, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map, l0, nl); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(Prec gp, const LevelDesc& ld, const BlockMeta* meta, const Tile* tiles, int n_tiles,
-                          int direct_block, const BlockPlan* plan, const float* coords, const void* dfeat, int64_t ss,
-                          int64_t ls, void* grad, int grouped, int xcd_map, hipStream_t s) {
+hipError_t launch_scatter(Prec gp, const LevelDesc& ld, int l0, int l1, const BlockMeta* meta, const Tile* tiles,
+                          int n_tiles, int direct_block, const BlockPlan* plan, const float* coords, const void* dfeat,
+                          int64_t ss, int64_t ls, void* grad, int grouped, int xcd_map, hipStream_t s) {
   int64_t n_direct = 0;
   int nt = n_tiles;
   if (!tiles) {
     n_direct = n_tiles;
     nt = (int)((n_direct + kTile - 1) / kTile);
   }
+  const int nl = l1 - l0;
   if (gp == Prec::F64)
-    return scat_dispatch<double, double, false>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, s);
+    return scat_dispatch<double, double, false>(ld, l0, nl, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, s);
   if (grouped)
-    return scat_dispatch<float, float, true>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, s);
-  return scat_dispatch<float, float, false>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, s);
+    return scat_dispatch<float, float, true>(ld, l0, nl, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, s);
+  return scat_dispatch<float, float, false>(ld, l0, nl, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, s);
 }
 
 // ===========================================================================

@@ -181,6 +181,34 @@ def test_one_step_gradient_parity_c1(precision, grouped):
     assert normwise(gg[nt:], g[nt:]) <= tol, "weight gradient"
 
 
+@pytest.mark.parametrize("precision,priv", [("fp32", -1), ("fp32", 0), ("mixed", -1), ("mixed", 2)])
+def test_sorted_sampling_gradient_parity(precision, priv):
+    """Spatially ordered sampling stores the same Philox draws grouped by bin; the
+    gradient (a sum over samples) must match the oracle's on the unordered draws."""
+    say(f"ordered sampling + privatized scatter {precision} priv_levels={priv}")
+    vol, lay, p0, model = _setup_c1_block(precision)
+    model.bind_volumes([dev(vol)])
+    p = p0.astype(np.float64).copy()
+    p[:lay.n_table_params] *= 1e3
+    model.load_params([p])
+    model.set_option("spatial_sort", 1)
+    model.set_option("priv_levels", priv)
+    model.set_option("apply_update", 0)
+    model.set_option("use_graph", 0)
+    loss = model.train(1, 4096, want_loss=True)
+    torch.cuda.synchronize()
+    pref = model.block_params(0).cpu().numpy().astype(np.float64) if precision == "fp32" else p
+    x = o.training_coords(77, 0, 0, 4096)
+    tgt = o.normalized_targets(vol, (64, 64, 64), 0, x)
+    L, g, _ = o.loss_and_grad(lay, pref, x, tgt)
+    gg = model.block_grads(0).cpu().numpy()
+    nt = lay.n_table_params
+    tol = 1e-5 if precision == "fp32" else 3e-2
+    assert abs(loss[0, 0].item() - L) <= (1e-5 if precision == "fp32" else 1e-2) * L
+    assert normwise(gg[:nt], g[:nt]) <= tol, "table gradient"
+    assert normwise(gg[nt:], g[nt:]) <= tol, "weight gradient"
+
+
 def test_adam_update_parity_c1():
     say("adam update c1 fp32")
     vol, lay, p0, model = _setup_c1_block("fp32")
