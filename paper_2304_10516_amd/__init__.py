@@ -7,14 +7,11 @@ Importing the package does not load the library; `paper_2304_10516_amd.DVNR`
 """
 from __future__ import annotations
 
-__all__ = ["DVNR", "EncodingCfg", "MlpCfg", "OptimCfg", "presets"]
+__all__ = ["DVNR", "EncodingCfg", "MlpCfg", "OptimCfg"]
 
 
 def __getattr__(name):
     if name in ("DVNR", "EncodingCfg", "MlpCfg", "OptimCfg"):
         from . import dvnr as _d
         return getattr(_d, name)
-    if name == "presets":
-        from . import presets as _p
-        return _p
     raise AttributeError(name)

@@ -9,10 +9,10 @@ namespace dvnrk {
 
 constexpr int kMaxLevels = 16;
 constexpr int kTile = 256;        // samples per tile (work item of the training kernels)
-constexpr int kMlpGrid = 512;     // workgroups of the persistent MLP kernel
+constexpr int kMlpGrid = 256;     // workgroups of the persistent MLP kernel (one per CU)
 constexpr int kLossRing = 1024;   // steps of per-block loss history kept on the device
 constexpr int kMaxBins = 512;     // spatial bins per block (B^3, B <= 8) of the ordered sampler
-constexpr int kSortGroup = 4096;  // samples per counting-sort group
+constexpr int kSortGroup = 1024;  // samples per counting-sort group
 
 // Level table, passed by value to kernels.
 struct LevelDesc {

@@ -334,9 +334,11 @@ hipError_t launch_scatter(Prec gp, const LevelDesc& ld, int l0, int l1, const Bl
 
 // ===========================================================================
 // Slot reduction: per block, sum the dW / loss partials written by the
-// workgroups (4 waves each) that processed the block's tiles.  Slots of block
-// b are [slot_ranges[2b], slot_ranges[2b+1]).  Writes the MLP gradient
-// (overwrite) and the block's mean loss into the loss ring.
+// workgroups that processed the block's tiles.  Slots of block b are
+// [slot_ranges[2b], slot_ranges[2b+1]).  Writes the MLP gradient (overwrite)
+// and the block's mean loss into the loss ring.  A workgroup covers 32
+// consecutive elements; its 8 rows of 32 lanes split the slot range
+// (coalesced 128-byte rows), then reduce through LDS in a fixed order.
 // ===========================================================================
 template <typename GT>
 __global__ __launch_bounds__(256) void k_reduce_slots(const float* __restrict__ slots, int64_t slot_stride,
@@ -344,18 +346,26 @@ __global__ __launch_bounds__(256) void k_reduce_slots(const float* __restrict__ 
                                                       int64_t mlp_rel_off, int64_t block_stride,
                                                       GT* __restrict__ grad, float* __restrict__ loss_ring,
                                                       Counters* __restrict__ ctr, int n_blocks) {
+  __shared__ float part[8][33];
   const int b = blockIdx.y;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e > n_mlp) return;
+  const int c = threadIdx.x % 32, r = threadIdx.x / 32;
+  const int64_t e = (int64_t)blockIdx.x * 32 + c;
   const int s0 = ranges[2 * b], s1 = ranges[2 * b + 1];
   float acc = 0.0f;
-  for (int sl = s0; sl < s1; ++sl) acc += slots[(int64_t)sl * slot_stride + e];
+  if (e <= n_mlp)
+    for (int sl = s0 + r; sl < s1; sl += 8) acc += slots[(int64_t)sl * slot_stride + e];
+  part[r][c] = acc;
+  __syncthreads();
+  if (r != 0 || e > n_mlp) return;
+  float sum = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sum += part[k][c];
   if (e < n_mlp) {
-    grad[(int64_t)b * block_stride + mlp_rel_off + e] = (GT)acc;
+    grad[(int64_t)b * block_stride + mlp_rel_off + e] = (GT)sum;
   } else {
     const int64_t step = ctr->step;
-    loss_ring[(step % kLossRing) * n_blocks + b] = acc;
-    if (!isfinite(acc)) ctr->nonfinite = 1;
+    loss_ring[(step % kLossRing) * n_blocks + b] = sum;
+    if (!isfinite(sum)) ctr->nonfinite = 1;
   }
 }
 
@@ -364,7 +374,7 @@ __global__ void k_bump(Counters* ctr) { ctr->step += 1; }
 hipError_t launch_reduce_slots(const float* slots, int64_t slot_stride, const int32_t* slot_ranges, int n_blocks,
                                int64_t n_mlp, int64_t mlp_rel_off, int64_t block_stride, Prec gp, void* grad,
                                float* loss_ring, Counters* ctr, int bump, hipStream_t s) {
-  dim3 grid((unsigned)((n_mlp + 1 + 255) / 256), (unsigned)n_blocks);
+  dim3 grid((unsigned)((n_mlp + 1 + 31) / 32), (unsigned)n_blocks);
   if (gp == Prec::F64)
     hipLaunchKernelGGL(k_reduce_slots<double>, grid, dim3(256), 0, s, slots, slot_stride, slot_ranges, n_mlp,
                        mlp_rel_off, block_stride, (double*)grad, loss_ring, ctr, n_blocks);

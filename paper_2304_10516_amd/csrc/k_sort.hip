@@ -67,9 +67,21 @@ __global__ __launch_bounds__(512) void k_sort_scan(const int32_t* __restrict__ g
   const int k = threadIdx.x;
   uint32_t run = 0;
   if (k < nbins) {
-    for (int g = g0; g < g1; ++g) {
+    // exclusive prefix over the block's groups, loads batched 8 at a time
+    int g = g0;
+    for (; g + 8 <= g1; g += 8) {
+      uint32_t c[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) c[u] = counts[(int64_t)(g + u) * nbins + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        counts[(int64_t)(g + u) * nbins + k] = run;
+        run += c[u];
+      }
+    }
+    for (; g < g1; ++g) {
       const uint32_t c = counts[(int64_t)g * nbins + k];
-      counts[(int64_t)g * nbins + k] = run;  // exclusive prefix over the block's groups
+      counts[(int64_t)g * nbins + k] = run;
       run += c;
     }
   }
