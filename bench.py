@@ -1,20 +1,23 @@
 """Benchmark of the DVNR hot path on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): one 256^3
-block of a seeded turbulence-like field (random-phase Fourier modes, shell
-energy ~ k^-5/3), multiresolution hash grid L=16, T=2^19, F=2, base 16,
+Default workload (the configuration the headline metric is quoted on): one
+256^3 block of a seeded turbulence-like field (random-phase Fourier modes,
+shell energy ~ k^-5/3), multiresolution hash grid L=16, T=2^19, F=2, base 16,
 finest 256, MLP 2 hidden layers of 64, L2 loss, Adam lr 1e-2, 2^18 samples per
-step.  A step is one pass of the whole training path: coordinate sampling and
+step.  `--workload c3`: 64 blocks with per-axis extents U{96..160} and a
+1-voxel periodic ghost layer cut from one seeded k^-5/3 field, one model per
+block (T=2^17, finest 160), 2^20 samples per step apportioned by voxel count.
+
+A step is one pass of the whole training path: coordinate sampling and
 ground-truth fetch, encoding, MLP forward / loss / backward, encoding
-backward, weight-gradient reduction and Adam.
+backward, weight-gradient reduction and Adam.  Two runs of K steps each:
+mixed precision (fp16 tables, bf16 MFMA MLP, fp32 masters; the headline
+`value`) and the plain fp32 path.  Each run is then decoded to the full grid
+(voxels/s) and scored by PSNR with an fp64 reduction.  The float64 CPU oracle
+is timed on one full training step of one block as the CPU baseline.
 
-Two runs of K steps each: mixed precision (fp16 tables, bf16 MFMA MLP, fp32
-masters) -- the headline `value` -- and the plain fp32 path.  Each run is then
-decoded to the full grid (voxels/s) and scored by PSNR with an fp64
-reduction.  The float64 CPU oracle is timed on one full training step of the
-same workload as the CPU baseline.
-
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3]
+                       [--no-cpu-baseline] [--precisions mixed,fp32]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -30,18 +33,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-BATCH = 1 << 18
-N = 256
 PEAK_HBM_GBS = 8000.0
-
-# Algorithmic bytes per training sample of each phase (mixed precision; fp32 in brackets):
-#   sample : 3 coords written (12) + 8 voxel reads (32) + target written (4)            = 48
-#   encode : coords read (12) + 16 levels x 8 corners x F=2 x 2 B [4 B] + 32 feats x 2 B [4 B] written
-#   scatter: coords (12) + 32 dX x 4 B read (128) + 16 x 8 x 2 fp32 atomic adds (1024)
-PHASE_BYTES = {
-    "mixed": {"sample": 48, "encode": 12 + 512 + 64, "scatter": 12 + 128 + 1024},
-    "fp32": {"sample": 48, "encode": 12 + 1024 + 128, "scatter": 12 + 128 + 1024},
-}
+L_LEVELS, F_FEAT = 16, 2
 ADAM_BYTES_PER_PARAM = {"mixed": 34, "fp32": 32}
 
 
@@ -49,45 +42,110 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_precision(torch, DVNR, cfg, vol_dev, precision, steps, warmup, seed=3):
-    from paper_2304_10516_amd.dvnr import EncodingCfg, MlpCfg, OptimCfg  # noqa: F401
-    enc, mlp, optim = cfg["enc"], cfg["mlp"], cfg["optim"]
-    model = DVNR(enc, mlp, [((N, N, N), 0)], optim, precision=precision, max_batch=BATCH, seed=seed)
-    model.bind_volumes([vol_dev])
+def phase_bytes(precision, phase, n_levels_priv):
+    """Algorithmic bytes per training sample of a phase (per launch = this x samples per step).
+
+    sample       : 3 coords written (12) + 8 voxel reads (32) + target written (4) = 48
+    encode       : coords (12) + L levels x 8 corners x F x table element (2 B fp16, 4 B fp32)
+                   + L x F features written (2 B bf16, 4 B fp32)
+    scatter_priv : the bin-privatized levels [0, lp): coords (12) + lp x F dX reads (4 B)
+                   + lp x 8 corners x F fp32 gradient adds (4 B)
+    scatter      : the same for the remaining levels [lp, L) (direct atomics)
+    """
+    te = 2 if precision == "mixed" else 4
+    if phase == "sample":
+        return 48
+    if phase == "encode":
+        return 12 + L_LEVELS * 8 * F_FEAT * te + L_LEVELS * F_FEAT * te
+    nl = n_levels_priv if phase == "scatter_priv" else L_LEVELS - n_levels_priv
+    if phase in ("scatter_priv", "scatter"):
+        return (12 + nl * F_FEAT * 4 + nl * 8 * F_FEAT * 4) if nl > 0 else 0
+    return None
+
+
+def make_workload(name, torch):
+    from paper_2304_10516_amd import presets
+    cfg = presets.get(name)
+    if name == "c2":
+        from fixtures import kolmogorov_field
+        log("[bench] generating the 256^3 k^-5/3 field")
+        vol = kolmogorov_field(256, seed=2)
+        blocks = [((256, 256, 256), 0)]
+        vols = [torch.tensor(vol, device="cuda")]
+        desc = ("single 256^3 block of a seeded k^-5/3 field; hash grid L=16, T=2^19, F=2, base 16, finest 256; "
+                "MLP 2x64 ReLU; L2 loss; Adam lr 1e-2")
+        return cfg, blocks, vols, desc, vol
+    if name == "c3":
+        from fixtures import kolmogorov_field_torch, uneven_block_sizes
+        sx, sy, sz = uneven_block_sizes(4, 96, 160, seed=3)
+        shape = (int(sz.sum()), int(sy.sum()), int(sx.sum()))
+        log(f"[bench] generating the {shape} periodic k^-5/3 field on the GPU and cutting 64 blocks")
+        f = kolmogorov_field_torch(shape, seed=3)
+        fp = torch.nn.functional.pad(f[None, None], (1, 1, 1, 1, 1, 1), mode="circular")[0, 0]
+        del f
+        ox, oy, oz = [np.concatenate([[0], np.cumsum(s)[:-1]]) for s in (sx, sy, sz)]
+        blocks, vols = [], []
+        for iz in range(4):
+            for iy in range(4):
+                for ix in range(4):
+                    d = (int(sx[ix]), int(sy[iy]), int(sz[iz]))
+                    z0, y0, x0 = int(oz[iz]), int(oy[iy]), int(ox[ix])
+                    vols.append(fp[z0:z0 + d[2] + 2, y0:y0 + d[1] + 2, x0:x0 + d[0] + 2].contiguous())
+                    blocks.append((d, 1))
+        del fp
+        desc = ("64 blocks, extents U{96..160} per axis, 1-voxel periodic ghost layer, cut from one seeded "
+                f"k^-5/3 field of {shape[2]}x{shape[1]}x{shape[0]}; per block L=16, T=2^17, F=2, base 16, "
+                "finest 160, MLP 2x64; samples per block proportional to voxels")
+        return cfg, blocks, vols, desc, None
+    raise ValueError(name)
+
+
+def run_precision(torch, DVNR, cfg, blocks, vols, precision, steps, warmup, seed=3):
+    batch = cfg["batch"]
+    model = DVNR(cfg["enc"], cfg["mlp"], blocks, cfg["optim"], precision=precision, max_batch=batch, seed=seed)
+    model.bind_volumes(vols)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         model.init_params(1, stream=stream)
         if warmup:
-            model.train(warmup, BATCH, stream=stream)
+            model.train(warmup, batch, stream=stream)
         model.init_params(1, stream=stream)  # the timed run starts from the initial state
         model.set_option("profile_phases", 1)
         model.phase_times()
         stream.synchronize()
-        log(f"[bench] {precision}: timing {steps} steps")
+        log(f"[bench] {precision}: timing {steps} steps of {batch} samples over {len(blocks)} block(s)")
         t0 = time.perf_counter()
-        loss = model.train(steps, BATCH, want_loss=True, stream=stream)
+        loss = model.train(steps, batch, want_loss=True, stream=stream)
         stream.synchronize()
         t1 = time.perf_counter()
         phases, nsteps = model.phase_times()
+        bins, priv = model.plan_info()
         model.set_option("profile_phases", 0)
+        outs = [torch.empty((d[2], d[1], d[0]), dtype=torch.float32, device="cuda") for d, _ in blocks]
+        for b in range(len(blocks)):  # warm
+            model.decode(b, out=outs[b], stream=stream)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        out = torch.empty((N, N, N), dtype=torch.float32, device="cuda")
-        model.decode(0, out=out, stream=stream)  # warm
         e0.record(stream)
-        model.decode(0, out=out, stream=stream)
+        for b in range(len(blocks)):
+            model.decode(b, out=outs[b], stream=stream)
         e1.record(stream)
         stream.synchronize()
         dec_ms = e0.elapsed_time(e1)
-        sse, cnt = model.squared_error(0, out, stream=stream)
+        sse, cnt = 0.0, 0
+        for b in range(len(blocks)):
+            s, c = model.squared_error(b, outs[b], stream=stream)
+            sse += s
+            cnt += c
         model.sync(stream=stream)
     ms = (t1 - t0) * 1e3 / steps
-    lossv = loss[:, 0].float().cpu().numpy()
-    res = dict(ms_per_step=ms, samples_per_s=BATCH / (ms * 1e-3), decode_ms=dec_ms,
-               decode_voxels_per_s=N ** 3 / (dec_ms * 1e-3), psnr=float(10 * np.log10(cnt / sse)),
+    lossv = loss.float().mean(dim=1).cpu().numpy()
+    res = dict(ms_per_step=ms, samples_per_s=batch / (ms * 1e-3), decode_ms=dec_ms,
+               decode_voxels_per_s=cnt / (dec_ms * 1e-3), psnr=float(10 * np.log10(cnt / sse)),
                loss_first=float(lossv[0]), loss_last=float(lossv[-1]),
-               phase_ms={k: v / max(nsteps, 1) for k, v in phases.items()}, n_params=model.sizes.n_params)
+               phase_ms={k: v / max(nsteps, 1) for k, v in phases.items()}, n_params=model.sizes.n_params,
+               bins_per_axis=bins, priv_levels=priv, batch=batch)
     log(f"[bench] {precision}: {ms:.3f} ms/step, {res['samples_per_s'] / 1e6:.1f} M samples/s, "
-        f"psnr {res['psnr']:.2f} dB, decode {dec_ms:.2f} ms, phases " +
+        f"psnr {res['psnr']:.2f} dB, decode {dec_ms:.2f} ms, bins {bins}^3, privatized levels {priv}, phases " +
         ", ".join(f"{k} {v:.3f}" for k, v in res["phase_ms"].items()))
     del model
     return res
@@ -96,12 +154,13 @@ def run_precision(torch, DVNR, cfg, vol_dev, precision, steps, warmup, seed=3):
 def roofline_for(precision, res):
     ph = res["phase_ms"]
     dom = max(ph, key=lambda k: ph[k])
+    batch = res["batch"]
     if dom == "adam":
         per_launch = ADAM_BYTES_PER_PARAM[precision] * res["n_params"]
-    elif dom in PHASE_BYTES[precision]:
-        per_launch = PHASE_BYTES[precision][dom] * BATCH
+    elif phase_bytes(precision, dom, res["priv_levels"]) is not None:
+        per_launch = phase_bytes(precision, dom, res["priv_levels"]) * batch
     else:  # mlp: MFMA-bound reading, 37,248 flop per sample
-        flops = 37248.0 * BATCH
+        flops = 37248.0 * batch
         tf = flops / (ph[dom] * 1e-3) / 1e12
         peak = 2500.0 if precision == "mixed" else 157.3
         return {"kernel": dom, "bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
@@ -112,8 +171,8 @@ def roofline_for(precision, res):
             "avg_launch_ms": ph[dom]}
 
 
-def cpu_baseline(cfg, vol):
-    """The float64 oracle, untuned, on one full training step of the workload (single thread)."""
+def cpu_baseline(cfg, vol, dims, n_samples):
+    """The float64 oracle, untuned, on one full training step of one block (single thread)."""
     from threadpoolctl import threadpool_limits
 
     from fixtures import init_param_draws
@@ -125,20 +184,22 @@ def cpu_baseline(cfg, vol):
     st = o.adam_init(lay.n_params)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        x = o.training_coords(3, 0, 0, BATCH)
-        tgt = o.normalized_targets(vol, (N, N, N), 0, x)
+        x = o.training_coords(3, 0, 0, n_samples)
+        tgt = o.normalized_targets(vol, dims, 0, x)
         o.train_step(lay, p, st, o.Optim(lr=1e-2), x, tgt)
         dt = time.perf_counter() - t0
-    return {"value": BATCH / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full training step (2^18 samples, dense Adam over {lay.n_params} params) "
-                      f"of the same workload, float64 numpy, 1 thread, {dt:.1f} s"}
+    return {"value": n_samples / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full training step ({n_samples} samples, dense Adam over {lay.n_params} params) "
+                      f"of one {dims[0]}x{dims[1]}x{dims[2]} block of the workload, float64 numpy, 1 thread, "
+                      f"{dt:.1f} s"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 5000 for c2, 2000 for c3)")
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="mixed,fp32")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -148,15 +209,11 @@ def main():
         print("bench.py measures one GPU: the DVNR hot path trains independent per-block models with no "
               "inter-GPU exchange, and this build targets a single MI355X; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    steps = args.steps if args.steps is not None else (5000 if args.workload == "c2" else 2000)
     import torch
 
-    from fixtures import kolmogorov_field
-    from paper_2304_10516_amd import presets
     from paper_2304_10516_amd.dvnr import DVNR
-    cfg = presets.get("c2")
-    log("[bench] generating the 256^3 k^-5/3 field")
-    vol = kolmogorov_field(N, seed=2)
-    vol_dev = torch.tensor(vol, device="cuda")
+    cfg, blocks, vols, desc, host_vol = make_workload(args.workload, torch)
     if args.calibrate_copy:
         a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -166,15 +223,15 @@ def main():
         del a, b
     results = {}
     for prec in args.precisions.split(","):
-        results[prec] = run_precision(torch, DVNR, cfg, vol_dev, prec, args.steps, args.warmup)
-    head = results.get("mixed") or next(iter(results.values()))
+        results[prec] = run_precision(torch, DVNR, cfg, blocks, vols, prec, steps, args.warmup)
     head_prec = "mixed" if "mixed" in results else next(iter(results))
+    head = results[head_prec]
     out = {
         "metric": "train samples/s & decode voxels/s at fixed PSNR; BF16 batched vs FP32 plain",
         "value": head["samples_per_s"],
         "unit": "samples/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
@@ -182,9 +239,8 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16" if head_prec == "mixed" else "f32",
         "data": "synthetic",
-        "config": {"workload": "single 256^3 block of a seeded k^-5/3 field; hash grid L=16, T=2^19, F=2, "
-                               "base 16, finest 256; MLP 2x64 ReLU; L2 loss; Adam lr 1e-2",
-                   "batch": BATCH, "steps": args.steps, "precision": head_prec},
+        "config": {"workload": desc, "name": args.workload, "blocks": len(blocks), "batch": cfg["batch"],
+                   "steps": steps, "precision": head_prec},
         "decode_voxels_per_s": head["decode_voxels_per_s"],
         "psnr_db": head["psnr"],
         "phase_ms": head["phase_ms"],
@@ -198,8 +254,14 @@ def main():
         out["speedup_vs_fp32_plain"] = head["samples_per_s"] / f["samples_per_s"]
         out["psnr_gap_db"] = head["psnr"] - f["psnr"]
     if not args.no_cpu_baseline:
-        log("[bench] timing the float64 CPU oracle on one full step")
-        out["cpu_baseline"] = cpu_baseline(cfg, vol)
+        log("[bench] timing the float64 CPU oracle on one full step of one block")
+        if host_vol is None:
+            d, g = blocks[0]
+            host_vol = vols[0][g:g + d[2], g:g + d[1], g:g + d[0]].contiguous().cpu().numpy()
+        d = blocks[0][0]
+        n0 = cfg["batch"] if len(blocks) == 1 else max(256, cfg["batch"] * d[0] * d[1] * d[2] //
+                                                        sum(b[0][0] * b[0][1] * b[0][2] for b in blocks))
+        out["cpu_baseline"] = cpu_baseline(cfg, host_vol, d, n0)
     print(json.dumps(out), flush=True)
 
 

@@ -9,6 +9,7 @@ imported by it.
 from .fields import (  # noqa: F401
     gaussian_sum_field,
     kolmogorov_field,
+    kolmogorov_field_torch,
     advected_blobs_field,
     cut_blocks,
     uneven_block_sizes,

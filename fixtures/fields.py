@@ -74,6 +74,34 @@ def kolmogorov_field(n: int = 256, seed: int = 2, shape=None) -> np.ndarray:
     return _normalize01(f)
 
 
+def kolmogorov_field_torch(shape, seed: int = 2, device="cuda"):
+    """`kolmogorov_field` synthesized with torch.fft in float32 on `device`.
+
+    Same recipe (random phases, amplitude |k|^(-11/6), DC and |k| > min(shape)/2
+    zeroed, min/max normalized), for fields too large for a host FFT; the phases
+    come from a torch generator, so the values differ from the numpy version.
+    Returns a float32 tensor (nz, ny, nx) on `device`.
+    """
+    import torch
+    nz, ny, nx = shape
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    kz = torch.fft.fftfreq(nz, device=device) * nz
+    ky = torch.fft.fftfreq(ny, device=device) * ny
+    kx = torch.fft.rfftfreq(nx, device=device) * nx
+    kk = torch.sqrt(kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2)
+    kmax = min(shape) / 2.0
+    amp = torch.where((kk > 0) & (kk <= kmax), kk.clamp_min(1e-12) ** (-11.0 / 6.0), torch.zeros_like(kk))
+    del kk
+    phase = torch.rand(amp.shape, generator=g, device=device) * (2.0 * np.pi)
+    spec = torch.polar(amp, phase)
+    del amp, phase
+    f = torch.fft.irfftn(spec, s=(nz, ny, nx))
+    del spec
+    lo, hi = f.min(), f.max()
+    return ((f - lo) / (hi - lo)).contiguous()
+
+
 def advected_blobs_field(n: int = 256, n_steps: int = 40, n_blobs: int = 16, seed: int = 4, step: int = 0) -> np.ndarray:
     """One timestep of Gaussian blobs advected by a seeded divergence-free flow.
 

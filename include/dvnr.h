@@ -211,11 +211,30 @@ dvnr_status dvnr_debug_indices(dvnr_t* h, int32_t level, int64_t n, const float*
 /* Per-phase device time in milliseconds, summed over the training steps run
  * with the "profile_phases" option since the previous call (those steps run
  * eagerly, with HIP events on the training stream between the phases):
- * ms6[0] sampler, [1] encoding forward, [2] MLP forward/loss/backward,
- * [3] encoding backward (scatter), [4] weight-gradient reduction, [5] Adam.
- * *n_steps (may be NULL) receives the number of steps covered.  Waits for
- * those steps to finish; resets the sums. */
-dvnr_status dvnr_phase_times(dvnr_t* h, double* ms6, int64_t* n_steps);
+ * ms7[0] sampler, [1] encoding forward, [2] MLP forward/loss/backward,
+ * [3] encoding backward of the bin-privatized levels, [4] encoding backward
+ * of the remaining levels (direct atomics), [5] weight-gradient reduction,
+ * [6] Adam.  *n_steps (may be NULL) receives the number of steps covered.
+ * Waits for those steps to finish; resets the sums. */
+dvnr_status dvnr_phase_times(dvnr_t* h, double* ms7, int64_t* n_steps);
+
+/* Autotuner: time the candidate step configurations (unordered or spatially
+ * ordered sampling, the number of bin-privatized coarse levels, the number of
+ * workgroups of the persistent MLP kernel) on n_trial_steps gradient-only
+ * steps of samples_per_step samples each, and keep the fastest for later
+ * dvnr_train_steps calls with that sample count.  Parameters and optimizer
+ * state are unchanged: trial steps apply no update, their gradients are
+ * cleared and the step counter is restored.  Synchronizes `stream`.
+ * *best_ms (may be NULL) receives the chosen configuration's time per step
+ * without the Adam update. */
+dvnr_status dvnr_autotune(dvnr_t* h, int64_t samples_per_step, int32_t n_trial_steps, double* best_ms,
+                          void* stream);
+
+/* Layout of the current training plan (the last samples_per_step given to
+ * dvnr_train_steps): spatial bins per axis of the ordered sampler and the
+ * number of coarse levels whose encoding backward is bin-privatized (levels
+ * [0, *priv_levels)); 0 when ordered sampling is off.  Any pointer may be NULL. */
+dvnr_status dvnr_plan_info(const dvnr_t* h, int32_t* bins_per_axis, int32_t* priv_levels);
 
 /* Wait for `stream`; reports HIP errors and a non-finite loss seen since the
  * last dvnr_sync (DVNR_E_NONFINITE). */

@@ -80,6 +80,8 @@ SIGNATURES = {
     "dvnr_sync": [P, VP],
     "dvnr_set_option": [P, C.c_char_p, I64],
     "dvnr_phase_times": [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
+    "dvnr_plan_info": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+    "dvnr_autotune": [P, I64, I32, C.POINTER(C.c_double), VP],
 }
 
 

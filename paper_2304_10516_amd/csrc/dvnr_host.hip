@@ -66,6 +66,7 @@ struct dvnr {
   int scatter_grouped = 0;
   int use_graph = 1;
   int xcd_map = 1;
+  int mlp_cap = kMlpGrid;  // workgroups of the persistent MLP kernel (autotuned)
   int apply_update = 1;
   // spatially ordered sampling and bin-privatized scatter of the coarse levels
   int spatial_sort = 0;
@@ -79,7 +80,8 @@ struct dvnr {
   int profile = 0;
   std::vector<hipEvent_t> prof_ev;
   int64_t prof_recorded = 0, prof_accumulated = 0;
-  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+  static constexpr int kPhases = 7;  // sample, encode, mlp, scatter (privatized), scatter (direct), reduce, adam
+  double prof_ms[kPhases] = {0, 0, 0, 0, 0, 0, 0};
   hipGraphExec_t graph = nullptr;
   hipStream_t graph_stream = nullptr;
   int64_t graph_total = -1;
@@ -246,7 +248,7 @@ dvnr_status dvnr_create(const dvnr_encoding* enc, const dvnr_mlp* mlp, const dvn
     };
     h->max_tiles = max_batch / kTile + n_blocks + 1;
     h->slot_stride = align_up(h->n_mlp + 1, 64);
-    h->n_slots = (int64_t)(kMlpGrid + n_blocks) * 4;
+    h->n_slots = (int64_t)(2 * kMlpGrid + n_blocks);  // slot w + b for w < MLP workgroups (<= 2 kMlpGrid)
     h->feat_elem = h->prec == Prec::MIXED ? 2 : (h->prec == Prec::F64 ? 8 : 4);
     const int64_t in_dim = md.in_dim;
     h->o_meta = take(sizeof(BlockMeta) * n_blocks);
@@ -460,7 +462,7 @@ static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_
   }
   h->n_tiles = (int)h->htiles.size();
   if (h->n_tiles > h->max_tiles) return fail(DVNR_E_INVALID, "too many tiles");
-  h->mlp_grid = std::max(1, std::min(kMlpGrid, h->n_tiles));
+  h->mlp_grid = std::max(1, std::min(h->mlp_cap, h->n_tiles));
   const int G = h->mlp_grid, T = h->n_tiles;
   auto wg_of_tile = [&](int t) {
     // the workgroup w with floor(w*T/G) <= t < floor((w+1)*T/G)
@@ -494,12 +496,14 @@ static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_
   int B = 1;
   while (B < 8 && (int64_t)(B + 1) * (B + 1) * (B + 1) * 512 <= min_n) ++B;
   h->sort_B = B;
-  const double per_bin = (double)min_n / (double)(B * B * B);
+  // Privatize the longest prefix of levels whose per-bin cell box fits the
+  // LDS budget (8192 cells) and whose corner hits per step are dense enough
+  // (>= 0.3 per grid vertex) for per-entry sums to save atomics.
   int pl = 0;
   for (int l = 0; l < h->enc.n_levels; ++l) {
-    const double side = (double)(h->ld.R[l] - 1) / (double)B + 2.0;  // vertices per axis of a bin's box
-    const double box = side * side * side;
-    if (box * h->enc.n_features > 0.75 * 16384 || box > 2.0 * 8.0 * per_bin) break;
+    const double R = (double)h->ld.R[l];
+    const double side = (R - 1.0) / (double)B + 1.5;  // cells per axis of a bin's box, with slack
+    if (side * side * side > 8192.0 || 8.0 * (double)min_n < 0.3 * R * R * R) break;
     pl = l + 1;
   }
   h->priv_L = h->priv_levels >= 0 ? std::min(h->priv_levels, h->enc.n_levels) : pl;
@@ -520,9 +524,10 @@ static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_
 
 // Fold the event times of recorded step `k` (ring slot k % kProfRing) into the sums.
 static dvnr_status prof_accumulate_one(dvnr_t* h, int64_t k) {
-  hipEvent_t* ev = &h->prof_ev[(size_t)(k % dvnr::kProfRing) * 7];
-  HIPCHK(hipEventSynchronize(ev[6]));
-  for (int p = 0; p < 6; ++p) {
+  constexpr int NE = dvnr::kPhases + 1;
+  hipEvent_t* ev = &h->prof_ev[(size_t)(k % dvnr::kProfRing) * NE];
+  HIPCHK(hipEventSynchronize(ev[dvnr::kPhases]));
+  for (int p = 0; p < dvnr::kPhases; ++p) {
     float ms = 0.0f;
     HIPCHK(hipEventElapsedTime(&ms, ev[p], ev[p + 1]));
     h->prof_ms[p] += ms;
@@ -530,12 +535,13 @@ static dvnr_status prof_accumulate_one(dvnr_t* h, int64_t k) {
   return DVNR_OK;
 }
 
-// Event marking the boundary before phase p of the step being recorded (p = 6: end).
+// Event marking the boundary before phase p of the step being recorded (p = kPhases: end).
 static dvnr_status prof_mark(dvnr_t* h, int p, hipStream_t s) {
+  constexpr int NE = dvnr::kPhases + 1;
   if (!h->profile) return DVNR_OK;
   if (p == 0) {
     if (h->prof_ev.empty()) {
-      h->prof_ev.resize((size_t)dvnr::kProfRing * 7);
+      h->prof_ev.resize((size_t)dvnr::kProfRing * NE);
       for (auto& e : h->prof_ev) HIPCHK(hipEventCreate(&e));
     }
     if (h->prof_recorded - h->prof_accumulated >= dvnr::kProfRing) {
@@ -544,8 +550,8 @@ static dvnr_status prof_mark(dvnr_t* h, int p, hipStream_t s) {
       h->prof_accumulated += 1;
     }
   }
-  HIPCHK(hipEventRecord(h->prof_ev[(size_t)(h->prof_recorded % dvnr::kProfRing) * 7 + p], s));
-  if (p == 6) h->prof_recorded += 1;
+  HIPCHK(hipEventRecord(h->prof_ev[(size_t)(h->prof_recorded % dvnr::kProfRing) * NE + p], s));
+  if (p == dvnr::kPhases) h->prof_recorded += 1;
   return DVNR_OK;
 }
 
@@ -584,21 +590,22 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   if (lp > 0)
     HIPCHK(launch_scatter_priv(h->ld, 0, lp, h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(),
                                h->d_coords(), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, s));
+  PROF(4);
   HIPCHK(launch_scatter(Prec::F32, h->ld, lp, h->enc.n_levels, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
                         h->d_coords(), h->d_dfeat(), F, h->max_batch * F, h->buf.grads, h->scatter_grouped,
                         h->xcd_map, s));
-  PROF(4);
+  PROF(5);
   HIPCHK(launch_reduce_slots(h->d_slots(), h->slot_stride, h->d_ranges(), h->nb, h->n_mlp, h->n_table, h->stride,
                              Prec::F32, h->buf.grads, h->d_ring(), h->d_ctr(), 1, s));
-  PROF(5);
+  PROF(6);
   if (!h->apply_update) {
-    PROF(6);
+    PROF(7);
     return DVNR_OK;
   }
   HIPCHK(launch_adam(h->prec, h->buf.params, h->buf.grads, h->buf.adam_m, h->buf.adam_v,
                      mixed ? (uint16_t*)h->buf.work16 : nullptr, h->nb, h->stride, h->n_table, h->n_table + h->n_mlp,
                      h->d_ctr(), h->opt.lr, h->opt.beta1, h->opt.beta2, h->opt.eps, h->opt.weight_decay, s));
-  PROF(6);
+  PROF(7);
   return DVNR_OK;
 }
 
@@ -857,15 +864,104 @@ dvnr_status dvnr_sync(dvnr_t* h, void* stream) {
   return DVNR_OK;
 }
 
-dvnr_status dvnr_phase_times(dvnr_t* h, double* ms6, int64_t* n_steps) {
-  if (!h || !ms6) return fail(DVNR_E_INVALID, "null argument");
+dvnr_status dvnr_autotune(dvnr_t* h, int64_t samples_per_step, int32_t n_trial_steps, double* best_ms,
+                          void* stream) {
+  try {
+    dvnr_status st = train_ready(h);
+    if (st) return st;
+    if (samples_per_step < 1 || samples_per_step > h->max_batch)
+      return fail(DVNR_E_INVALID, "samples_per_step must be in [1, max_batch]");
+    if (h->nb > 1 && samples_per_step % kTile)
+      return fail(DVNR_E_INVALID, "with several blocks samples_per_step must be a multiple of 256");
+    if (n_trial_steps < 1 || n_trial_steps > 1000) return fail(DVNR_E_INVALID, "n_trial_steps must be in [1, 1000]");
+    hipStream_t s = (hipStream_t)stream;
+    const int save_update = h->apply_update, save_profile = h->profile;
+    const int64_t saved_step = h->host_step;
+    const std::vector<int64_t> n = apportion(h, samples_per_step);
+    // the automatic privatized-level count of this plan
+    h->priv_levels = -1;
+    h->spatial_sort = 1;
+    st = set_plan(h, n, s);
+    if (st) return st;
+    const int auto_pl = h->priv_L, L = h->enc.n_levels;
+    struct Cand {
+      int sort, priv, cap;
+    };
+    std::vector<Cand> cands = {{0, 0, kMlpGrid},
+                               {1, auto_pl, kMlpGrid},
+                               {1, std::max(0, auto_pl - 2), kMlpGrid},
+                               {1, std::min(L, auto_pl + 1), kMlpGrid},
+                               {1, auto_pl, kMlpGrid / 2},
+                               {1, auto_pl, 2 * kMlpGrid}};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    h->apply_update = 0;
+    h->profile = 0;
+    double best = 1e300;
+    Cand pick = cands[1];
+    for (const Cand& c : cands) {
+      h->spatial_sort = c.sort;
+      h->priv_levels = c.priv;
+      h->mlp_cap = c.cap;
+      st = set_plan(h, n, s);
+      if (st) break;
+      for (int k = 0; k < 2 && !st; ++k) st = enqueue_step(h, 1, s);
+      if (st) break;
+      HIPCHK(hipEventRecord(e0, s));
+      for (int k = 0; k < n_trial_steps && !st; ++k) st = enqueue_step(h, 1, s);
+      if (st) break;
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      const double per = (double)ms / n_trial_steps;
+      if (per < best) {
+        best = per;
+        pick = c;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->apply_update = save_update;
+    h->profile = save_profile;
+    if (st) return st;
+    // restore the step counter and clear the trial gradients
+    int64_t* dstep = (int64_t*)((char*)h->d_ctr() + offsetof(Counters, step));
+    HIPCHK(hipMemcpyAsync(dstep, &saved_step, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_zero(h->buf.grads, h->n_params * (int64_t)h->pelem(), s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->host_step = saved_step;
+    h->spatial_sort = pick.sort;
+    h->priv_levels = pick.priv;
+    h->mlp_cap = pick.cap;
+    st = set_plan(h, n, s);
+    if (st) return st;
+    h->plan_total = samples_per_step;
+    if (best_ms) *best_ms = best;
+    return DVNR_OK;
+  } catch (...) {
+    return fail(DVNR_E_INVALID, "autotune failed");
+  }
+}
+
+dvnr_status dvnr_plan_info(const dvnr_t* h, int32_t* bins_per_axis, int32_t* priv_levels) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  const bool on = h->spatial_sort && h->n_groups > 0;
+  if (bins_per_axis) *bins_per_axis = on ? h->sort_B : 0;
+  if (priv_levels) *priv_levels = on ? h->priv_L : 0;
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_phase_times(dvnr_t* h, double* ms7, int64_t* n_steps) {
+  if (!h || !ms7) return fail(DVNR_E_INVALID, "null argument");
   while (h->prof_accumulated < h->prof_recorded) {
     dvnr_status st = prof_accumulate_one(h, h->prof_accumulated);
     if (st) return st;
     h->prof_accumulated += 1;
   }
-  for (int p = 0; p < 6; ++p) {
-    ms6[p] = h->prof_ms[p];
+  for (int p = 0; p < dvnr::kPhases; ++p) {
+    ms7[p] = h->prof_ms[p];
     h->prof_ms[p] = 0.0;
   }
   if (n_steps) *n_steps = h->prof_recorded;

@@ -167,13 +167,21 @@ hipError_t launch_sorted_sample(const Tile* groups, int n_groups, const int32_t*
 
 // ===========================================================================
 // Bin-privatized encoding backward for levels [l0, l1).  One workgroup per
-// (block, bin, level).  The vertex box touched by the bin's samples is found
-// by a min/max reduction over their cell origins; when its F floats per
-// vertex fit the LDS budget, the workgroup accumulates there and flushes one
-// atomic per touched (vertex, feature); otherwise it falls back to grouped
-// direct atomics.
+// (block, bin, level), in gather form:
+//   1. the cell box touched by the bin's samples (min/max of cell origins);
+//   2. a counting sort of the samples by cell inside the box (one integer LDS
+//      atomic per sample) that stores each sample's fractions t and dL/dy in
+//      cell order;
+//   3. one lane per (box vertex, feature) sums w_c * dy over the samples of
+//      the up to 8 cells that have the vertex as a corner (no float atomics),
+//      and adds the sum to the table gradient with one global atomic; lanes
+//      walk vertices x fastest, so an atomic instruction covers contiguous
+//      entries (dense) or a few aligned segments (hashed, x prime 1).
+// A bin whose cell box exceeds the LDS budget falls back to grouped direct
+// atomics.  Samples beyond kPrivRecs per bin are processed in chunks.
 // ===========================================================================
-constexpr int kPrivFloats = 16384;  // 64 KiB of fp32 accumulators
+constexpr int kPrivCells = 8192;  // cells of the box (int counters / starts)
+constexpr int kPrivRecs = 1024;   // samples per chunk held in LDS
 
 template <int F>
 __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int nlev, int B,
@@ -183,8 +191,12 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
                                                       const float* __restrict__ coords,
                                                       const float* __restrict__ dfeat, int64_t ls,
                                                       float* __restrict__ grad) {
-  __shared__ float acc[kPrivFloats];
+  __shared__ int cstart[kPrivCells + 1];
+  __shared__ float4 rt[kPrivRecs];       // tx, ty, tz of each placed sample
+  __shared__ float rd[kPrivRecs * F];    // dL/dy of each placed sample
+  __shared__ int part[256];
   __shared__ int box[6];
+  constexpr int PER = kPrivRecs / 256;   // samples per thread in a chunk
   const int nbins = B * B * B;
   const int wg = blockIdx.x;
   const int l = l0 + wg % nlev;
@@ -198,9 +210,10 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
   const float sc = ld.scale[l];
   const int dense = ld.dense[l];
   float* g = grad + meta[b].param_off + (int64_t)ld.off[l] * F;
-  // ---- vertex box of the bin's samples
+  const int tid = threadIdx.x;
+  // ---- 1. cell box of the bin's samples
   int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
-  for (int j = s0 + (int)threadIdx.x; j < s1; j += blockDim.x) {
+  for (int j = s0 + tid; j < s1; j += 256) {
     const int64_t gi = base + j;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -219,61 +232,28 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
       hi[a] = max(hi[a], __shfl_xor(hi[a], o, 64));
     }
   }
-  if (threadIdx.x == 0)
+  if (tid == 0)
     for (int a = 0; a < 3; ++a) {
       box[a] = 1 << 30;
       box[3 + a] = -1;
     }
   __syncthreads();
-  if ((threadIdx.x & 63) == 0)
+  if ((tid & 63) == 0)
     for (int a = 0; a < 3; ++a) {
       atomicMin(&box[a], lo[a]);
       atomicMax(&box[3 + a], hi[a]);
     }
   __syncthreads();
   const int bx0 = box[0], by0 = box[1], bz0 = box[2];
-  const int dx = box[3] - bx0 + 2, dy = box[4] - by0 + 2, dz = box[5] - bz0 + 2;  // vertices per axis
-  const int64_t nv = (int64_t)dx * dy * dz;
-  if (nv * F <= kPrivFloats) {
-    for (int i = threadIdx.x; i < nv * F; i += blockDim.x) acc[i] = 0.0f;
-    __syncthreads();
-    for (int j = s0 + (int)threadIdx.x; j < s1; j += blockDim.x) {
-      const int64_t gi = base + j;
-      int ix, iy, iz;
-      float tx, ty, tz;
-      grid_pos(coords[3 * gi + 0], sc, R, ix, tx);
-      grid_pos(coords[3 * gi + 1], sc, R, iy, ty);
-      grid_pos(coords[3 * gi + 2], sc, R, iz, tz);
-      float d[F];
-#pragma unroll
-      for (int f = 0; f < F; ++f) d[f] = dfeat[(int64_t)l * ls + gi * F + f];
-      const int lx = ix - bx0, ly = iy - by0, lz = iz - bz0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
-        const float w = (cx ? tx : 1.0f - tx) * (cy ? ty : 1.0f - ty) * (cz ? tz : 1.0f - tz);
-        const int v = (lx + cx) + dx * ((ly + cy) + dy * (lz + cz));
-#pragma unroll
-        for (int f = 0; f < F; ++f) atomicAdd(&acc[v * F + f], w * d[f]);
-      }
-    }
-    __syncthreads();
-    // flush: element e = v * F + f, x fastest, so consecutive lanes hit consecutive entries
-    for (int e = threadIdx.x; e < nv * F; e += blockDim.x) {
-      const float val = acc[e];
-      if (val == 0.0f) continue;
-      const int v = e / F, f = e % F;
-      const int vx = bx0 + v % dx, vy = by0 + (v / dx) % dy, vz = bz0 + v / (dx * dy);
-      const uint32_t ent = corner_index(dense, R, ld.T_mask, (uint32_t)vx, (uint32_t)vy, (uint32_t)vz);
-      unsafeAtomicAdd(&g[(int64_t)ent * F + f], val);
-    }
-  } else {
+  const int cx_n = box[3] - bx0 + 1, cy_n = box[4] - by0 + 1, cz_n = box[5] - bz0 + 1;  // cells per axis
+  const int64_t C = (int64_t)cx_n * cy_n * cz_n;
+  if (C > kPrivCells) {
     // box too large for LDS: grouped direct atomics (2F lanes per x-neighbour pair)
     constexpr int G = 2 * F;
-    const int q = threadIdx.x % G;
+    const int q = tid % G;
     const int cx = q / F, f = q % F;
     const int items = (s1 - s0) * 4;
-    for (int it = threadIdx.x / G; it < items; it += blockDim.x / G) {
+    for (int it = tid / G; it < items; it += 256 / G) {
       const int64_t gi = base + s0 + (it >> 2);
       const int yz = it & 3;
       int ix, iy, iz;
@@ -286,6 +266,94 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
       const float w = (cx ? tx : 1.0f - tx) * (cy ? ty : 1.0f - ty) * (cz ? tz : 1.0f - tz);
       unsafeAtomicAdd(&g[(int64_t)e * F + f], w * dfeat[(int64_t)l * ls + gi * F + f]);
     }
+    return;
+  }
+  const int vx_n = cx_n + 1, vy_n = cy_n + 1, vz_n = cz_n + 1;  // vertices per axis
+  const int NV = vx_n * vy_n * vz_n;
+  for (int c0 = s0; c0 < s1; c0 += kPrivRecs) {
+    const int cn = min(kPrivRecs, s1 - c0);
+    for (int i = tid; i <= C; i += 256) cstart[i] = 0;
+    __syncthreads();
+    // ---- 2a. cell of each sample and its rank within the cell
+    int mcell[PER], mrank[PER];
+    float mt[PER][3], md[PER][F];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int j = tid + 256 * u;
+      mcell[u] = -1;
+      if (j < cn) {
+        const int64_t gi = base + c0 + j;
+        int i0[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) grid_pos(coords[3 * gi + a], sc, R, i0[a], mt[u][a]);
+#pragma unroll
+        for (int f = 0; f < F; ++f) md[u][f] = dfeat[(int64_t)l * ls + gi * F + f];
+        mcell[u] = (i0[0] - bx0) + cx_n * ((i0[1] - by0) + cy_n * (i0[2] - bz0));
+        mrank[u] = atomicAdd(&cstart[mcell[u]], 1);
+      }
+    }
+    __syncthreads();
+    // ---- 2b. exclusive scan of the C cell counts (contiguous chunk per thread)
+    {
+      const int chunk = (int)((C + 255) / 256);
+      const int a0 = tid * chunk, a1 = min((int)C, a0 + chunk);
+      int run = 0;
+      for (int i = a0; i < a1; ++i) run += cstart[i];
+      part[tid] = run;
+      __syncthreads();
+      for (int o = 1; o < 256; o <<= 1) {
+        const int v = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+      }
+      int acc = part[tid] - run;
+      for (int i = a0; i < a1; ++i) {
+        const int c = cstart[i];
+        cstart[i] = acc;
+        acc += c;
+      }
+      if (tid == 255) cstart[C] = part[255];
+      __syncthreads();
+    }
+    // ---- 2c. place the samples in cell order
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      if (mcell[u] >= 0) {
+        const int p = cstart[mcell[u]] + mrank[u];
+        rt[p] = make_float4(mt[u][0], mt[u][1], mt[u][2], 0.0f);
+#pragma unroll
+        for (int f = 0; f < F; ++f) rd[p * F + f] = md[u][f];
+      }
+    }
+    __syncthreads();
+    // ---- 3. gather per (vertex, feature), x fastest, and one atomic per touched entry
+    for (int e = tid; e < NV * F; e += 256) {
+      const int v = e / F, f = e % F;
+      const int lx = v % vx_n, ly = (v / vx_n) % vy_n, lz = v / (vx_n * vy_n);
+      float acc = 0.0f;
+      bool touched = false;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int ccx = k & 1, ccy = (k >> 1) & 1, ccz = (k >> 2) & 1;  // corner of the cell
+        const int x = lx - ccx, y = ly - ccy, z = lz - ccz;                 // the cell
+        if (x < 0 || y < 0 || z < 0 || x >= cx_n || y >= cy_n || z >= cz_n) continue;
+        const int cell = x + cx_n * (y + cy_n * z);
+        const int p0 = cstart[cell], p1 = cstart[cell + 1];
+        for (int p = p0; p < p1; ++p) {
+          const float4 t = rt[p];
+          const float w = (ccx ? t.x : 1.0f - t.x) * (ccy ? t.y : 1.0f - t.y) * (ccz ? t.z : 1.0f - t.z);
+          acc += w * rd[p * F + f];
+          touched = true;
+        }
+      }
+      if (touched) {
+        const uint32_t ent = corner_index(dense, R, ld.T_mask, (uint32_t)(bx0 + lx), (uint32_t)(by0 + ly),
+                                          (uint32_t)(bz0 + lz));
+        unsafeAtomicAdd(&g[(int64_t)ent * F + f], acc);
+      }
+    }
+    __syncthreads();
   }
 }
 

@@ -188,14 +188,27 @@ class DVNR:
                                                     _stream_ptr(stream)))
         return coords, target
 
-    PHASES = ("sample", "encode", "mlp", "scatter", "reduce", "adam")
+    PHASES = ("sample", "encode", "mlp", "scatter_priv", "scatter", "reduce", "adam")
 
     def phase_times(self):
         """{phase: total ms} and the step count since the previous call (needs option profile_phases=1)."""
-        ms = (C.c_double * 6)()
+        ms = (C.c_double * 7)()
         n = C.c_int64()
         L.check(self.lib.dvnr_phase_times(self.h, ms, C.byref(n)))
         return dict(zip(self.PHASES, list(ms))), n.value
+
+    def autotune(self, samples_per_step: int, n_trial_steps: int = 5, stream=None) -> float:
+        """Pick the fastest step configuration for this sample count; returns its ms per step (no update)."""
+        ms = C.c_double()
+        L.check(self.lib.dvnr_autotune(self.h, int(samples_per_step), int(n_trial_steps), C.byref(ms),
+                                       _stream_ptr(stream)))
+        return ms.value
+
+    def plan_info(self):
+        """(spatial bins per axis, number of bin-privatized coarse levels) of the current training plan."""
+        bpa, pl = C.c_int32(), C.c_int32()
+        L.check(self.lib.dvnr_plan_info(self.h, C.byref(bpa), C.byref(pl)))
+        return bpa.value, pl.value
 
     def sync(self, stream=None):
         L.check(self.lib.dvnr_sync(self.h, _stream_ptr(stream)))
