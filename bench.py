@@ -75,27 +75,39 @@ def make_workload(name, torch):
         desc = ("single 256^3 block of a seeded k^-5/3 field; hash grid L=16, T=2^19, F=2, base 16, finest 256; "
                 "MLP 2x64 ReLU; L2 loss; Adam lr 1e-2")
         return cfg, blocks, vols, desc, vol
-    if name == "c3":
+    if name in ("c3", "c5"):
         from fixtures import kolmogorov_field_torch, uneven_block_sizes
-        sx, sy, sz = uneven_block_sizes(4, 96, 160, seed=3)
+        if name == "c3":
+            sx, sy, sz = uneven_block_sizes(4, 96, 160, seed=3)
+            seed = 3
+        else:
+            sx = sy = sz = np.full(8, 128)
+            seed = 5
+        nb_axis = len(sx)
         shape = (int(sz.sum()), int(sy.sum()), int(sx.sum()))
-        log(f"[bench] generating the {shape} periodic k^-5/3 field on the GPU and cutting 64 blocks")
-        f = kolmogorov_field_torch(shape, seed=3)
+        log(f"[bench] generating the {shape} periodic k^-5/3 field on the GPU and cutting {nb_axis ** 3} blocks")
+        f = kolmogorov_field_torch(shape, seed=seed)
         fp = torch.nn.functional.pad(f[None, None], (1, 1, 1, 1, 1, 1), mode="circular")[0, 0]
         del f
         ox, oy, oz = [np.concatenate([[0], np.cumsum(s)[:-1]]) for s in (sx, sy, sz)]
         blocks, vols = [], []
-        for iz in range(4):
-            for iy in range(4):
-                for ix in range(4):
+        for iz in range(nb_axis):
+            for iy in range(nb_axis):
+                for ix in range(nb_axis):
                     d = (int(sx[ix]), int(sy[iy]), int(sz[iz]))
                     z0, y0, x0 = int(oz[iz]), int(oy[iy]), int(ox[ix])
                     vols.append(fp[z0:z0 + d[2] + 2, y0:y0 + d[1] + 2, x0:x0 + d[0] + 2].contiguous())
                     blocks.append((d, 1))
         del fp
-        desc = ("64 blocks, extents U{96..160} per axis, 1-voxel periodic ghost layer, cut from one seeded "
-                f"k^-5/3 field of {shape[2]}x{shape[1]}x{shape[0]}; per block L=16, T=2^17, F=2, base 16, "
-                "finest 160, MLP 2x64; samples per block proportional to voxels")
+        torch.cuda.empty_cache()
+        if name == "c3":
+            desc = ("64 blocks, extents U{96..160} per axis, 1-voxel periodic ghost layer, cut from one seeded "
+                    f"k^-5/3 field of {shape[2]}x{shape[1]}x{shape[0]}; per block L=16, T=2^17, F=2, base 16, "
+                    "finest 160, MLP 2x64; samples per block proportional to voxels")
+        else:
+            desc = ("one GPU's share at scale: 1024^3 seeded k^-5/3 field cut into 512 blocks of 128^3 with a "
+                    "1-voxel periodic ghost layer; per block L=16, T=2^19, F=2, base 16, finest 128, MLP 2x64; "
+                    "2^21 samples per step (4096 per block)")
         return cfg, blocks, vols, desc, None
     raise ValueError(name)
 
@@ -151,6 +163,48 @@ def run_precision(torch, DVNR, cfg, blocks, vols, precision, steps, warmup, seed
     return res
 
 
+def run_timeseries(torch, DVNR, cfg, precision, n_timesteps, steps_per_t, seed=3):
+    """In situ time series: every timestep of the advected-blob field is compressed by
+    training the previous timestep's model for `steps_per_t` steps (weights kept,
+    Adam moments and step reset: warm start); reports per-timestep latency."""
+    from fixtures import advected_blobs_series_torch
+    n = 256
+    batch = cfg["batch"]
+    series = advected_blobs_series_torch(n, n_timesteps, 16, seed=4)
+    vol = next(series).contiguous()
+    model = DVNR(cfg["enc"], cfg["mlp"], [((n, n, n), 0)], cfg["optim"], precision=precision, max_batch=batch,
+                 seed=seed)
+    model.bind_volumes([vol])
+    vol_bound = model._vols[0]
+    stream = torch.cuda.Stream()
+    lat, psnr = [], []
+    out = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
+    with torch.cuda.stream(stream):
+        model.init_params(1, stream=stream)
+        model.train(5, batch, stream=stream)  # build the plan and the graph
+        model.init_params(1, stream=stream)
+        stream.synchronize()
+        for t in range(n_timesteps):
+            if t > 0:
+                vol_bound.copy_(next(series))
+            stream.synchronize()
+            t0 = time.perf_counter()
+            model.prepare(stream=stream)
+            model.reset_optimizer(stream=stream)
+            model.train(steps_per_t, batch, stream=stream)
+            stream.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e3)
+            model.decode(0, out=out, stream=stream)
+            sse, cnt = model.squared_error(0, out, stream=stream)
+            psnr.append(float(10 * np.log10(cnt / sse)))
+            log(f"[bench] c4 {precision} timestep {t}: {lat[-1]:.1f} ms, psnr {psnr[-1]:.2f} dB")
+        model.sync(stream=stream)
+    del model
+    ms = float(np.mean(lat)) / steps_per_t
+    return dict(ms_per_step=ms, samples_per_s=batch / (ms * 1e-3), latency_ms=lat, psnr_per_t=psnr,
+                psnr=float(np.mean(psnr)), batch=batch)
+
+
 def roofline_for(precision, res):
     ph = res["phase_ms"]
     dom = max(ph, key=lambda k: ph[k])
@@ -199,7 +253,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 5000 for c2, 2000 for c3)")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--timesteps", type=int, default=40, help="c4: timesteps of the series")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="mixed,fp32")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -209,10 +264,28 @@ def main():
         print("bench.py measures one GPU: the DVNR hot path trains independent per-block models with no "
               "inter-GPU exchange, and this build targets a single MI355X; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    steps = args.steps if args.steps is not None else (5000 if args.workload == "c2" else 2000)
+    steps = args.steps if args.steps is not None else {"c2": 5000, "c3": 2000, "c4": 500, "c5": 100}[args.workload]
     import torch
 
     from paper_2304_10516_amd.dvnr import DVNR
+    if args.workload == "c4":
+        from paper_2304_10516_amd import presets
+        cfg = presets.get("c4")
+        res = {p: run_timeseries(torch, DVNR, cfg, p, args.timesteps, steps) for p in args.precisions.split(",")}
+        head_prec = "mixed" if "mixed" in res else next(iter(res))
+        head = res[head_prec]
+        out = {"metric": "train samples/s & decode voxels/s at fixed PSNR; BF16 batched vs FP32 plain",
+               "value": head["samples_per_s"], "unit": "samples/s", "n_gpus": 1, "steps": steps * args.timesteps,
+               "warmup": 5, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "bf16" if head_prec == "mixed" else "f32", "data": "synthetic",
+               "config": {"workload": f"in situ time series: {args.timesteps} timesteps of a 256^3 field of 16 "
+                                      "Gaussian blobs advected by a seeded divergence-free flow; per timestep "
+                                      f"{steps} warm-started steps of 2^18 samples; c2 model",
+                          "name": "c4", "timesteps": args.timesteps, "steps_per_timestep": steps},
+               "timestep_latency_ms": {p: r["latency_ms"] for p, r in res.items()},
+               "psnr_per_timestep_db": {p: r["psnr_per_t"] for p, r in res.items()}}
+        print(json.dumps(out), flush=True)
+        return
     cfg, blocks, vols, desc, host_vol = make_workload(args.workload, torch)
     if args.calibrate_copy:
         a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")

@@ -11,6 +11,8 @@ from .fields import (  # noqa: F401
     kolmogorov_field,
     kolmogorov_field_torch,
     advected_blobs_field,
+    advected_blob_trajectories,
+    advected_blobs_series_torch,
     cut_blocks,
     uneven_block_sizes,
     init_param_draws,

@@ -102,6 +102,69 @@ def kolmogorov_field_torch(shape, seed: int = 2, device="cuda"):
     return ((f - lo) / (hi - lo)).contiguous()
 
 
+def advected_blobs_series_torch(n: int = 256, n_steps: int = 40, n_blobs: int = 16, seed: int = 4, device="cuda"):
+    """Generator of the `advected_blobs_field` time series synthesized with torch on `device`.
+
+    Blob parameters and trajectories are the numpy ones (same seed and draw
+    order); each timestep's field is built with separable Gaussians in float32
+    on the device.  Yields float32 tensors (n, n, n), clipped to [0, 1] after
+    dividing by the sum of amplitudes.
+    """
+    import torch
+    traj, sigma, amp = advected_blob_trajectories(n, n_steps, n_blobs, seed)
+    c = torch.arange(n, device=device, dtype=torch.float32)
+    for t in range(n_steps):
+        f = torch.zeros((n, n, n), device=device, dtype=torch.float32)
+        for g in range(n_blobs):
+            cx, cy, cz = [float(v) for v in traj[t, g]]
+            s2 = float(2.0 * sigma[g] ** 2)
+            ds = []
+            for cc in (cz, cy, cx):
+                d = torch.abs(c - cc)
+                d = torch.minimum(d, n - d)
+                ds.append(torch.exp(-d * d / s2))
+            f += float(amp[g]) * ds[0][:, None, None] * ds[1][None, :, None] * ds[2][None, None, :]
+        yield torch.clamp(f / float(amp.sum()), 0.0, 1.0)
+
+
+def advected_blob_trajectories(n: int = 256, n_steps: int = 40, n_blobs: int = 16, seed: int = 4):
+    """Blob centers of every timestep [n_steps, n_blobs, 3] (voxels), sigma and amplitude.
+
+    Same draws and RK4 advection as `advected_blobs_field`."""
+    rng = np.random.default_rng(seed)
+    centers = rng.uniform(0.0, n, size=(n_blobs, 3))
+    sigma = rng.uniform(8.0, 16.0, size=n_blobs)
+    amp = rng.uniform(0.5, 1.0, size=n_blobs)
+    modes = []
+    while len(modes) < 4:
+        kv = rng.integers(-3, 4, size=3)
+        if 0 < np.linalg.norm(kv) <= 3:
+            modes.append(kv.astype(np.float64))
+    avec = rng.normal(size=(4, 3))
+    phs = rng.uniform(0.0, 2.0 * np.pi, size=4)
+
+    def vel(p):
+        u = np.zeros_like(p)
+        for kv, a, ph in zip(modes, avec, phs):
+            arg = 2.0 * np.pi * (p @ kv) / n + ph
+            grad = (2.0 * np.pi / n) * np.cos(arg)[:, None] * kv[None, :]
+            u += np.cross(grad, a[None, :])
+        return u
+
+    probe = rng.uniform(0.0, n, size=(4096, 3))
+    umax = np.abs(vel(probe)).max()
+    scale = 2.0 / umax if umax > 0 else 1.0
+    traj = np.empty((n_steps, n_blobs, 3))
+    for t in range(n_steps):
+        traj[t] = centers
+        k1 = scale * vel(centers)
+        k2 = scale * vel(centers + 0.5 * k1)
+        k3 = scale * vel(centers + 0.5 * k2)
+        k4 = scale * vel(centers + k3)
+        centers = np.mod(centers + (k1 + 2 * k2 + 2 * k3 + k4) / 6.0, n)
+    return traj, sigma, amp
+
+
 def advected_blobs_field(n: int = 256, n_steps: int = 40, n_blobs: int = 16, seed: int = 4, step: int = 0) -> np.ndarray:
     """One timestep of Gaussian blobs advected by a seeded divergence-free flow.
 

@@ -67,6 +67,7 @@ struct dvnr {
   int use_graph = 1;
   int xcd_map = 1;
   int mlp_cap = kMlpGrid;  // workgroups of the persistent MLP kernel (autotuned)
+  int decode_fused = 1;    // decode with the fused brick kernel (else encode + MLP over chunks)
   int apply_update = 1;
   // spatially ordered sampling and bin-privatized scatter of the coarse levels
   int spatial_sort = 0;
@@ -769,8 +770,16 @@ dvnr_status dvnr_decode(dvnr_t* h, int32_t block, float* out, void* stream) {
   if (block >= h->nb) return fail(DVNR_E_INVALID, "bad block");
   hipStream_t s = (hipStream_t)stream;
   int64_t out_off = 0;
+  const bool mixed = h->prec == Prec::MIXED;
   for (int b = b0; b < b1; ++b) {
     const int64_t nvox = owned_voxels(h->blocks[b]);
+    if (h->decode_fused) {
+      const void* table = mixed ? h->buf.work16 : h->buf.params;
+      HIPCHK(launch_decode_fused(h->prec, h->ld, h->md, h->d_meta(), h->d_range(), b, h->blocks[b].dims, table,
+                                 table, h->n_table, out + out_off, s));
+      out_off += nvox;
+      continue;
+    }
     for (int64_t c0 = 0; c0 < nvox; c0 += h->max_batch) {
       const int64_t cn = std::min(h->max_batch, nvox - c0);
       HIPCHK(launch_voxel_coords(h->d_meta(), b, c0, cn, h->d_coords(), s));
@@ -980,6 +989,8 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
     h->xcd_map = value ? 1 : 0;
   } else if (n == "apply_update") {
     h->apply_update = value ? 1 : 0;
+  } else if (n == "decode_fused") {
+    h->decode_fused = value ? 1 : 0;
   } else if (n == "spatial_sort") {
     h->spatial_sort = value ? 1 : 0;
   } else if (n == "priv_levels") {

@@ -139,6 +139,13 @@ hipError_t launch_mlp_simple_fwd(Prec p, const MlpDesc& md, int64_t n, const voi
 hipError_t launch_mlp_simple_bwd(Prec p, const MlpDesc& md, int64_t n, const void* feats, const void* w,
                                  const void* dout, void* dfeats, void* dw, hipStream_t s);
 
+// Fused decode of one block (voxel centers, encoding through LDS-staged vertex
+// boxes, MLP forward); table / wsrc point at element 0 of the parameter index
+// space (fp16 / bf16 working copy for mixed precision, fp32 masters otherwise).
+hipError_t launch_decode_fused(Prec p, const LevelDesc& ld, const MlpDesc& md, const BlockMeta* meta,
+                               const BlockRange* range, int block, const int32_t* dims, const void* table,
+                               const void* wsrc, int64_t n_table_params, float* out, hipStream_t s);
+
 hipError_t launch_voxel_coords(const BlockMeta* meta, int block, int64_t first, int64_t n, float* coords,
                                hipStream_t s);
 hipError_t launch_mse(const BlockMeta* meta, int block, const float* decoded, double* acc, hipStream_t s);

@@ -267,15 +267,34 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpDesc md, int F, const Bloc
       mySZ[k] = SZ(wave, k);
       mySI[k] = SI(wave, k);
     }
-    // this wave's 64 samples of the tile: passes of DWS samples, groups of 16
+    // this wave's 64 samples of the tile: 4 groups of 16, passes of DWS samples;
+    // the features and target of group k+1 are loaded while group k computes
+    constexpr int NG = 4;
+    float xr[8], yr;
+    auto load_group = [&](int k, float (&x)[8], float& y) {
+      const int sl = wave * 64 + k * 16 + c;
+      const bool ok = sl < tl.count;
+      const int64_t gi = base + sl;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int f = 8 * g + i;
+        x[i] = (ok && f < md.in_dim) ? load_feat(feat, plane, F, gi, f) : 0.0f;
+      }
+      y = ok ? target[gi] : 0.0f;
+    };
+    load_group(0, xr, yr);
 #pragma unroll 1
-    for (int p = 0; p < 64 / S::DWS; ++p) {
-#pragma unroll 1
-      for (int q = 0; q < S::GP; ++q) {
-        const int sl = wave * 64 + p * S::DWS + q * 16 + c;  // sample within the tile
+    for (int kg = 0; kg < NG; ++kg) {
+      const int q = kg % S::GP;
+      float xn[8], yn = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) xn[i] = 0.0f;
+      if (kg + 1 < NG) load_group(kg + 1, xn, yn);
+      {
+        const int sl = wave * 64 + kg * 16 + c;  // sample within the tile
         const bool valid = sl < tl.count;
         const int64_t gi = base + sl;
-        const int scol = q * 16 + c;                          // staging column
+        const int scol = q * 16 + c;              // staging column
         // ---- input features (B operand of layer 0) and their staging
         op_t xb[S::KS_IN];
 #pragma unroll
@@ -283,7 +302,7 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpDesc md, int F, const Bloc
 #pragma unroll
           for (int j = 0; j < TR::VPL; ++j) {
             const int f = 8 * g + s * TR::VPL + j;
-            const float x = (valid && f < md.in_dim) ? load_feat(feat, plane, F, gi, f) : 0.0f;
+            const float x = xr[s * TR::VPL + j];
             TR::put(xb[s], j, x);
             mySI[0][f * S::RS + scol] = (st_t)x;
           }
@@ -319,7 +338,7 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpDesc md, int F, const Bloc
         op += __shfl_xor(op, 16, 64);
         op += __shfl_xor(op, 32, 64);
         // ---- L2 loss, dL/do = 2 (o - y) / n_b
-        const float y = valid ? target[gi] : 0.0f;
+        const float y = yr;
         const float r = op - y;
         const float dO = valid ? 2.0f * r * inv_n : 0.0f;
         if (valid && g == 0) loss_acc += r * r * inv_n;
@@ -380,7 +399,11 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpDesc md, int F, const Bloc
             }
           }
         }
-      }  // groups of the pass
+      }  // group kg
+#pragma unroll
+      for (int i = 0; i < 8; ++i) xr[i] = xn[i];
+      yr = yn;
+      if (q != S::GP - 1) continue;
       __syncthreads();  // all waves' staging of this pass is complete
       // ---- weight gradients: this wave's output tiles over the 4 waves' staged samples
 #pragma unroll
@@ -400,7 +423,7 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpDesc md, int F, const Bloc
         }
       }
       __syncthreads();  // staging may be overwritten by the next pass
-    }  // passes
+    }  // groups
   }
   flush(cur_block);
 }

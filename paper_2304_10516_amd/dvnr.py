@@ -135,6 +135,10 @@ class DVNR:
         L.check(self.lib.dvnr_bind(self.h, C.byref(b)))
         L.check(self.lib.dvnr_prepare(self.h, _stream_ptr(stream)))
 
+    def prepare(self, stream=None):
+        """Recompute the per-block value ranges (after the bound voxels changed in place)."""
+        L.check(self.lib.dvnr_prepare(self.h, _stream_ptr(stream)))
+
     def ranges(self, stream=None):
         lo = (C.c_float * self.n_blocks)()
         hi = (C.c_float * self.n_blocks)()

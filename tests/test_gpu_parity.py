@@ -236,17 +236,21 @@ def test_adam_update_parity_c1():
 
 
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("mixed", 1e-2)])
-def test_decode_and_sample_parity(precision, tol):
-    say(f"decode / sample parity {precision}")
-    dims, ghost = (24, 20, 16), 1
+@pytest.mark.parametrize("fused,dims,cfg_name", [(1, (24, 20, 16), "c2"), (0, (24, 20, 16), "c2"),
+                                                 (1, (37, 9, 21), "c1")])
+def test_decode_and_sample_parity(precision, tol, fused, dims, cfg_name):
+    say(f"decode / sample parity {precision} fused={fused} dims={dims} {cfg_name}")
+    ghost = 1
     rng = np.random.default_rng(9)
     vol = rng.random((dims[2] + 2, dims[1] + 2, dims[0] + 2)).astype(np.float32)
-    lay = o.layout(*C2)
+    cfg = {"c1": C1, "c2": C2}[cfg_name]
+    lay = o.layout(*cfg)
     p = init_param_draws(lay.n_table_params, lay.mlp_shapes, seed=5).astype(np.float64)
     p[:lay.n_table_params] = rng.normal(size=lay.n_table_params) * 0.5
-    model = make(C2, [(dims, ghost)], precision=precision, max_batch=4096)
+    model = make(cfg, [(dims, ghost)], precision=precision, max_batch=4096)
     model.bind_volumes([dev(vol)])
     model.load_params([p])
+    model.set_option("decode_fused", fused)
     if precision == "mixed":  # the oracle evaluates the rounded working copy
         tab = p[:lay.n_table_params].astype(np.float16).astype(np.float64)
         w = torch.tensor(p[lay.n_table_params:]).to(torch.bfloat16).to(torch.float64).numpy()
@@ -369,6 +373,46 @@ def test_autotune_leaves_state_and_results_unchanged():
     L, g, _ = o.loss_and_grad(lay, p, x, o.normalized_targets(vol, (64, 64, 64), 0, x))
     assert abs(loss[0, 0].item() - L) <= 1e-2 * L
     assert normwise(model.block_grads(0).cpu().numpy(), g) <= 3e-2
+
+
+def test_graph_replay_matches_eager_steps():
+    """Steps replayed from the captured hipGraph (with eager work and host syncs
+    between replays) follow the same trajectory as eagerly launched steps."""
+    say("graph replay vs eager steps")
+    vol, lay, p0, _ = _setup_c1_block("fp32")
+    losses = {}
+    for use_graph in (0, 1):
+        model = make(C1, [((64, 64, 64), 0)], precision="fp32", max_batch=1 << 14, seed=77)
+        model.bind_volumes([dev(vol)])
+        model.load_params([p0.astype(np.float64)])
+        model.set_option("use_graph", use_graph)
+        s = torch.cuda.Stream()
+        out = []
+        with torch.cuda.stream(s):
+            for _ in range(4):
+                out.append(model.train(3, 4096, want_loss=True, stream=s)[:, 0].clone())
+                torch.mul(model.params, 1.0)  # unrelated eager work on the stream
+                s.synchronize()
+        losses[use_graph] = torch.cat(out).cpu().numpy()
+        model.sync(stream=s)
+    np.testing.assert_allclose(losses[1], losses[0], rtol=2e-4, atol=0)
+
+
+def test_nonfinite_loss_is_reported_at_sync():
+    """A NaN voxel in the input makes the loss non-finite; the library reports it
+    at dvnr_sync (every kernel still runs to completion)."""
+    say("non-finite loss reporting")
+    from paper_2304_10516_amd._lib import DVNR_E_NONFINITE, DvnrError
+    vol = gaussian_sum_field(16, seed=2)
+    vol[3] = np.nan  # a NaN plane: many samples interpolate it
+    model = make(C1, [((16, 16, 16), 0)], precision="fp32", max_batch=1024, seed=3)
+    model.bind_volumes([dev(vol)])
+    model.init_params(0)
+    model.train(2, 1024)
+    with pytest.raises(DvnrError) as ei:
+        model.sync()
+    assert ei.value.code == DVNR_E_NONFINITE
+    model.sync()  # the flag is cleared once reported
 
 
 def test_gradcheck_fp64_autograd():
