@@ -75,7 +75,7 @@ struct dvnr {
   int sort_B = 0, priv_L = 0, n_groups = 0;
   std::vector<Tile> hgroups;
   std::vector<int32_t> hgrange;
-  int64_t o_groups = 0, o_grange = 0, o_counts = 0, o_binstart = 0, max_groups = 0;
+  int64_t o_groups = 0, o_grange = 0, o_counts = 0, o_binstart = 0, o_totals = 0, max_groups = 0;
   // per-phase event timing (eager steps only): ring of kProfRing steps x 7 events
   static constexpr int kProfRing = 128;
   int profile = 0;
@@ -107,6 +107,7 @@ struct dvnr {
   int32_t* d_grange() const { return (int32_t*)(ws() + o_grange); }
   uint32_t* d_counts() const { return (uint32_t*)(ws() + o_counts); }
   int32_t* d_binstart() const { return (int32_t*)(ws() + o_binstart); }
+  uint32_t* d_totals() const { return (uint32_t*)(ws() + o_totals); }
   size_t pelem() const { return prec == Prec::F64 ? 8 : 4; }
 
   ~dvnr() {
@@ -272,6 +273,7 @@ dvnr_status dvnr_create(const dvnr_encoding* enc, const dvnr_mlp* mlp, const dvn
     h->o_grange = take(sizeof(int32_t) * 2 * n_blocks);
     h->o_counts = take(sizeof(uint32_t) * kMaxBins * h->max_groups);
     h->o_binstart = take(sizeof(int32_t) * (kMaxBins + 1) * n_blocks);
+    h->o_totals = take(sizeof(uint32_t) * kMaxBins * n_blocks);
     h->spatial_sort = (h->prec == Prec::MIXED) ? 1 : 0;
     h->ws_bytes = o;
     *out = h;
@@ -570,7 +572,8 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   PROF(0);
   if (sorted) {
     HIPCHK(launch_sorted_sample(h->d_groups(), h->n_groups, h->d_grange(), h->nb, h->sort_B, h->seed, h->d_ctr(),
-                                h->d_counts(), h->d_binstart(), h->d_meta(), h->d_range(), h->d_plan(), h->d_coords(),
+                                h->d_counts(), h->d_totals(), h->d_binstart(), h->d_meta(), h->d_range(), h->d_plan(),
+                                h->d_coords(),
                                 h->d_target(), s));
   } else {
     HIPCHK(launch_sample(h->d_meta(), h->d_range(), h->d_plan(), h->d_tiles(), h->n_tiles, 0, gen, h->seed,
@@ -594,7 +597,7 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   PROF(4);
   HIPCHK(launch_scatter(Prec::F32, h->ld, lp, h->enc.n_levels, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
                         h->d_coords(), h->d_dfeat(), F, h->max_batch * F, h->buf.grads, h->scatter_grouped,
-                        h->xcd_map, s));
+                        h->xcd_map, sorted ? 1 : 0, s));
   PROF(5);
   HIPCHK(launch_reduce_slots(h->d_slots(), h->slot_stride, h->d_ranges(), h->nb, h->n_mlp, h->n_table, h->stride,
                              Prec::F32, h->buf.grads, h->d_ring(), h->d_ctr(), 1, s));
@@ -826,7 +829,7 @@ dvnr_status dvnr_encode_backward(dvnr_t* h, int64_t n, const float* coords, cons
   const Prec gp = h->prec == Prec::F64 ? Prec::F64 : Prec::F32;
   HIPCHK(launch_scatter(gp, h->ld, 0, h->enc.n_levels, nullptr, nullptr, (int)n, 0, nullptr, coords, dfeats, LF,
                         h->enc.n_features, dtable,
-                        0, 0, (hipStream_t)stream));
+                        0, 0, 0, (hipStream_t)stream));
   return DVNR_OK;
 }
 

@@ -98,15 +98,15 @@ hipError_t launch_encode(Prec tp, int out_kind, const LevelDesc& ld, const Block
 // Encoding backward (scatter-add into gradient tables) of levels [l0, l1).
 hipError_t launch_scatter(Prec gp, const LevelDesc& ld, int l0, int l1, const BlockMeta* meta, const Tile* tiles,
                           int n_tiles, int direct_block, const BlockPlan* plan, const float* coords, const void* dfeat,
-                          int64_t ss, int64_t ls, void* grad, int grouped, int xcd_map, hipStream_t s);
+                          int64_t ss, int64_t ls, void* grad, int grouped, int xcd_map, int strided, hipStream_t s);
 
 // Spatially ordered sampler: Philox draws of every group (<= kSortGroup
 // samples of one block) stored grouped by B^3 spatial bins; bin_start
 // [n_blocks][kMaxBins + 1] receives each bin's first sample (within the block).
 hipError_t launch_sorted_sample(const Tile* groups, int n_groups, const int32_t* group_range, int n_blocks, int B,
-                                uint64_t seed, const Counters* ctr, uint32_t* counts, int32_t* bin_start,
-                                const BlockMeta* meta, const BlockRange* range, const BlockPlan* plan, float* coords,
-                                float* target, hipStream_t s);
+                                uint64_t seed, const Counters* ctr, uint32_t* counts, uint32_t* totals,
+                                int32_t* bin_start, const BlockMeta* meta, const BlockRange* range,
+                                const BlockPlan* plan, float* coords, float* target, hipStream_t s);
 // Bin-privatized encoding backward of levels [l0, l1) (needs the ordered sampler).
 hipError_t launch_scatter_priv(const LevelDesc& ld, int l0, int l1, int B, int n_blocks, const BlockMeta* meta,
                                const BlockPlan* plan, const int32_t* bin_start, const float* coords,

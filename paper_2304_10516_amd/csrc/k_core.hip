@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_scatter(LevelDesc ld, const BlockMeta* 
                                                  int direct_block, const BlockPlan* __restrict__ plan,
                                                  const float* __restrict__ coords, const DT* __restrict__ dfeat,
                                                  int64_t ss, int64_t ls, GT* __restrict__ grad, int xcd_map,
-                                                 int l0, int nl) {
+                                                 int l0, int nl, int strided) {
   int tile, l;
   if (!level_major_item(blockIdx.x, l0, nl, n_tiles, xcd_map, tile, l)) return;
   const int R = ld.R[l];
@@ -267,11 +267,23 @@ __global__ __launch_bounds__(256) void k_scatter(LevelDesc ld, const BlockMeta* 
     int count;
     int64_t base;
     int block;
+    // strided: tile t' of a block with n samples takes samples j * ceil(n/256) + t', so
+    // that the lanes of an instruction do not come from one spatial bin of an ordered
+    // sample buffer (neighbouring samples would hit the same entries and serialize)
+    int64_t stride = 0, first = 0, n_valid = 0;
     if (tiles) {
       const Tile tl = tiles[tile];
-      count = tl.count;
       block = tl.block;
-      base = plan[tl.block].sample_off + tl.start;
+      if (strided) {
+        n_valid = plan[tl.block].n;
+        stride = (n_valid + kTile - 1) / kTile;
+        first = tl.start / kTile;
+        base = plan[tl.block].sample_off;
+        count = kTile;
+      } else {
+        count = tl.count;
+        base = plan[tl.block].sample_off + tl.start;
+      }
     } else {
       base = (int64_t)tile * kTile;
       count = (int)min((int64_t)kTile, n_direct - base);
@@ -281,7 +293,12 @@ __global__ __launch_bounds__(256) void k_scatter(LevelDesc ld, const BlockMeta* 
     const int items = count * 4;
     for (int it = threadIdx.x / G; it < items; it += kTile / G) {
       const int j = it >> 2, yz = it & 3;
-      const int64_t gi = base + j;
+      int64_t si = j;
+      if (stride) {
+        si = (int64_t)j * stride + first;
+        if (si >= n_valid) continue;
+      }
+      const int64_t gi = base + si;
       const float x = coords[3 * gi + 0], y = coords[3 * gi + 1], z = coords[3 * gi + 2];
       int ix, iy, iz;
       float tx, ty, tz;
@@ -300,16 +317,17 @@ __global__ __launch_bounds__(256) void k_scatter(LevelDesc ld, const BlockMeta* 
 template <typename GT, typename DT, bool GROUPED>
 static hipError_t scat_dispatch(const LevelDesc& ld, int l0, int nl, const BlockMeta* meta, const Tile* tiles, int nt,
                                 int64_t n_direct, int direct_block, const BlockPlan* plan, const float* coords,
-                                const void* dfeat, int64_t ss, int64_t ls, void* grad, int xcd_map, hipStream_t s) {
+                                const void* dfeat, int64_t ss, int64_t ls, void* grad, int xcd_map, int strided,
+                                hipStream_t s) {
   const int grid = level_major_grid(nl, nt, xcd_map);
   if (grid <= 0 || nl <= 0) return hipSuccess;
   const DT* d = (const DT*)dfeat;
   GT* g = (GT*)grad;
   switch (ld.F) {
-    case 1: hipLaunchKernelGGL((k_scatter<GT, DT, 1, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map, l0, nl); break;
-    case 2: hipLaunchKernelGGL((k_scatter<GT, DT, 2, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map, l0, nl); break;
-    case 4: hipLaunchKernelGGL((k_scatter<GT, DT, 4, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map, l0, nl); break;
-    case 8: hipLaunchKernelGGL((k_scatter<GT, DT, 8, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map, l0, nl); break;
+    case 1: hipLaunchKernelGGL((k_scatter<GT, DT, 1, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map, l0, nl, strided); break;
+    case 2: hipLaunchKernelGGL((k_scatter<GT, DT, 2, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map, l0, nl, strided); break;
+    case 4: hipLaunchKernelGGL((k_scatter<GT, DT, 4, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map, l0, nl, strided); break;
+    case 8: hipLaunchKernelGGL((k_scatter<GT, DT, 8, GROUPED>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, nt, n_direct, direct_block, plan, coords, d, ss, ls, g, xcd_map, l0, nl, strided); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -317,19 +335,20 @@ static hipError_t scat_dispatch(const LevelDesc& ld, int l0, int nl, const Block
 
 hipError_t launch_scatter(Prec gp, const LevelDesc& ld, int l0, int l1, const BlockMeta* meta, const Tile* tiles,
                           int n_tiles, int direct_block, const BlockPlan* plan, const float* coords, const void* dfeat,
-                          int64_t ss, int64_t ls, void* grad, int grouped, int xcd_map, hipStream_t s) {
+                          int64_t ss, int64_t ls, void* grad, int grouped, int xcd_map, int strided, hipStream_t s) {
   int64_t n_direct = 0;
   int nt = n_tiles;
   if (!tiles) {
     n_direct = n_tiles;
     nt = (int)((n_direct + kTile - 1) / kTile);
+    strided = 0;
   }
   const int nl = l1 - l0;
   if (gp == Prec::F64)
-    return scat_dispatch<double, double, false>(ld, l0, nl, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, s);
+    return scat_dispatch<double, double, false>(ld, l0, nl, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, 0, s);
   if (grouped)
-    return scat_dispatch<float, float, true>(ld, l0, nl, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, s);
-  return scat_dispatch<float, float, false>(ld, l0, nl, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, s);
+    return scat_dispatch<float, float, true>(ld, l0, nl, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, strided, s);
+  return scat_dispatch<float, float, false>(ld, l0, nl, meta, tiles, nt, n_direct, direct_block, plan, coords, dfeat, ss, ls, grad, xcd_map, 0, s);
 }
 
 // ===========================================================================

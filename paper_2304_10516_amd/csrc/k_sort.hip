@@ -56,46 +56,36 @@ __global__ __launch_bounds__(256) void k_sort_count(const Tile* __restrict__ gro
   for (int i = threadIdx.x; i < nbins; i += blockDim.x) out[i] = hist[i];
 }
 
-// One workgroup per block; thread k owns bin k (nbins <= blockDim).  Groups of
-// block b are [g0, g1).
-__global__ __launch_bounds__(512) void k_sort_scan(const int32_t* __restrict__ group_range, int B,
-                                                   uint32_t* __restrict__ counts, int32_t* __restrict__ bin_start) {
-  __shared__ uint32_t tot[kMaxBins];
+// Exclusive prefix over the groups of each block, per bin, in place, and the
+// per-bin totals.  Workgroup (block b, chunk of 64 bins), 1024 threads: lane
+// k of the chunk's 64 bins, row r of 16 that owns a contiguous run of the
+// block's groups [g0, g1).  Pass 1 sums each row's run, the 16 row sums are
+// prefixed in LDS, pass 2 writes the running prefix.
+__global__ __launch_bounds__(1024) void k_sort_scan(const int32_t* __restrict__ group_range, int B,
+                                                    uint32_t* __restrict__ counts, uint32_t* __restrict__ totals) {
+  __shared__ uint32_t part[16][64];
   const int b = blockIdx.x;
   const int nbins = B * B * B;
+  const int k = blockIdx.y * 64 + threadIdx.x % 64;
+  const int r = threadIdx.x / 64;
   const int g0 = group_range[2 * b], g1 = group_range[2 * b + 1];
-  const int k = threadIdx.x;
-  uint32_t run = 0;
-  if (k < nbins) {
-    // exclusive prefix over the block's groups, loads batched 8 at a time
-    int g = g0;
-    for (; g + 8 <= g1; g += 8) {
-      uint32_t c[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) c[u] = counts[(int64_t)(g + u) * nbins + k];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        counts[(int64_t)(g + u) * nbins + k] = run;
-        run += c[u];
-      }
-    }
-    for (; g < g1; ++g) {
-      const uint32_t c = counts[(int64_t)g * nbins + k];
-      counts[(int64_t)g * nbins + k] = run;
-      run += c;
-    }
-  }
-  tot[k] = k < nbins ? run : 0u;
+  const int per = (g1 - g0 + 15) / 16;
+  const int ra = g0 + r * per, rb = min(g1, ra + per);
+  uint32_t sum = 0;
+  if (k < nbins)
+    for (int g = ra; g < rb; ++g) sum += counts[(int64_t)g * nbins + k];
+  part[r][threadIdx.x % 64] = sum;
   __syncthreads();
-  // exclusive scan of bin totals (Hillis-Steele on 512 entries)
-  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-    const uint32_t v = (k >= o) ? tot[k - o] : 0u;
-    __syncthreads();
-    tot[k] += v;
-    __syncthreads();
+  uint32_t base = 0;
+  for (int q = 0; q < r; ++q) base += part[q][threadIdx.x % 64];
+  if (k < nbins) {
+    for (int g = ra; g < rb; ++g) {
+      const uint32_t c = counts[(int64_t)g * nbins + k];
+      counts[(int64_t)g * nbins + k] = base;
+      base += c;
+    }
+    if (r == 15) totals[b * kMaxBins + k] = base;  // the last row ends with the bin total
   }
-  if (k < nbins) bin_start[b * (kMaxBins + 1) + k] = (int32_t)(tot[k] - run);
-  if (k == nbins - 1) bin_start[b * (kMaxBins + 1) + nbins] = (int32_t)tot[k];
 }
 
 __device__ __forceinline__ void cell_pos_s(float x, int n, int g, int N, int& i0, float& t) {
@@ -106,20 +96,47 @@ __device__ __forceinline__ void cell_pos_s(float x, int n, int g, int N, int& i0
   t = fminf(fmaxf(p - (float)i, 0.0f), 1.0f);
 }
 
-__global__ __launch_bounds__(256) void k_sort_place(const Tile* __restrict__ groups, int B, uint64_t seed,
-                                                    const Counters* __restrict__ ctr,
+// Bin starts are the exclusive scan of the block's bin totals; every
+// workgroup computes them in LDS, the block's first group also stores them
+// (bin_start[b][0..nbins], last = sample count) for the privatized scatter.
+__global__ __launch_bounds__(256) void k_sort_place(const Tile* __restrict__ groups, const int32_t* __restrict__ grange,
+                                                    int B, uint64_t seed, const Counters* __restrict__ ctr,
                                                     const uint32_t* __restrict__ prefix,
-                                                    const int32_t* __restrict__ bin_start,
+                                                    const uint32_t* __restrict__ totals,
+                                                    int32_t* __restrict__ bin_start,
                                                     const BlockMeta* __restrict__ meta,
                                                     const BlockRange* __restrict__ range,
                                                     const BlockPlan* __restrict__ plan, float* __restrict__ coords,
                                                     float* __restrict__ target) {
   __shared__ uint32_t cursor[kMaxBins];
+  __shared__ uint32_t scan[kMaxBins];
   const int nbins = B * B * B;
   const Tile gr = groups[blockIdx.x];
   const uint32_t* pre = prefix + (int64_t)blockIdx.x * nbins;
-  const int32_t* bs = bin_start + gr.block * (kMaxBins + 1);
-  for (int i = threadIdx.x; i < nbins; i += blockDim.x) cursor[i] = pre[i] + (uint32_t)bs[i];
+  const uint32_t* tot = totals + gr.block * kMaxBins;
+  // exclusive scan of the bin totals: each thread owns 2 consecutive bins
+  const int t = threadIdx.x;
+  const uint32_t a0 = 2 * t < nbins ? tot[2 * t] : 0u, a1 = 2 * t + 1 < nbins ? tot[2 * t + 1] : 0u;
+  scan[t] = a0 + a1;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const uint32_t v = t >= o ? scan[t - o] : 0u;
+    __syncthreads();
+    scan[t] += v;
+    __syncthreads();
+  }
+  const uint32_t ex = scan[t] - a0 - a1;  // start of bin 2t
+  const bool first = grange[2 * gr.block] == (int)blockIdx.x;
+  int32_t* bs = bin_start + gr.block * (kMaxBins + 1);
+  if (2 * t < nbins) {
+    cursor[2 * t] = ex + pre[2 * t];
+    if (first) bs[2 * t] = (int32_t)ex;
+  }
+  if (2 * t + 1 < nbins) {
+    cursor[2 * t + 1] = ex + a0 + pre[2 * t + 1];
+    if (first) bs[2 * t + 1] = (int32_t)(ex + a0);
+  }
+  if (first && t == 255) bs[nbins] = (int32_t)scan[255];
   __syncthreads();
   const uint32_t step = (uint32_t)ctr->step;
   const BlockMeta bm = meta[gr.block];
@@ -153,15 +170,17 @@ __global__ __launch_bounds__(256) void k_sort_place(const Tile* __restrict__ gro
 }
 
 hipError_t launch_sorted_sample(const Tile* groups, int n_groups, const int32_t* group_range, int n_blocks, int B,
-                                uint64_t seed, const Counters* ctr, uint32_t* counts, int32_t* bin_start,
-                                const BlockMeta* meta, const BlockRange* range, const BlockPlan* plan, float* coords,
-                                float* target, hipStream_t s) {
+                                uint64_t seed, const Counters* ctr, uint32_t* counts, uint32_t* totals,
+                                int32_t* bin_start, const BlockMeta* meta, const BlockRange* range,
+                                const BlockPlan* plan, float* coords, float* target, hipStream_t s) {
   if (n_groups <= 0) return hipSuccess;
   if (B < 1 || B * B * B > kMaxBins) return hipErrorInvalidValue;
+  const int nbins = B * B * B;
   hipLaunchKernelGGL(k_sort_count, dim3(n_groups), dim3(256), 0, s, groups, B, seed, ctr, counts);
-  hipLaunchKernelGGL(k_sort_scan, dim3(n_blocks), dim3(kMaxBins), 0, s, group_range, B, counts, bin_start);
-  hipLaunchKernelGGL(k_sort_place, dim3(n_groups), dim3(256), 0, s, groups, B, seed, ctr, counts, bin_start, meta,
-                     range, plan, coords, target);
+  hipLaunchKernelGGL(k_sort_scan, dim3(n_blocks, (nbins + 63) / 64), dim3(1024), 0, s, group_range, B, counts,
+                     totals);
+  hipLaunchKernelGGL(k_sort_place, dim3(n_groups), dim3(256), 0, s, groups, group_range, B, seed, ctr, counts,
+                     totals, bin_start, meta, range, plan, coords, target);
   return hipGetLastError();
 }
 
