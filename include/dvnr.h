@@ -6,9 +6,11 @@
  * independently of every other block (paper Sec. III-A, model parallelism).
  * Each INR maps a block-normalized position x in [0,1]^3 to a normalized
  * value (Eq. (1)); it is a multiresolution hash-grid encoding followed by a
- * small bias-free ReLU MLP (Sec. III).  Training draws uniform random
- * coordinates, fetches trilinearly interpolated ground truth from the block's
- * voxels, and takes Adam steps on an L2 loss (Sec. III-B, III-F).  Trained
+ * small bias-free ReLU MLP (Sec. III).  Training draws random coordinates
+ * (uniform, optionally mixed with boundary-centered half-normal samples,
+ * Sec. III-E), fetches trilinearly interpolated ground truth from the block's
+ * voxels, and takes Adam steps on an L2 or L1 loss (Sec. III-B, III-E,
+ * III-F).  Trained
  * models are queried at arbitrary coordinates or decoded back to the voxel
  * grid (Sec. III, on-demand inference and decoding).
  *
@@ -156,11 +158,13 @@ dvnr_status dvnr_params_updated(dvnr_t* h, void* stream);
  * moments and the step counter. */
 dvnr_status dvnr_reset_optimizer(dvnr_t* h, void* stream);
 
-/* n_steps optimizer steps.  Each step draws samples_per_step uniform
- * coordinates split over blocks in proportion to owned voxel counts
- * (largest remainder in units of 256), with Philox4x32-10 counter
- * (sample, step, block, 'DVNR') and key (seed lo, seed hi); then forward,
- * L2 loss (mean per block), backward and Adam.  loss_out: device float
+/* n_steps optimizer steps.  Each step draws samples_per_step coordinates
+ * split over blocks in proportion to owned voxel counts (largest remainder
+ * in units of 256).  Of a block's n samples, the first n - nb are uniform,
+ * Philox4x32-10 counter (sample, step, block, 'DVNR') and key (seed lo,
+ * seed hi); the last nb = floor(boundary_frac * n + 1/2) are boundary-centered
+ * (dvnr_set_loss; nb = 0 by default).  Then forward, the loss (mean per block;
+ * L2 by default), backward and Adam.  loss_out: device float
  * [n_steps][n_blocks] or NULL.  samples_per_step <= max_batch. */
 dvnr_status dvnr_train_steps(dvnr_t* h, int32_t n_steps, int64_t samples_per_step, float* loss_out,
                              void* stream);
@@ -240,6 +244,26 @@ dvnr_status dvnr_plan_info(const dvnr_t* h, int32_t* bins_per_axis, int32_t* pri
  * last dvnr_sync (DVNR_E_NONFINITE). */
 dvnr_status dvnr_sync(dvnr_t* h, void* stream);
 
+/* Loss and sampling distribution of training (Sec. III-E, Eq. (4)-(5)).
+ *  loss          : DVNR_LOSS_L2 (mean squared error, the default) or
+ *                  DVNR_LOSS_L1 (mean absolute error, dL/do = sign(o - y)/n
+ *                  with sign(0) = 0).
+ *  boundary_frac : lambda in [0, 1], the share of each block's samples drawn
+ *                  near the block faces (0 by default; the paper uses 0.15
+ *                  with the L1 loss).  The total per step is unchanged.
+ *  sigma         : spread in (0, 1] of the boundary samples (paper: 0.005).
+ *                  A boundary sample, Philox counter (sample, step, block,
+ *                  'DVNB'), output words u0..u3: face = floor(6 u3 / 2^32)
+ *                  (axis face/2, low side if face is even); distance to the
+ *                  face sigma sqrt(2) erfinv((u2 >> 8) 2^-24) (a half-normal
+ *                  quantile), clipped to 1; the two other coordinates, in
+ *                  increasing axis order, (u0 >> 8) 2^-24 and (u1 >> 8) 2^-24.
+ * Takes effect at the next training call.  DVNR_E_INVALID for values out of
+ * range. */
+#define DVNR_LOSS_L2 0
+#define DVNR_LOSS_L1 1
+dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double sigma);
+
 /* Options (runtime switches):
  *  "scatter_grouped" 0/1 : grouped-lane scatter (default 1 for mixed, 0 for fp32)
  *  "use_graph"       0/1 : capture one step in a hipGraph and replay it on a
@@ -251,6 +275,11 @@ dvnr_status dvnr_sync(dvnr_t* h, void* stream);
  *  "profile_phases"  0/1 : record HIP events between the phases of every
  *                          training step (steps then run without a graph);
  *                          read with dvnr_phase_times().
+ *  "spatial_sort"    0/1 : store each step's samples grouped by spatial bin
+ *                          (default 1 for mixed, 0 for fp32); enables the
+ *                          bin-privatized backward of the coarse levels
+ *  "priv_levels"     n   : privatize levels [0, n) (-1: chosen per plan)
+ *  "decode_fused"    0/1 : decode with the fused brick kernel (default 1)
  * Returns DVNR_E_INVALID for an unknown name. */
 dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value);
 

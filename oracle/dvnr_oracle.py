@@ -19,8 +19,10 @@ What it computes, per partition block (one implicit neural representation,
 * uniform sampling with a counter-based generator (Philox4x32-10, Salmon et
   al., SC'11) and trilinear ground-truth fetch in cell-centered convention with
   per-block min/max normalization (`training_coords`, `sample_volume`);
-* the L2 loss, the encoding backward (scatter-add), Adam with L2 weight decay
-  (Sec. III-F) (`train_step`, `adam`);
+* boundary-centered half-normal samples (Sec. III-E, Eq. (4)) mixed into a
+  step's batch (`boundary_coords`, `step_coords`);
+* the L2 or L1 loss (Sec. III-E, Eq. (5)), the encoding backward
+  (scatter-add), Adam with L2 weight decay (Sec. III-F) (`train_step`, `adam`);
 * decoding at voxel centers and PSNR over owned voxels (`decode`, `psnr`).
 
 Readings of points the paper leaves open are listed in the design notes and
@@ -324,6 +326,65 @@ def training_coords(seed: int, block: int, step: int, n: int, first: int = 0) ->
     return ((u[:, :3] >> 8).astype(np.float64) * 2.0 ** -24).astype(np.float32)
 
 
+BOUND_TAG = 0x44564E42  # fourth counter word of boundary-sample draws
+
+
+def boundary_count(n: int, frac: float) -> int:
+    """Boundary samples among a block's n samples of one step: lambda * n
+    rounded half up (Sec. III-E draws (1 - lambda) N uniform and lambda N
+    boundary samples, so that the step always trains on N samples)."""
+    return int(np.floor(frac * n + 0.5))
+
+
+def boundary_coords(seed: int, block: int, step: int, n: int, first: int, sigma: float) -> np.ndarray:
+    """Boundary-centered training coordinates (Sec. III-E, Eq. (4)).
+
+    Reading of the density: an equal-weight mixture over the six faces of the
+    unit cube; a sample picks a face, sits at a half-normal distance
+    abs(N(0, sigma^2)) from it along the face normal, and is uniform in the
+    two tangential coordinates.
+    Sample i (i = first .. first + n - 1) draws Philox4x32-10 with counter
+    (i, step, block, BOUND_TAG) and the seed as key.  Output words u0..u3:
+      face  = floor(u3 * 6 / 2^32)  (axis = face // 2, side = face % 2);
+      tangential coordinates, in increasing axis order: (u0 >> 8) 2^-24, (u1 >> 8) 2^-24;
+      distance d = sigma * sqrt(2) * erfinv(v), v = (u2 >> 8) 2^-24 (the half-normal
+      quantile of v), clipped to [0, 1];
+      normal coordinate d on the low face, 1 - d on the high face.
+    Returns float32 [n, 3]; the distance is evaluated in float64 and the
+    coordinate rounded to float32 once.
+    """
+    from scipy.special import erfinv
+
+    i = np.arange(first, first + n, dtype=np.uint64)
+    ctr = np.stack([i & np.uint64(MASK32), np.full_like(i, step & MASK32),
+                    np.full_like(i, block & MASK32), np.full_like(i, BOUND_TAG)], axis=1)
+    u = philox4x32_10(ctr, (seed & MASK32, (seed >> 32) & MASK32)).astype(np.uint64)
+    face = (u[:, 3] * np.uint64(6)) >> np.uint64(32)
+    axis, side = (face // 2).astype(np.int64), (face % 2).astype(np.int64)
+    tang = (u[:, :2] >> np.uint64(8)).astype(np.float64) * 2.0 ** -24
+    v = (u[:, 2] >> np.uint64(8)).astype(np.float64) * 2.0 ** -24
+    d = np.clip(sigma * np.sqrt(2.0) * erfinv(v), 0.0, 1.0)
+    x = np.empty((n, 3), dtype=np.float64)
+    rows = np.arange(n)
+    x[rows, axis] = np.where(side == 1, 1.0 - d, d)
+    t0 = np.where(axis == 0, 1, 0)          # first tangential axis
+    t1 = np.where(axis == 2, 1, 2)          # second tangential axis
+    x[rows, t0] = tang[:, 0]
+    x[rows, t1] = tang[:, 1]
+    return x.astype(np.float32)
+
+
+def step_coords(seed: int, block: int, step: int, n: int, n_boundary: int = 0, sigma: float = 0.005) -> np.ndarray:
+    """All n coordinates of one block at one step: samples 0 .. n - n_boundary - 1
+    uniform (`training_coords`), the remaining n_boundary boundary-centered
+    (`boundary_coords`).  Returns float32 [n, 3]."""
+    nu = n - n_boundary
+    x = training_coords(seed, block, step, nu)
+    if n_boundary == 0:
+        return x
+    return np.concatenate([x, boundary_coords(seed, block, step, n_boundary, nu, sigma)], axis=0)
+
+
 def block_value_range(vol: np.ndarray):
     """(vmin, vmax) over every stored voxel of a block, ghost layer included."""
     return float(np.min(vol)), float(np.max(vol))
@@ -407,10 +468,13 @@ def adam(params: np.ndarray, grad: np.ndarray, st: AdamState, opt: Optim) -> np.
     return th - opt.lr * mhat / (np.sqrt(vhat) + opt.eps)
 
 
-def loss_and_grad(lay: Layout, params: np.ndarray, x: np.ndarray, target: np.ndarray):
-    """L2 loss of one block, mean over its samples, and its gradient.
+def loss_and_grad(lay: Layout, params: np.ndarray, x: np.ndarray, target: np.ndarray, loss: str = "l2"):
+    """Loss of one block, mean over its samples, and its gradient.
 
-    L = (1/n) sum (o - y)^2, dL/do = 2 (o - y) / n.  Returns (L, grad vector, o).
+    loss "l2": L = (1/n) sum (o - y)^2, dL/do = 2 (o - y) / n.
+    loss "l1" (the unweighted L1 of Sec. III-E): L = (1/n) sum abs(o - y),
+    dL/do = sign(o - y) / n with sign(0) = 0.
+    Returns (L, grad vector, o).
     """
     y = encode(lay, params, x)
     W = mlp_weights(lay, params)
@@ -418,8 +482,14 @@ def loss_and_grad(lay: Layout, params: np.ndarray, x: np.ndarray, target: np.nda
     o = o[:, 0]
     n = o.shape[0]
     r = o - np.asarray(target, dtype=np.float64)
-    L = float(np.mean(r * r))
-    do = (2.0 / n) * r
+    if loss == "l2":
+        L = float(np.mean(r * r))
+        do = (2.0 / n) * r
+    elif loss == "l1":
+        L = float(np.mean(np.abs(r)))
+        do = np.sign(r) / n
+    else:
+        raise ValueError(loss)
     dy, dWs = mlp_backward(W, acts, do[:, None])
     g = np.empty(lay.n_params, dtype=np.float64)
     g[:lay.n_table_params] = encode_backward(lay, x, dy)
@@ -428,26 +498,29 @@ def loss_and_grad(lay: Layout, params: np.ndarray, x: np.ndarray, target: np.nda
     return L, g, o
 
 
-def train_step(lay: Layout, params, st: AdamState, opt: Optim, x, target):
-    """One iteration: forward, L2 loss, backward, Adam.  Returns (new params, loss)."""
-    L, g, _ = loss_and_grad(lay, params, x, target)
+def train_step(lay: Layout, params, st: AdamState, opt: Optim, x, target, loss: str = "l2"):
+    """One iteration: forward, loss, backward, Adam.  Returns (new params, loss)."""
+    L, g, _ = loss_and_grad(lay, params, x, target, loss)
     return adam(params, g, st, opt), L
 
 
 def train(lay: Layout, params0, vol, dims, ghost, n_steps: int, batch: int, seed: int,
-          opt: Optim, block: int = 0, coords_fn=None):
+          opt: Optim, block: int = 0, coords_fn=None, loss: str = "l2", boundary_frac: float = 0.0,
+          sigma: float = 0.005):
     """Train one block's INR for n_steps from params0.
 
-    Coordinates of step s are training_coords(seed, block, s, batch) unless
-    `coords_fn(s)` supplies them.  Returns (params, losses, adam state).
+    Coordinates of step s are step_coords(seed, block, s, batch,
+    boundary_count(batch, boundary_frac), sigma) unless `coords_fn(s)` supplies
+    them.  Returns (params, losses, adam state).
     """
     params = np.asarray(params0, dtype=np.float64).copy()
     st = adam_init(lay.n_params)
     losses = []
+    nbd = boundary_count(batch, boundary_frac)
     for s in range(n_steps):
-        x = coords_fn(s) if coords_fn is not None else training_coords(seed, block, s, batch)
+        x = coords_fn(s) if coords_fn is not None else step_coords(seed, block, s, batch, nbd, sigma)
         tgt = normalized_targets(vol, dims, ghost, x)
-        params, L = train_step(lay, params, st, opt, x, tgt)
+        params, L = train_step(lay, params, st, opt, x, tgt, loss)
         losses.append(L)
     return params, np.array(losses), st
 

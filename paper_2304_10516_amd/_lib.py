@@ -79,6 +79,7 @@ SIGNATURES = {
     "dvnr_debug_indices": [P, I32, I64, VP, VP, VP, VP],
     "dvnr_sync": [P, VP],
     "dvnr_set_option": [P, C.c_char_p, I64],
+    "dvnr_set_loss": [P, I32, C.c_double, C.c_double],
     "dvnr_phase_times": [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
     "dvnr_plan_info": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
     "dvnr_autotune": [P, I64, I32, C.POINTER(C.c_double), VP],

@@ -35,9 +35,38 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 
 constexpr uint32_t kCoordTag = 0x44564E52u;  // 'DVNR': fourth counter word of coordinate draws
 constexpr uint32_t kInitTag = 0x494E4954u;   // 'INIT': parameter initialization draws
+constexpr uint32_t kBoundTag = 0x44564E42u;  // 'DVNB': fourth counter word of boundary-sample draws
 
 // uniform in [0,1): top 24 bits scaled by 2^-24 (exact in float32)
 __device__ __forceinline__ float u24(uint32_t u) { return (float)(u >> 8) * 5.9604644775390625e-8f; }
+
+// Training coordinate of sample i of a block at one step.  Samples below
+// n_uni are uniform in [0,1)^3 (Philox words 0..2 of counter (i, step, block,
+// 'DVNR')).  The others are boundary-centered (Sec. III-E, Eq. (4)), read as
+// an equal mixture over the six cube faces: counter (i, step, block, 'DVNB');
+// face = floor(6 u3 / 2^32) picks axis face/2 and side face%2, the distance
+// to the face is the half-normal quantile sigma sqrt(2) erfinv(v) of
+// v = u24(u2) (clipped to 1), and the two tangential coordinates, in
+// increasing axis order, are u24(u0) and u24(u1).
+__device__ __forceinline__ void train_coord(uint32_t i, uint32_t step, uint32_t block, int n_uni,
+                                            float sigma_sqrt2, uint64_t seed, float& x, float& y, float& z) {
+  const bool bnd = (int)i >= n_uni;
+  const U4 u = philox4x32_10(U4{i, step, block, bnd ? kBoundTag : kCoordTag}, (uint32_t)seed, (uint32_t)(seed >> 32));
+  if (!bnd) {
+    x = u24(u.x);
+    y = u24(u.y);
+    z = u24(u.z);
+    return;
+  }
+  const uint32_t face = __umulhi(u.w, 6u);
+  const uint32_t axis = face >> 1;
+  const float d = fminf(sigma_sqrt2 * erfinvf(u24(u.z)), 1.0f);
+  const float nc = (face & 1u) ? 1.0f - d : d;
+  const float t0 = u24(u.x), t1 = u24(u.y);
+  x = axis == 0 ? nc : t0;
+  y = axis == 1 ? nc : (axis == 0 ? t0 : t1);
+  z = axis == 2 ? nc : t1;
+}
 
 // ---------------------------------------------------------------------------
 // Grid position on a level of R vertices per axis.  x is clamped to [0,1];
@@ -98,22 +127,24 @@ __device__ __forceinline__ uint32_t xcc_id() {
 }
 
 // Map a linear workgroup id of a level-major launch to (tile, level).  With
-// xcd_map, workgroups dispatched to XCD x (round-robin dispatch puts
-// workgroup w on XCD w % 8) work on levels l with l % 8 == x, so that each
-// XCD's L2 holds only its own levels' tables.  Any mapping is correct; this
-// one only improves locality.  Returns false for idle workgroups.
-// Levels handled by one launch are [l0, l0 + L).
+// xcd_map, the workgroups dispatched to one XCD (round-robin dispatch puts
+// workgroup w on XCD w % 8) take a contiguous run of the level-major work
+// list, so that each XCD's L2 holds only a few levels' tables.  Any mapping is
+// correct; this one only improves locality.  Returns false for idle
+// workgroups.  Levels handled by one launch are [l0, l0 + L).
 __device__ __forceinline__ bool level_major_item(int wg, int l0, int L, int n_tiles, int xcd_map, int& tile,
                                                  int& level) {
-  if (xcd_map && L >= 8) {
-    const int lp = (L + 7) / 8;
+  if (xcd_map) {
+    // work items (level, tile) in level-major order; XCD x (workgroups w with
+    // w mod 8 == x) takes the contiguous eighth [x per, (x + 1) per), so each
+    // XCD's L2 holds the tables of about L/8 + 1 levels, never all L
+    const int per = (int)(((int64_t)L * n_tiles + 7) / 8);
     const int x = wg & 7, r = wg >> 3;
-    const int slot = r % lp;
-    tile = r / lp;
-    level = x + 8 * slot;
-    const bool ok = level < L && tile < n_tiles;
-    level += l0;
-    return ok;
+    const int64_t k = (int64_t)x * per + r;
+    if (r >= per || k >= (int64_t)L * n_tiles) return false;
+    level = l0 + (int)(k / n_tiles);
+    tile = (int)(k % n_tiles);
+    return true;
   }
   level = l0 + wg % L;
   tile = wg / L;
@@ -121,7 +152,7 @@ __device__ __forceinline__ bool level_major_item(int wg, int l0, int L, int n_ti
 }
 
 __host__ __device__ inline int level_major_grid(int L, int n_tiles, int xcd_map) {
-  if (xcd_map && L >= 8) return 8 * ((L + 7) / 8) * n_tiles;
+  if (xcd_map) return 8 * (int)(((int64_t)L * n_tiles + 7) / 8);
   return L * n_tiles;
 }
 

@@ -64,11 +64,16 @@ struct dvnr {
 
   int64_t host_step = 0;  // mirror of the device step counter
   int scatter_grouped = 0;
+  int scatter_strided = 1;  // direct scatter over ordered samples: spread a tile over the block's bins
   int use_graph = 1;
   int xcd_map = 1;
   int mlp_cap = kMlpGrid;  // workgroups of the persistent MLP kernel (autotuned)
   int decode_fused = 1;    // decode with the fused brick kernel (else encode + MLP over chunks)
   int apply_update = 1;
+  // loss (Sec. III-E): 0 L2, 1 L1; fraction and spread of boundary-centered samples
+  int loss_l1 = 0;
+  double bnd_frac = 0.0, bnd_sigma = 0.005;
+  SampleDist dist() const { return SampleDist{(float)(bnd_sigma * 1.4142135623730951), 0}; }
   // spatially ordered sampling and bin-privatized scatter of the coarse levels
   int spatial_sort = 0;
   int priv_levels = -1;  // -1: chosen per plan
@@ -444,6 +449,9 @@ static std::vector<int64_t> apportion(const dvnr_t* h, int64_t total) {
 }
 
 // Build and upload a training plan for the given per-block sample counts.
+// Boundary samples among n: boundary_frac * n rounded half up.
+static int64_t boundary_count(int64_t n, double frac) { return (int64_t)std::floor(frac * (double)n + 0.5); }
+
 static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_t s) {
   int64_t total = 0;
   for (auto v : n) total += v;
@@ -456,6 +464,8 @@ static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_
     h->hplan[b].sample_off = off;
     h->hplan[b].n = (int32_t)n[b];
     h->hplan[b].inv_n = n[b] > 0 ? (float)(1.0 / (double)n[b]) : 0.0f;
+    h->hplan[b].n_uni = (int32_t)(n[b] - boundary_count(n[b], h->bnd_frac));
+    h->hplan[b].pad = 0;
     for (int64_t st = 0; st < n[b]; st += kTile) {
       if (first_tile[b] < 0) first_tile[b] = (int)h->htiles.size();
       last_tile[b] = (int)h->htiles.size();
@@ -499,14 +509,17 @@ static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_
   int B = 1;
   while (B < 8 && (int64_t)(B + 1) * (B + 1) * (B + 1) * 512 <= min_n) ++B;
   h->sort_B = B;
-  // Privatize the longest prefix of levels whose per-bin cell box fits the
-  // LDS budget (8192 cells) and whose corner hits per step are dense enough
-  // (>= 0.3 per grid vertex) for per-entry sums to save atomics.
+  // Privatize the longest prefix of levels whose per-bin box fits the LDS
+  // budget (cells and vertex accumulators) and whose corner hits per step are
+  // dense enough (>= 0.3 per grid vertex) for per-entry sums to save atomics.
   int pl = 0;
   for (int l = 0; l < h->enc.n_levels; ++l) {
     const double R = (double)h->ld.R[l];
     const double side = (R - 1.0) / (double)B + 1.5;  // cells per axis of a bin's box, with slack
-    if (side * side * side > 8192.0 || 8.0 * (double)min_n < 0.3 * R * R * R) break;
+    const double F = (double)h->enc.n_features;
+    if (side * side * side > kPrivCells || (side + 1.0) * (side + 1.0) * (side + 1.0) * F > kPrivVertFloats ||
+        8.0 * (double)min_n < 0.3 * R * R * R)
+      break;
     pl = l + 1;
   }
   h->priv_L = h->priv_levels >= 0 ? std::min(h->priv_levels, h->enc.n_levels) : pl;
@@ -571,13 +584,14 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   const bool sorted = gen && h->spatial_sort && h->n_groups > 0;
   PROF(0);
   if (sorted) {
-    HIPCHK(launch_sorted_sample(h->d_groups(), h->n_groups, h->d_grange(), h->nb, h->sort_B, h->seed, h->d_ctr(),
+    HIPCHK(launch_sorted_sample(h->d_groups(), h->n_groups, h->d_grange(), h->nb, h->sort_B, h->seed, h->dist(),
+                                h->d_ctr(),
                                 h->d_counts(), h->d_totals(), h->d_binstart(), h->d_meta(), h->d_range(), h->d_plan(),
                                 h->d_coords(),
                                 h->d_target(), s));
   } else {
     HIPCHK(launch_sample(h->d_meta(), h->d_range(), h->d_plan(), h->d_tiles(), h->n_tiles, 0, gen, h->seed,
-                         h->d_ctr(), -1, h->d_coords(), h->d_target(), s));
+                         h->dist(), h->d_ctr(), -1, h->d_coords(), h->d_target(), s));
   }
   PROF(1);
   const void* table = mixed ? h->buf.work16 : h->buf.params;
@@ -588,16 +602,16 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
                            : (const void*)((const float*)h->buf.params + h->n_table);
   HIPCHK(launch_mlp_train(h->prec, h->md, h->ld, h->d_meta(), h->d_plan(), h->d_tiles(), h->n_tiles, h->d_feat(),
                           h->d_target(), wsrc, h->d_dfeat(), h->max_batch, h->d_slots(), h->slot_stride, h->mlp_grid,
-                          s));
+                          h->loss_l1, s));
   PROF(3);
   const int lp = sorted ? h->priv_L : 0;
   if (lp > 0)
     HIPCHK(launch_scatter_priv(h->ld, 0, lp, h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(),
-                               h->d_coords(), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, s));
+                               h->d_coords(), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, h->xcd_map, s));
   PROF(4);
   HIPCHK(launch_scatter(Prec::F32, h->ld, lp, h->enc.n_levels, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
                         h->d_coords(), h->d_dfeat(), F, h->max_batch * F, h->buf.grads, h->scatter_grouped,
-                        h->xcd_map, sorted ? 1 : 0, s));
+                        h->xcd_map, sorted ? h->scatter_strided : 0, s));
   PROF(5);
   HIPCHK(launch_reduce_slots(h->d_slots(), h->slot_stride, h->d_ranges(), h->nb, h->n_mlp, h->n_table, h->stride,
                              Prec::F32, h->buf.grads, h->d_ring(), h->d_ctr(), 1, s));
@@ -728,7 +742,9 @@ dvnr_status dvnr_draw_training_samples(dvnr_t* h, int32_t block, int64_t step, i
   if (block < 0 || block >= h->nb) return fail(DVNR_E_INVALID, "bad block");
   if (n < 0 || n >= ((int64_t)1 << 31) || step < 0 || !coords || !target) return fail(DVNR_E_INVALID, "bad arguments");
   if (n == 0) return DVNR_OK;
-  HIPCHK(launch_sample(h->d_meta(), h->d_range(), nullptr, nullptr, (int)n, block, 1, h->seed, h->d_ctr(), step,
+  SampleDist d = h->dist();
+  d.direct_n_uni = (int32_t)(n - boundary_count(n, h->bnd_frac));
+  HIPCHK(launch_sample(h->d_meta(), h->d_range(), nullptr, nullptr, (int)n, block, 1, h->seed, d, h->d_ctr(), step,
                        coords, target, (hipStream_t)stream));
   return DVNR_OK;
 }
@@ -988,6 +1004,8 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
     h->scatter_grouped = value ? 1 : 0;
   } else if (n == "use_graph") {
     h->use_graph = value ? 1 : 0;
+  } else if (n == "scatter_strided") {
+    h->scatter_strided = value ? 1 : 0;
   } else if (n == "xcd_map") {
     h->xcd_map = value ? 1 : 0;
   } else if (n == "apply_update") {
@@ -1004,6 +1022,22 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
   } else {
     return fail(DVNR_E_INVALID, "unknown option " + n);
   }
+  if (h->graph) {
+    (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double sigma) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (loss != DVNR_LOSS_L2 && loss != DVNR_LOSS_L1) return fail(DVNR_E_INVALID, "unknown loss");
+  if (!(boundary_frac >= 0.0 && boundary_frac <= 1.0)) return fail(DVNR_E_INVALID, "boundary_frac must be in [0, 1]");
+  if (!(sigma > 0.0 && sigma <= 1.0)) return fail(DVNR_E_INVALID, "sigma must be in (0, 1]");
+  h->loss_l1 = loss == DVNR_LOSS_L1 ? 1 : 0;
+  h->bnd_frac = boundary_frac;
+  h->bnd_sigma = sigma;
+  h->plan_total = -1;  // per-block boundary counts live in the plan
   if (h->graph) {
     (void)hipGraphExecDestroy(h->graph);
     h->graph = nullptr;

@@ -13,6 +13,8 @@ constexpr int kMlpGrid = 256;     // workgroups of the persistent MLP kernel (on
 constexpr int kLossRing = 1024;   // steps of per-block loss history kept on the device
 constexpr int kMaxBins = 512;     // spatial bins per block (B^3, B <= 8) of the ordered sampler
 constexpr int kSortGroup = 1024;  // samples per counting-sort group
+constexpr int kPrivCells = 4096;  // cells of a bin's box in the privatized backward (LDS counters)
+constexpr int kPrivVertFloats = 8192;  // box vertices x features accumulated in LDS
 
 // Level table, passed by value to kernels.
 struct LevelDesc {
@@ -49,6 +51,14 @@ struct BlockPlan {
   int64_t sample_off;
   int32_t n;
   float inv_n;                 // 1/n (0 when n == 0)
+  int32_t n_uni;               // samples [0, n_uni) uniform, [n_uni, n) boundary-centered
+  int32_t pad;
+};
+
+// Sampling distribution of a step (boundary loss of Sec. III-E).
+struct SampleDist {
+  float sigma_sqrt2;           // sigma * sqrt(2): half-normal quantile scale of boundary samples
+  int32_t direct_n_uni;        // n_uni of the block of a direct-mode draw
 };
 
 struct Tile {
@@ -84,7 +94,7 @@ hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
 // Direct mode when tiles == nullptr: n_tiles is then the sample count of block
 // direct_block, written to coords/target [0, n).
 hipError_t launch_sample(const BlockMeta* meta, const BlockRange* range, const BlockPlan* plan, const Tile* tiles,
-                         int n_tiles, int direct_block, int gen, uint64_t seed, const Counters* ctr,
+                         int n_tiles, int direct_block, int gen, uint64_t seed, SampleDist dist, const Counters* ctr,
                          int64_t step_override, float* coords, float* target, hipStream_t s);
 
 // Encoding forward.  Output element (sample i, level l, feature f) goes to
@@ -104,20 +114,20 @@ hipError_t launch_scatter(Prec gp, const LevelDesc& ld, int l0, int l1, const Bl
 // samples of one block) stored grouped by B^3 spatial bins; bin_start
 // [n_blocks][kMaxBins + 1] receives each bin's first sample (within the block).
 hipError_t launch_sorted_sample(const Tile* groups, int n_groups, const int32_t* group_range, int n_blocks, int B,
-                                uint64_t seed, const Counters* ctr, uint32_t* counts, uint32_t* totals,
+                                uint64_t seed, SampleDist dist, const Counters* ctr, uint32_t* counts, uint32_t* totals,
                                 int32_t* bin_start, const BlockMeta* meta, const BlockRange* range,
                                 const BlockPlan* plan, float* coords, float* target, hipStream_t s);
 // Bin-privatized encoding backward of levels [l0, l1) (needs the ordered sampler).
 hipError_t launch_scatter_priv(const LevelDesc& ld, int l0, int l1, int B, int n_blocks, const BlockMeta* meta,
                                const BlockPlan* plan, const int32_t* bin_start, const float* coords,
-                               const float* dfeat, int64_t ls, float* grad, hipStream_t s);
+                               const float* dfeat, int64_t ls, float* grad, int xcd_map, hipStream_t s);
 
 // MLP training pass (forward, L2 loss, backward) on MFMA; writes dfeat
 // (level-major f32) and per-wave dW/loss partials into slots.
 hipError_t launch_mlp_train(Prec p, const MlpDesc& md, const LevelDesc& ld, const BlockMeta* meta,
                             const BlockPlan* plan, const Tile* tiles, int n_tiles, const void* feat,
                             const float* target, const void* weights_src, float* dfeat, int64_t plane,
-                            float* slots, int64_t slot_stride, int grid, hipStream_t s);
+                            float* slots, int64_t slot_stride, int grid, int loss_l1, hipStream_t s);
 // MLP inference: out[i] = INR output de-normalized with the block range.
 hipError_t launch_mlp_infer(Prec p, const MlpDesc& md, const LevelDesc& ld, const BlockMeta* meta,
                             const BlockRange* range, const BlockPlan* plan, const Tile* tiles, int n_tiles,

@@ -58,7 +58,8 @@ __global__ __launch_bounds__(256) void k_sample(const BlockMeta* __restrict__ me
                                                 const BlockRange* __restrict__ range,
                                                 const BlockPlan* __restrict__ plan, const Tile* __restrict__ tiles,
                                                 int64_t n_direct, int direct_block, int gen, uint64_t seed,
-                                                const Counters* __restrict__ ctr, int64_t step_override,
+                                                SampleDist dist, const Counters* __restrict__ ctr,
+                                                int64_t step_override,
                                                 float* __restrict__ coords, float* __restrict__ target) {
   Tile tl;
   int64_t gi;
@@ -77,11 +78,8 @@ __global__ __launch_bounds__(256) void k_sample(const BlockMeta* __restrict__ me
   float x, y, z;
   if (gen) {
     const uint32_t step = (uint32_t)(step_override >= 0 ? step_override : ctr->step);
-    const U4 u = philox4x32_10(U4{(uint32_t)(tl.start + j), step, (uint32_t)b, kCoordTag}, (uint32_t)seed,
-                               (uint32_t)(seed >> 32));
-    x = u24(u.x);
-    y = u24(u.y);
-    z = u24(u.z);
+    const int n_uni = tiles ? plan[b].n_uni : dist.direct_n_uni;
+    train_coord((uint32_t)(tl.start + j), step, (uint32_t)b, n_uni, dist.sigma_sqrt2, seed, x, y, z);
     coords[3 * gi + 0] = x;
     coords[3 * gi + 1] = y;
     coords[3 * gi + 2] = z;
@@ -112,7 +110,7 @@ __global__ __launch_bounds__(256) void k_sample(const BlockMeta* __restrict__ me
 }
 
 hipError_t launch_sample(const BlockMeta* meta, const BlockRange* range, const BlockPlan* plan, const Tile* tiles,
-                         int n_tiles, int direct_block, int gen, uint64_t seed, const Counters* ctr,
+                         int n_tiles, int direct_block, int gen, uint64_t seed, SampleDist dist, const Counters* ctr,
                          int64_t step_override, float* coords, float* target, hipStream_t s) {
   int64_t n_direct = 0;
   int nt = n_tiles;
@@ -122,7 +120,7 @@ hipError_t launch_sample(const BlockMeta* meta, const BlockRange* range, const B
   }
   if (nt <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_sample, dim3(nt), dim3(kTile), 0, s, meta, range, plan, tiles, n_direct, direct_block, gen,
-                     seed, ctr, step_override, coords, target);
+                     seed, dist, ctr, step_override, coords, target);
   return hipGetLastError();
 }
 

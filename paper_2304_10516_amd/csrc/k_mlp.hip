@@ -1,4 +1,5 @@
-// Fused MLP forward + L2 loss + backward of the DVNR network on MFMA (gfx950),
+// Fused MLP forward + loss (L2, or the L1 of the boundary loss) + backward of
+// the DVNR network on MFMA (gfx950),
 // and the simple thread-per-sample MLP used by the autograd building blocks.
 //
 // Network (paper Sec. III): bias-free, ReLU after every hidden layer, linear
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpDesc md, int F, const Bloc
                                                    const FT* __restrict__ feat, const float* __restrict__ target,
                                                    const WSRC* __restrict__ wsrc_all, float* __restrict__ dfeat,
                                                    int64_t plane, float* __restrict__ slots, int64_t slot_stride,
-                                                   int64_t n_table_params) {
+                                                   int64_t n_table_params, int l1) {
   using S = MlpShape<TR, W, NH>;
   using op_t = typename TR::op_t;
   using st_t = typename TR::st_t;
@@ -337,11 +338,12 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpDesc md, int F, const Bloc
           for (int i = 0; i < 4; ++i) op += wout[16 * m + 4 * g + i] * h[NH - 1][m][i];
         op += __shfl_xor(op, 16, 64);
         op += __shfl_xor(op, 32, 64);
-        // ---- L2 loss, dL/do = 2 (o - y) / n_b
+        // ---- loss: L2, dL/do = 2 (o - y) / n_b; L1, dL/do = sign(o - y) / n_b
         const float y = yr;
         const float r = op - y;
-        const float dO = valid ? 2.0f * r * inv_n : 0.0f;
-        if (valid && g == 0) loss_acc += r * r * inv_n;
+        const float sg = r > 0.0f ? inv_n : (r < 0.0f ? -inv_n : 0.0f);
+        const float dO = valid ? (l1 ? sg : 2.0f * r * inv_n) : 0.0f;
+        if (valid && g == 0) loss_acc += l1 ? fabsf(r) * inv_n : r * r * inv_n;
         // ---- backward through the output layer
         f32x4 dz[S::MT];
 #pragma unroll
@@ -524,14 +526,14 @@ static size_t infer_smem() {
 template <class TR, int W, int NH, typename FT, typename WSRC>
 static hipError_t run_train(const MlpDesc& md, int F, const BlockMeta* meta, const BlockPlan* plan, const Tile* tiles,
                             int n_tiles, const void* feat, const float* target, const void* wsrc, float* dfeat,
-                            int64_t plane, float* slots, int64_t slot_stride, int grid, int64_t n_table,
+                            int64_t plane, float* slots, int64_t slot_stride, int grid, int64_t n_table, int l1,
                             hipStream_t s) {
   const size_t sm = train_smem<TR, W, NH>();
   auto kern = k_mlp_train<TR, W, NH, FT, WSRC>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), sm, s, md, F, meta, plan, tiles, n_tiles, (const FT*)feat, target,
-                     (const WSRC*)wsrc, dfeat, plane, slots, slot_stride, n_table);
+                     (const WSRC*)wsrc, dfeat, plane, slots, slot_stride, n_table, l1);
   return hipGetLastError();
 }
 
@@ -556,7 +558,7 @@ static hipError_t run_infer(const MlpDesc& md, int F, const BlockMeta* meta, con
 hipError_t launch_mlp_train(Prec p, const MlpDesc& md, const LevelDesc& ld, const BlockMeta* meta,
                             const BlockPlan* plan, const Tile* tiles, int n_tiles, const void* feat,
                             const float* target, const void* weights_src, float* dfeat, int64_t plane,
-                            float* slots, int64_t slot_stride, int grid, hipStream_t s) {
+                            float* slots, int64_t slot_stride, int grid, int loss_l1, hipStream_t s) {
   // weights_src points at the MLP weights of block 0 (element n_table_params);
   // the kernel adds each block's parameter offset.
 #define X(WW, NN)                                                                                                   \
@@ -564,9 +566,9 @@ hipError_t launch_mlp_train(Prec p, const MlpDesc& md, const LevelDesc& ld, cons
     if (p == Prec::MIXED)                                                                                           \
       return run_train<TrBF16, WW, NN, __bf16, __bf16>(md, ld.F, meta, plan, tiles, n_tiles, feat, target,          \
                                                         weights_src, dfeat, plane, slots, slot_stride, grid,        \
-                                                        (int64_t)0, s);                                             \
+                                                        (int64_t)0, loss_l1, s);                                           \
     return run_train<TrF32, WW, NN, float, float>(md, ld.F, meta, plan, tiles, n_tiles, feat, target, weights_src, \
-                                                   dfeat, plane, slots, slot_stride, grid, (int64_t)0, s);          \
+                                                   dfeat, plane, slots, slot_stride, grid, (int64_t)0, loss_l1, s); \
   }
   DVNR_MLP_SHAPES(X)
 #undef X

@@ -21,24 +21,29 @@
 
 namespace dvnrk {
 
+__device__ __forceinline__ int bin_1d(float x, int B) { return min((int)(x * (float)B), B - 1); }
+
 __device__ __forceinline__ int bin_of(float x, float y, float z, int B) {
-  const int bx = min((int)(x * (float)B), B - 1);
-  const int by = min((int)(y * (float)B), B - 1);
-  const int bz = min((int)(z * (float)B), B - 1);
-  return bx + B * (by + B * bz);
+  return bin_1d(x, B) + B * (bin_1d(y, B) + B * bin_1d(z, B));
 }
 
-__device__ __forceinline__ void draw_coords(const Tile& gr, int i_in_block, uint32_t step, uint64_t seed, float& x,
-                                            float& y, float& z) {
-  const U4 u = philox4x32_10(U4{(uint32_t)i_in_block, step, (uint32_t)gr.block, kCoordTag}, (uint32_t)seed,
-                             (uint32_t)(seed >> 32));
-  x = u24(u.x);
-  y = u24(u.y);
-  z = u24(u.z);
+// Smallest and largest float32 x in [0, 1] that bin_1d puts in bin k (bin_1d
+// is monotone in x; k / B rounded is within an ulp of the boundary).
+__device__ __forceinline__ void bin_x_range(int k, int B, float& lo, float& hi) {
+  lo = (float)k / (float)B;
+  for (int it = 0; it < 4 && lo > 0.0f && bin_1d(nextafterf(lo, -1.0f), B) >= k; ++it) lo = nextafterf(lo, -1.0f);
+  for (int it = 0; it < 4 && bin_1d(lo, B) < k; ++it) lo = nextafterf(lo, 2.0f);
+  hi = 1.0f;
+  if (k < B - 1) {
+    hi = (float)(k + 1) / (float)B;
+    for (int it = 0; it < 4 && bin_1d(hi, B) > k; ++it) hi = nextafterf(hi, -1.0f);
+    for (int it = 0; it < 4 && hi < 1.0f && bin_1d(nextafterf(hi, 2.0f), B) <= k; ++it) hi = nextafterf(hi, 2.0f);
+  }
 }
 
 // groups: Tile entries with count <= kSortGroup samples of one block.
 __global__ __launch_bounds__(256) void k_sort_count(const Tile* __restrict__ groups, int B, uint64_t seed,
+                                                    SampleDist dist, const BlockPlan* __restrict__ plan,
                                                     const Counters* __restrict__ ctr, uint32_t* __restrict__ counts) {
   __shared__ uint32_t hist[kMaxBins];
   const int nbins = B * B * B;
@@ -46,9 +51,10 @@ __global__ __launch_bounds__(256) void k_sort_count(const Tile* __restrict__ gro
   __syncthreads();
   const Tile gr = groups[blockIdx.x];
   const uint32_t step = (uint32_t)ctr->step;
+  const int n_uni = plan[gr.block].n_uni;
   for (int j = threadIdx.x; j < gr.count; j += blockDim.x) {
     float x, y, z;
-    draw_coords(gr, gr.start + j, step, seed, x, y, z);
+    train_coord((uint32_t)(gr.start + j), step, (uint32_t)gr.block, n_uni, dist.sigma_sqrt2, seed, x, y, z);
     atomicAdd(&hist[bin_of(x, y, z, B)], 1u);
   }
   __syncthreads();
@@ -100,7 +106,8 @@ __device__ __forceinline__ void cell_pos_s(float x, int n, int g, int N, int& i0
 // workgroup computes them in LDS, the block's first group also stores them
 // (bin_start[b][0..nbins], last = sample count) for the privatized scatter.
 __global__ __launch_bounds__(256) void k_sort_place(const Tile* __restrict__ groups, const int32_t* __restrict__ grange,
-                                                    int B, uint64_t seed, const Counters* __restrict__ ctr,
+                                                    int B, uint64_t seed, SampleDist dist,
+                                                    const Counters* __restrict__ ctr,
                                                     const uint32_t* __restrict__ prefix,
                                                     const uint32_t* __restrict__ totals,
                                                     int32_t* __restrict__ bin_start,
@@ -142,11 +149,12 @@ __global__ __launch_bounds__(256) void k_sort_place(const Tile* __restrict__ gro
   const BlockMeta bm = meta[gr.block];
   const BlockRange br = range[gr.block];
   const int64_t base = plan[gr.block].sample_off;
+  const int n_uni = plan[gr.block].n_uni;
   const int g = bm.ghost;
   const int NX = bm.dims[0] + 2 * g, NY = bm.dims[1] + 2 * g, NZ = bm.dims[2] + 2 * g;
   for (int j = threadIdx.x; j < gr.count; j += blockDim.x) {
     float x, y, z;
-    draw_coords(gr, gr.start + j, step, seed, x, y, z);
+    train_coord((uint32_t)(gr.start + j), step, (uint32_t)gr.block, n_uni, dist.sigma_sqrt2, seed, x, y, z);
     const uint32_t dst = atomicAdd(&cursor[bin_of(x, y, z, B)], 1u);
     const int64_t gi = base + dst;
     coords[3 * gi + 0] = x;
@@ -170,57 +178,59 @@ __global__ __launch_bounds__(256) void k_sort_place(const Tile* __restrict__ gro
 }
 
 hipError_t launch_sorted_sample(const Tile* groups, int n_groups, const int32_t* group_range, int n_blocks, int B,
-                                uint64_t seed, const Counters* ctr, uint32_t* counts, uint32_t* totals,
+                                uint64_t seed, SampleDist dist, const Counters* ctr, uint32_t* counts, uint32_t* totals,
                                 int32_t* bin_start, const BlockMeta* meta, const BlockRange* range,
                                 const BlockPlan* plan, float* coords, float* target, hipStream_t s) {
   if (n_groups <= 0) return hipSuccess;
   if (B < 1 || B * B * B > kMaxBins) return hipErrorInvalidValue;
   const int nbins = B * B * B;
-  hipLaunchKernelGGL(k_sort_count, dim3(n_groups), dim3(256), 0, s, groups, B, seed, ctr, counts);
+  hipLaunchKernelGGL(k_sort_count, dim3(n_groups), dim3(256), 0, s, groups, B, seed, dist, plan, ctr, counts);
   hipLaunchKernelGGL(k_sort_scan, dim3(n_blocks, (nbins + 63) / 64), dim3(1024), 0, s, group_range, B, counts,
                      totals);
-  hipLaunchKernelGGL(k_sort_place, dim3(n_groups), dim3(256), 0, s, groups, group_range, B, seed, ctr, counts,
+  hipLaunchKernelGGL(k_sort_place, dim3(n_groups), dim3(256), 0, s, groups, group_range, B, seed, dist, ctr, counts,
                      totals, bin_start, meta, range, plan, coords, target);
   return hipGetLastError();
 }
 
 // ===========================================================================
 // Bin-privatized encoding backward for levels [l0, l1).  One workgroup per
-// (block, bin, level), in gather form:
+// (block, bin, level):
 //   1. the cell box touched by the bin's samples (min/max of cell origins);
 //   2. a counting sort of the samples by cell inside the box (one integer LDS
 //      atomic per sample) that stores each sample's fractions t and dL/dy in
-//      cell order;
-//   3. one lane per (box vertex, feature) sums w_c * dy over the samples of
-//      the up to 8 cells that have the vertex as a corner (no float atomics),
-//      and adds the sum to the table gradient with one global atomic; lanes
-//      walk vertices x fastest, so an atomic instruction covers contiguous
-//      entries (dense) or a few aligned segments (hashed, x prime 1).
-// A bin whose cell box exceeds the LDS budget falls back to grouped direct
-// atomics.  Samples beyond kPrivRecs per bin are processed in chunks.
+//      cell order (chunks of kPrivRecs samples);
+//   3. cell pass: the lanes of a cell (1..8, more when the box has few cells)
+//      sum w_c * dy over the cell's samples for its 8 corners and F features
+//      in registers, then add them to an LDS accumulator of the box vertices
+//      (8 F LDS atomics per cell and lane instead of per sample);
+//   4. vertex pass: one global atomic per nonzero (box vertex, feature) sum;
+//      lanes walk vertices x fastest, so an atomic instruction covers
+//      contiguous entries (dense levels) or a few aligned segments (hashed
+//      levels, whose x prime is 1).
+// A bin whose box exceeds the LDS budget falls back to grouped direct atomics.
 // ===========================================================================
-constexpr int kPrivCells = 8192;  // cells of the box (int counters / starts)
 constexpr int kPrivRecs = 1024;   // samples per chunk held in LDS
 
 template <int F>
-__global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int nlev, int B,
+__global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int nlev, int B, int n_blocks,
                                                       const BlockMeta* __restrict__ meta,
                                                       const BlockPlan* __restrict__ plan,
                                                       const int32_t* __restrict__ bin_start,
                                                       const float* __restrict__ coords,
                                                       const float* __restrict__ dfeat, int64_t ls,
-                                                      float* __restrict__ grad) {
+                                                      float* __restrict__ grad, int xcd_map) {
   __shared__ int cstart[kPrivCells + 1];
+  __shared__ float vacc[kPrivVertFloats];
   __shared__ float4 rt[kPrivRecs];       // tx, ty, tz of each placed sample
   __shared__ float rd[kPrivRecs * F];    // dL/dy of each placed sample
   __shared__ int part[256];
-  __shared__ int box[6];
   constexpr int PER = kPrivRecs / 256;   // samples per thread in a chunk
   const int nbins = B * B * B;
-  const int wg = blockIdx.x;
-  const int l = l0 + wg % nlev;
-  const int bin = (wg / nlev) % nbins;
-  const int b = wg / (nlev * nbins);
+  int unit, l;  // unit = block * nbins + bin
+  if (!level_major_item(blockIdx.x, l0, nlev, n_blocks * nbins, xcd_map, unit, l)) return;
+  const int bin = unit % nbins;
+  const int b = unit / nbins;
+  if (plan[b].n == 0) return;  // no sample this step: its bin starts were not rewritten
   const int32_t* bs = bin_start + b * (kMaxBins + 1);
   const int s0 = bs[bin], s1 = bs[bin + 1];
   if (s0 >= s1) return;
@@ -230,43 +240,28 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
   const int dense = ld.dense[l];
   float* g = grad + meta[b].param_off + (int64_t)ld.off[l] * F;
   const int tid = threadIdx.x;
-  // ---- 1. cell box of the bin's samples
-  int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
-  for (int j = s0 + tid; j < s1; j += 256) {
-    const int64_t gi = base + j;
+  // ---- 1. cell box of the bin: cell origins of its extreme coordinates (grid_pos
+  // and bin_1d are both monotone in x, so every sample of the bin lies inside)
+  int bo[3], bn[3];
+  {
+    const int bc[3] = {bin % B, (bin / B) % B, bin / (B * B)};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      int i0;
-      float t;
-      grid_pos(coords[3 * gi + a], sc, R, i0, t);
-      lo[a] = min(lo[a], i0);
-      hi[a] = max(hi[a], i0);
+      float xl, xh, t;
+      bin_x_range(bc[a], B, xl, xh);
+      int il, ih;
+      grid_pos(xl, sc, R, il, t);
+      grid_pos(xh, sc, R, ih, t);
+      bo[a] = il;
+      bn[a] = ih - il + 1;
     }
   }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      lo[a] = min(lo[a], __shfl_xor(lo[a], o, 64));
-      hi[a] = max(hi[a], __shfl_xor(hi[a], o, 64));
-    }
-  }
-  if (tid == 0)
-    for (int a = 0; a < 3; ++a) {
-      box[a] = 1 << 30;
-      box[3 + a] = -1;
-    }
-  __syncthreads();
-  if ((tid & 63) == 0)
-    for (int a = 0; a < 3; ++a) {
-      atomicMin(&box[a], lo[a]);
-      atomicMax(&box[3 + a], hi[a]);
-    }
-  __syncthreads();
-  const int bx0 = box[0], by0 = box[1], bz0 = box[2];
-  const int cx_n = box[3] - bx0 + 1, cy_n = box[4] - by0 + 1, cz_n = box[5] - bz0 + 1;  // cells per axis
+  const int bx0 = bo[0], by0 = bo[1], bz0 = bo[2];
+  const int cx_n = bn[0], cy_n = bn[1], cz_n = bn[2];  // cells per axis
+  const int vx_n = cx_n + 1, vy_n = cy_n + 1, vz_n = cz_n + 1;                           // vertices per axis
   const int64_t C = (int64_t)cx_n * cy_n * cz_n;
-  if (C > kPrivCells) {
+  const int64_t NV = (int64_t)vx_n * vy_n * vz_n;
+  if (C > kPrivCells || NV * F > kPrivVertFloats) {
     // box too large for LDS: grouped direct atomics (2F lanes per x-neighbour pair)
     constexpr int G = 2 * F;
     const int q = tid % G;
@@ -287,11 +282,12 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
     }
     return;
   }
-  const int vx_n = cx_n + 1, vy_n = cy_n + 1, vz_n = cz_n + 1;  // vertices per axis
-  const int NV = vx_n * vy_n * vz_n;
+  const int nc = (int)C, nvf = (int)NV * F;
+  for (int i = tid; i < nvf; i += 256) vacc[i] = 0.0f;
+  const int sub = nc >= 256 ? 1 : min(8, 256 / nc);  // lanes per cell in the cell pass
   for (int c0 = s0; c0 < s1; c0 += kPrivRecs) {
     const int cn = min(kPrivRecs, s1 - c0);
-    for (int i = tid; i <= C; i += 256) cstart[i] = 0;
+    for (int i = tid; i <= nc; i += 256) cstart[i] = 0;
     __syncthreads();
     // ---- 2a. cell of each sample and its rank within the cell
     int mcell[PER], mrank[PER];
@@ -307,15 +303,29 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
         for (int a = 0; a < 3; ++a) grid_pos(coords[3 * gi + a], sc, R, i0[a], mt[u][a]);
 #pragma unroll
         for (int f = 0; f < F; ++f) md[u][f] = dfeat[(int64_t)l * ls + gi * F + f];
-        mcell[u] = (i0[0] - bx0) + cx_n * ((i0[1] - by0) + cy_n * (i0[2] - bz0));
-        mrank[u] = atomicAdd(&cstart[mcell[u]], 1);
+        const int lx = i0[0] - bx0, ly = i0[1] - by0, lz = i0[2] - bz0;
+        if ((unsigned)lx < (unsigned)cx_n && (unsigned)ly < (unsigned)cy_n && (unsigned)lz < (unsigned)cz_n) {
+          mcell[u] = lx + cx_n * (ly + cy_n * lz);
+          mrank[u] = atomicAdd(&cstart[mcell[u]], 1);
+        } else {
+          // outside the bin's box (not expected; kept for safety): direct atomics
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int kx = k & 1, ky = (k >> 1) & 1, kz = k >> 2;
+            const uint32_t e = corner_index(dense, R, ld.T_mask, i0[0] + kx, i0[1] + ky, i0[2] + kz);
+            const float w = (kx ? mt[u][0] : 1.0f - mt[u][0]) * (ky ? mt[u][1] : 1.0f - mt[u][1]) *
+                            (kz ? mt[u][2] : 1.0f - mt[u][2]);
+#pragma unroll
+            for (int f = 0; f < F; ++f) unsafeAtomicAdd(&g[(int64_t)e * F + f], w * md[u][f]);
+          }
+        }
       }
     }
     __syncthreads();
-    // ---- 2b. exclusive scan of the C cell counts (contiguous chunk per thread)
+    // ---- 2b. exclusive scan of the cell counts (contiguous chunk per thread)
     {
-      const int chunk = (int)((C + 255) / 256);
-      const int a0 = tid * chunk, a1 = min((int)C, a0 + chunk);
+      const int chunk = (nc + 255) / 256;
+      const int a0 = tid * chunk, a1 = min(nc, a0 + chunk);
       int run = 0;
       for (int i = a0; i < a1; ++i) run += cstart[i];
       part[tid] = run;
@@ -332,7 +342,7 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
         cstart[i] = acc;
         acc += c;
       }
-      if (tid == 255) cstart[C] = part[255];
+      if (tid == 255) cstart[nc] = part[255];
       __syncthreads();
     }
     // ---- 2c. place the samples in cell order
@@ -346,47 +356,63 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
       }
     }
     __syncthreads();
-    // ---- 3. gather per (vertex, feature), x fastest, and one atomic per touched entry
-    for (int e = tid; e < NV * F; e += 256) {
-      const int v = e / F, f = e % F;
-      const int lx = v % vx_n, ly = (v / vx_n) % vy_n, lz = v / (vx_n * vy_n);
-      float acc = 0.0f;
-      bool touched = false;
+    // ---- 3. cell pass: corner sums in registers, one LDS atomic per (corner, feature)
+    for (int q = tid; q < nc * sub; q += 256) {
+      const int c = q / sub, s = q - c * sub;
+      const int p1 = cstart[c + 1];
+      int p = cstart[c] + s;
+      if (p >= p1) continue;
+      float acc[8][F];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int ccx = k & 1, ccy = (k >> 1) & 1, ccz = (k >> 2) & 1;  // corner of the cell
-        const int x = lx - ccx, y = ly - ccy, z = lz - ccz;                 // the cell
-        if (x < 0 || y < 0 || z < 0 || x >= cx_n || y >= cy_n || z >= cz_n) continue;
-        const int cell = x + cx_n * (y + cy_n * z);
-        const int p0 = cstart[cell], p1 = cstart[cell + 1];
-        for (int p = p0; p < p1; ++p) {
-          const float4 t = rt[p];
-          const float w = (ccx ? t.x : 1.0f - t.x) * (ccy ? t.y : 1.0f - t.y) * (ccz ? t.z : 1.0f - t.z);
-          acc += w * rd[p * F + f];
-          touched = true;
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int f = 0; f < F; ++f) acc[k][f] = 0.0f;
+      for (; p < p1; p += sub) {
+        const float4 t = rt[p];
+        float d[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) d[f] = rd[p * F + f];
+        const float wx[2] = {1.0f - t.x, t.x}, wy[2] = {1.0f - t.y, t.y}, wz[2] = {1.0f - t.z, t.z};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const float w = wx[k & 1] * wy[(k >> 1) & 1] * wz[k >> 2];
+#pragma unroll
+          for (int f = 0; f < F; ++f) acc[k][f] += w * d[f];
         }
       }
-      if (touched) {
-        const uint32_t ent = corner_index(dense, R, ld.T_mask, (uint32_t)(bx0 + lx), (uint32_t)(by0 + ly),
-                                          (uint32_t)(bz0 + lz));
-        unsafeAtomicAdd(&g[(int64_t)ent * F + f], acc);
+      const int lx = c % cx_n, ly = (c / cx_n) % cy_n, lz = c / (cx_n * cy_n);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int v = (lx + (k & 1)) + vx_n * ((ly + ((k >> 1) & 1)) + vy_n * (lz + (k >> 2)));
+#pragma unroll
+        for (int f = 0; f < F; ++f) atomicAdd(&vacc[v * F + f], acc[k][f]);
       }
     }
     __syncthreads();
+  }
+  // ---- 4. vertex pass, x fastest: one global atomic per nonzero sum
+  for (int e = tid; e < nvf; e += 256) {
+    const float acc = vacc[e];
+    if (acc == 0.0f) continue;
+    const int v = e / F, f = e - v * F;
+    const int lx = v % vx_n, ly = (v / vx_n) % vy_n, lz = v / (vx_n * vy_n);
+    const uint32_t ent = corner_index(dense, R, ld.T_mask, (uint32_t)(bx0 + lx), (uint32_t)(by0 + ly),
+                                      (uint32_t)(bz0 + lz));
+    unsafeAtomicAdd(&g[(int64_t)ent * F + f], acc);
   }
 }
 
 hipError_t launch_scatter_priv(const LevelDesc& ld, int l0, int l1, int B, int n_blocks, const BlockMeta* meta,
                                const BlockPlan* plan, const int32_t* bin_start, const float* coords,
-                               const float* dfeat, int64_t ls, float* grad, hipStream_t s) {
+                               const float* dfeat, int64_t ls, float* grad, int xcd_map, hipStream_t s) {
   const int nlev = l1 - l0;
   if (nlev <= 0) return hipSuccess;
-  const int grid = n_blocks * B * B * B * nlev;
+  const int grid = level_major_grid(nlev, n_blocks * B * B * B, xcd_map);
   switch (ld.F) {
-    case 1: hipLaunchKernelGGL(k_scatter_priv<1>, dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, meta, plan, bin_start, coords, dfeat, ls, grad); break;
-    case 2: hipLaunchKernelGGL(k_scatter_priv<2>, dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, meta, plan, bin_start, coords, dfeat, ls, grad); break;
-    case 4: hipLaunchKernelGGL(k_scatter_priv<4>, dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, meta, plan, bin_start, coords, dfeat, ls, grad); break;
-    case 8: hipLaunchKernelGGL(k_scatter_priv<8>, dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, meta, plan, bin_start, coords, dfeat, ls, grad); break;
+    case 1: hipLaunchKernelGGL(k_scatter_priv<1>, dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, n_blocks, meta, plan, bin_start, coords, dfeat, ls, grad, xcd_map); break;
+    case 2: hipLaunchKernelGGL(k_scatter_priv<2>, dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, n_blocks, meta, plan, bin_start, coords, dfeat, ls, grad, xcd_map); break;
+    case 4: hipLaunchKernelGGL(k_scatter_priv<4>, dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, n_blocks, meta, plan, bin_start, coords, dfeat, ls, grad, xcd_map); break;
+    case 8: hipLaunchKernelGGL(k_scatter_priv<8>, dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, n_blocks, meta, plan, bin_start, coords, dfeat, ls, grad, xcd_map); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

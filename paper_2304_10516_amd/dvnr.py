@@ -148,6 +148,15 @@ class DVNR:
     def set_option(self, name: str, value: int):
         L.check(self.lib.dvnr_set_option(self.h, name.encode(), int(value)))
 
+    LOSSES = {"l2": 0, "l1": 1}
+
+    def set_loss(self, loss: str = "l2", boundary_frac: float = 0.0, sigma: float = 0.005):
+        """Training loss ("l2" or "l1") and the share / spread of
+        boundary-centered samples (Sec. III-E; the paper uses l1, 0.15, 0.005)."""
+        if loss not in self.LOSSES:
+            raise ValueError(f"unknown loss {loss!r}")
+        L.check(self.lib.dvnr_set_loss(self.h, self.LOSSES[loss], float(boundary_frac), float(sigma)))
+
     # -- parameters ---------------------------------------------------------------
     def block_params(self, b: int) -> torch.Tensor:
         """View of block b's parameters (tables then weights, canonical layout)."""

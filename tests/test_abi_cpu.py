@@ -119,3 +119,20 @@ def test_fp64_handle_rejects_training():
     lib, code, h = _make(o.Encoding(3, 2, 6, 2, 2.0), o.MLP(1, 16), precision="fp64")
     assert code == 0
     lib.dvnr_destroy(h)
+
+
+def test_set_loss_validates_arguments():
+    lib, code, h = _make(o.Encoding(4, 2, 12, 4, 2.0), o.MLP(1, 16))
+    assert code == 0
+    lib.dvnr_set_loss.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double]
+    try:
+        assert lib.dvnr_set_loss(h, 1, 0.15, 0.005) == 0
+        assert lib.dvnr_set_loss(h, 0, 0.0, 0.005) == 0
+        assert lib.dvnr_set_loss(h, 2, 0.15, 0.005) == 1       # unknown loss
+        assert lib.dvnr_set_loss(h, 1, -0.1, 0.005) == 1       # fraction out of [0, 1]
+        assert lib.dvnr_set_loss(h, 1, 1.5, 0.005) == 1
+        assert lib.dvnr_set_loss(h, 1, float("nan"), 0.005) == 1
+        assert lib.dvnr_set_loss(h, 1, 0.15, 0.0) == 1         # sigma must be positive
+        assert lib.dvnr_set_loss(h, 1, 0.15, 2.0) == 1
+    finally:
+        lib.dvnr_destroy(h)

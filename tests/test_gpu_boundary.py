@@ -1,0 +1,171 @@
+"""GPU parity of the boundary loss (Sec. III-E) against the float64 oracle.
+
+* boundary-centered training samples: uniform prefix bit-exact, boundary
+  coordinates within 1e-6 (the half-normal quantile is evaluated in float32 on
+  the GPU and in float64 in the oracle), targets at those coordinates;
+* one-step L1 gradients with a boundary share of 0.15 (unordered and
+  spatially ordered samplers) within the fp32 bar;
+* end-to-end L1 + boundary training on the 64^3 configuration within 0.3 dB
+  of the oracle-trained model;
+* the property the paper reports: on two neighbouring blocks, the boundary
+  term raises the accuracy of both INRs on their shared face.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from fixtures import cut_blocks, gaussian_sum_field, init_param_draws, kolmogorov_field
+from oracle import dvnr_oracle as o
+
+pytestmark = pytest.mark.gpu
+
+C1 = (o.Encoding(4, 2, 12, 4, 2.0), o.MLP(1, 16))
+LAM, SIGMA = 0.15, 0.005
+
+
+def say(msg):
+    print(f"[gpu-boundary] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def normwise(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def make(cfg, blocks, precision="fp32", max_batch=1 << 14, seed=0):
+    from paper_2304_10516_amd.dvnr import DVNR, EncodingCfg, MlpCfg, OptimCfg
+    enc, mlp = cfg
+    e = EncodingCfg(enc.n_levels, enc.n_features, enc.log2_table_size, enc.base_resolution,
+                    enc.per_level_scale, enc.finest_resolution)
+    return DVNR(e, MlpCfg(mlp.n_hidden_layers, mlp.width), blocks, OptimCfg(lr=1e-2), precision=precision,
+                max_batch=max_batch, seed=seed)
+
+
+def dev(x, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+@pytest.mark.parametrize("dims,ghost", [((16, 16, 16), 0), ((13, 9, 11), 1)])
+def test_boundary_samples_match_oracle(dims, ghost):
+    say(f"boundary samples dims={dims} ghost={ghost}")
+    rng = np.random.default_rng(sum(dims) + 1)
+    vol = rng.random((dims[2] + 2 * ghost, dims[1] + 2 * ghost, dims[0] + 2 * ghost)).astype(np.float32)
+    model = make(C1, [(dims, ghost)], seed=4321)
+    model.bind_volumes([dev(vol)])
+    model.set_loss("l1", LAM, SIGMA)
+    n = 5000
+    nb = o.boundary_count(n, LAM)
+    for step in (0, 3):
+        c, t = model.draw_training_samples(0, step, n)
+        torch.cuda.synchronize()
+        c, t = c.cpu().numpy(), t.cpu().numpy()
+        rc = o.step_coords(4321, 0, step, n, nb, SIGMA)
+        assert np.array_equal(c[:n - nb], rc[:n - nb])
+        assert np.max(np.abs(c[n - nb:].astype(np.float64) - rc[n - nb:])) <= 1e-6
+        # the face each boundary sample sits next to is an integer decision: identical
+        near = lambda x: np.argmin(np.concatenate([x, 1.0 - x], axis=1), axis=1)
+        assert np.array_equal(near(c[n - nb:]), near(rc[n - nb:]))
+        rt = o.normalized_targets(vol, dims, ghost, rc)
+        assert np.max(np.abs(t[:n - nb] - rt[:n - nb])) <= 2e-6
+        assert np.max(np.abs(t[n - nb:] - rt[n - nb:])) <= 1e-4
+
+
+def _c1_setup(precision):
+    vol = gaussian_sum_field(64, seed=1)
+    lay = o.layout(*C1)
+    p0 = init_param_draws(lay.n_table_params, lay.mlp_shapes, seed=0)
+    model = make(C1, [((64, 64, 64), 0)], precision=precision, seed=77)
+    model.bind_volumes([dev(vol)])
+    return vol, lay, p0, model
+
+
+@pytest.mark.parametrize("sort", [0, 1])
+def test_l1_boundary_gradient_parity(sort):
+    say(f"one-step L1 + boundary gradient fp32 spatial_sort={sort}")
+    vol, lay, p0, model = _c1_setup("fp32")
+    p = p0.astype(np.float64).copy()
+    p[:lay.n_table_params] *= 1e3
+    model.load_params([p])
+    model.set_loss("l1", LAM, SIGMA)
+    model.set_option("spatial_sort", sort)
+    model.set_option("apply_update", 0)
+    model.set_option("use_graph", 0)
+    loss = model.train(1, 4096, want_loss=True)
+    torch.cuda.synchronize()
+    pref = model.block_params(0).cpu().numpy().astype(np.float64)
+    x = o.step_coords(77, 0, 0, 4096, o.boundary_count(4096, LAM), SIGMA)
+    tgt = o.normalized_targets(vol, (64, 64, 64), 0, x)
+    L, g, out = o.loss_and_grad(lay, pref, x, tgt, "l1")
+    # a sample whose residual is within float32 reach of 0 may take the other sign
+    close = np.sum(np.abs(out - tgt) < 1e-5)
+    say(f"loss gpu {loss[0, 0].item():.6e} oracle {L:.6e}; near-zero residuals {close}")
+    gg = model.block_grads(0).cpu().numpy()
+    nt = lay.n_table_params
+    assert abs(loss[0, 0].item() - L) <= 1e-5 * L
+    tol = 1e-5 + 2.0 * close / 4096
+    assert normwise(gg[:nt], g[:nt]) <= tol, "table gradient"
+    assert normwise(gg[nt:], g[nt:]) <= tol, "weight gradient"
+
+
+def test_l1_boundary_end_to_end_psnr_within_03db():
+    say("c1 end-to-end L1 + boundary training fp32")
+    vol, lay, p0, model = _c1_setup("fp32")
+    model.load_params([p0.astype(np.float64)])
+    model.set_loss("l1", LAM, SIGMA)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        loss = model.train(200, 4096, want_loss=True, stream=s)
+        dec = model.decode(0, stream=s)
+        sse, cnt = model.squared_error(0, dec, stream=s)
+    s.synchronize()
+    gpu_psnr = o.psnr(sse, cnt)
+    params, _, _ = o.train(lay, p0, vol, (64, 64, 64), 0, n_steps=200, batch=4096, seed=77, opt=o.Optim(lr=1e-2),
+                           loss="l1", boundary_frac=LAM, sigma=SIGMA)
+    vmin, vmax = o.block_value_range(vol)
+    ref_psnr = o.psnr(*o.squared_error(o.decode(lay, params, (64, 64, 64), vmin, vmax), vol))
+    say(f"psnr gpu {gpu_psnr:.3f} oracle {ref_psnr:.3f}")
+    assert abs(gpu_psnr - ref_psnr) <= 0.3
+    lg = loss.cpu().numpy()[:, 0]
+    assert np.all(np.isfinite(lg)) and lg[-10:].mean() < lg[:10].mean()
+    model.sync(stream=s)
+
+
+def _face_psnr(model, field, blocks, steps, lam, batch):
+    """Mean PSNR of the two INRs on their shared face x = 32 against the field."""
+    model.set_loss("l1", lam, SIGMA)
+    model.train(steps, batch)
+    ny, nz = field.shape[1], field.shape[0]
+    yy, zz = np.meshgrid((np.arange(ny) + 0.5) / ny, (np.arange(nz) + 0.5) / nz)
+    yz = np.stack([yy.ravel(), zz.ravel()], axis=1)
+    # the face lies halfway between voxel 31 of the left block and voxel 0 of the right one
+    truth = 0.5 * (field[:, :, 31] + field[:, :, 32]).astype(np.float64).ravel()
+    psnrs = []
+    for b, xface in ((0, 1.0), (1, 0.0)):
+        x = np.concatenate([np.full((yz.shape[0], 1), xface), yz], axis=1).astype(np.float32)
+        pred = model.sample(b, dev(x)).cpu().numpy().astype(np.float64)
+        mse = np.mean((pred - truth) ** 2)
+        psnr = 10 * np.log10(1.0 / mse)  # the field spans [0, 1]
+        psnrs.append(psnr)
+    return float(np.mean(psnrs))
+
+
+def test_boundary_loss_raises_shared_face_accuracy():
+    say("two neighbouring blocks: shared-face PSNR with and without the boundary term")
+    field = kolmogorov_field(64, seed=6)[:32, :32, :]  # 64 x 32 x 32 (x fastest)
+    field = ((field - field.min()) / (field.max() - field.min())).astype(np.float32)
+    parts = cut_blocks(field, ([32, 32], [32], [32]), ghost=1, periodic=False)
+    enc = o.Encoding(6, 2, 14, 4, 1.6)
+    cfg = (enc, o.MLP(2, 32))
+    res = {}
+    for lam in (0.0, LAM):
+        model = make(cfg, [(p["dims"], p["ghost"]) for p in parts], seed=9, max_batch=1 << 15)
+        model.bind_volumes([dev(p["data"]) for p in parts])
+        model.init_params(3)
+        res[lam] = _face_psnr(model, field, parts, steps=600, lam=lam, batch=1 << 14)
+        torch.cuda.synchronize()
+    say(f"shared-face PSNR: lambda=0 {res[0.0]:.2f} dB, lambda={LAM} {res[LAM]:.2f} dB")
+    assert res[LAM] > res[0.0] + 0.5
