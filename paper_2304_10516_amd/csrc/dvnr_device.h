@@ -127,24 +127,23 @@ __device__ __forceinline__ uint32_t xcc_id() {
 }
 
 // Map a linear workgroup id of a level-major launch to (tile, level).  With
-// xcd_map, the workgroups dispatched to one XCD (round-robin dispatch puts
-// workgroup w on XCD w % 8) take a contiguous run of the level-major work
-// list, so that each XCD's L2 holds only a few levels' tables.  Any mapping is
-// correct; this one only improves locality.  Returns false for idle
-// workgroups.  Levels handled by one launch are [l0, l0 + L).
+// xcd_map and at least 8 levels, the workgroups dispatched to XCD x
+// (round-robin dispatch puts workgroup w on XCD w % 8) work on levels l with
+// l % 8 == x: each XCD's L2 holds only its own levels' tables, and every XCD
+// pairs coarse (cheap) with fine (expensive) levels, which balances the XCDs.
+// Any mapping is correct; this one only improves locality and balance.
+// Returns false for idle workgroups.  Levels of the launch are [l0, l0 + L).
 __device__ __forceinline__ bool level_major_item(int wg, int l0, int L, int n_tiles, int xcd_map, int& tile,
                                                  int& level) {
-  if (xcd_map) {
-    // work items (level, tile) in level-major order; XCD x (workgroups w with
-    // w mod 8 == x) takes the contiguous eighth [x per, (x + 1) per), so each
-    // XCD's L2 holds the tables of about L/8 + 1 levels, never all L
-    const int per = (int)(((int64_t)L * n_tiles + 7) / 8);
+  if (xcd_map && L >= 8) {
+    const int lp = (L + 7) / 8;
     const int x = wg & 7, r = wg >> 3;
-    const int64_t k = (int64_t)x * per + r;
-    if (r >= per || k >= (int64_t)L * n_tiles) return false;
-    level = l0 + (int)(k / n_tiles);
-    tile = (int)(k % n_tiles);
-    return true;
+    const int slot = r % lp;
+    tile = r / lp;
+    level = x + 8 * slot;
+    const bool ok = level < L && tile < n_tiles;
+    level += l0;
+    return ok;
   }
   level = l0 + wg % L;
   tile = wg / L;
@@ -152,7 +151,7 @@ __device__ __forceinline__ bool level_major_item(int wg, int l0, int L, int n_ti
 }
 
 __host__ __device__ inline int level_major_grid(int L, int n_tiles, int xcd_map) {
-  if (xcd_map) return 8 * (int)(((int64_t)L * n_tiles + 7) / 8);
+  if (xcd_map && L >= 8) return 8 * ((L + 7) / 8) * n_tiles;
   return L * n_tiles;
 }
 

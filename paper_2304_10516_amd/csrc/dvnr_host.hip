@@ -509,19 +509,12 @@ static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_
   int B = 1;
   while (B < 8 && (int64_t)(B + 1) * (B + 1) * (B + 1) * 512 <= min_n) ++B;
   h->sort_B = B;
-  // Privatize the longest prefix of levels whose per-bin box fits the LDS
-  // budget (cells and vertex accumulators) and whose corner hits per step are
-  // dense enough (>= 0.3 per grid vertex) for per-entry sums to save atomics.
-  int pl = 0;
-  for (int l = 0; l < h->enc.n_levels; ++l) {
-    const double R = (double)h->ld.R[l];
-    const double side = (R - 1.0) / (double)B + 1.5;  // cells per axis of a bin's box, with slack
-    const double F = (double)h->enc.n_features;
-    if (side * side * side > kPrivCells || (side + 1.0) * (side + 1.0) * (side + 1.0) * F > kPrivVertFloats ||
-        8.0 * (double)min_n < 0.3 * R * R * R)
-      break;
-    pl = l + 1;
-  }
+  // Ordered sampling privatizes every level by default: a (bin, level)
+  // workgroup accumulates in LDS when the bin's cell box fits, and otherwise
+  // issues grouped direct atomics over its bin's samples, which keeps each
+  // XCD on its own levels' tables (a separate direct launch over the fine
+  // levels would spread them over every XCD).
+  const int pl = h->enc.n_levels;
   h->priv_L = h->priv_levels >= 0 ? std::min(h->priv_levels, h->enc.n_levels) : pl;
   HIPCHK(hipMemcpyAsync(h->d_plan(), h->hplan.data(), sizeof(BlockPlan) * h->nb, hipMemcpyHostToDevice, s));
   if (h->n_tiles)
@@ -917,8 +910,8 @@ dvnr_status dvnr_autotune(dvnr_t* h, int64_t samples_per_step, int32_t n_trial_s
     };
     std::vector<Cand> cands = {{0, 0, kMlpGrid},
                                {1, auto_pl, kMlpGrid},
-                               {1, std::max(0, auto_pl - 2), kMlpGrid},
-                               {1, std::min(L, auto_pl + 1), kMlpGrid},
+                               {1, std::max(0, L - 3), kMlpGrid},
+                               {1, std::max(0, L - 5), kMlpGrid},
                                {1, auto_pl, kMlpGrid / 2},
                                {1, auto_pl, 2 * kMlpGrid}};
     hipEvent_t e0, e1;

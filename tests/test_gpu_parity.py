@@ -209,6 +209,40 @@ def test_sorted_sampling_gradient_parity(precision, priv):
     assert normwise(gg[nt:], g[nt:]) <= tol, "weight gradient"
 
 
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_sorted_sampling_gradient_parity_fine_levels(precision):
+    """16 levels up to R = 256 with 8192 samples (2^3 bins of ~1024): coarse
+    levels accumulate in LDS, levels whose bin box exceeds the LDS budget take
+    the in-kernel direct-atomic path; bins above 1024 samples take two chunks."""
+    say(f"ordered sampling, all levels privatized, c2 levels {precision}")
+    vol = gaussian_sum_field(64, seed=3)
+    lay = o.layout(*C2)
+    p = init_param_draws(lay.n_table_params, lay.mlp_shapes, seed=2).astype(np.float64)
+    p[:lay.n_table_params] *= 1e3
+    model = make(C2, [((64, 64, 64), 0)], precision=precision, max_batch=1 << 14, seed=91)
+    model.bind_volumes([dev(vol)])
+    model.load_params([p])
+    model.set_option("spatial_sort", 1)
+    model.set_option("priv_levels", -1)
+    model.set_option("apply_update", 0)
+    model.set_option("use_graph", 0)
+    loss = model.train(1, 8192, want_loss=True)
+    torch.cuda.synchronize()
+    assert model.plan_info() == (2, 16)
+    pref = model.block_params(0).cpu().numpy().astype(np.float64) if precision == "fp32" else p
+    x = o.training_coords(91, 0, 0, 8192)
+    tgt = o.normalized_targets(vol, (64, 64, 64), 0, x)
+    L, g, _ = o.loss_and_grad(lay, pref, x, tgt)
+    gg = model.block_grads(0).cpu().numpy()
+    nt = lay.n_table_params
+    tol = 1e-5 if precision == "fp32" else 3e-2
+    assert abs(loss[0, 0].item() - L) <= (1e-5 if precision == "fp32" else 1e-2) * L
+    for l, lvl in enumerate(lay.levels):
+        a, b_ = lvl.off * 2, (lvl.off + lvl.E) * 2
+        assert normwise(gg[a:b_], g[a:b_]) <= tol, f"level {l} table gradient"
+    assert normwise(gg[nt:], g[nt:]) <= tol, "weight gradient"
+
+
 def test_adam_update_parity_c1():
     say("adam update c1 fp32")
     vol, lay, p0, model = _setup_c1_block("fp32")
