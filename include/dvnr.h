@@ -164,10 +164,36 @@ dvnr_status dvnr_reset_optimizer(dvnr_t* h, void* stream);
  * Philox4x32-10 counter (sample, step, block, 'DVNR') and key (seed lo,
  * seed hi); the last nb = floor(boundary_frac * n + 1/2) are boundary-centered
  * (dvnr_set_loss; nb = 0 by default).  Then forward, the loss (mean per block;
- * L2 by default), backward and Adam.  loss_out: device float
+ * L2 by default), backward and Adam; a block that draws no sample in a step
+ * is left unchanged by that step.  loss_out: device float
  * [n_steps][n_blocks] or NULL.  samples_per_step <= max_batch. */
 dvnr_status dvnr_train_steps(dvnr_t* h, int32_t n_steps, int64_t samples_per_step, float* loss_out,
                              void* stream);
+/* Training length (Sec. III-B).  Block b trains at most
+ *   N_max(b) = max(min_steps, ceil(N_vox(b) / n_b) * epochs)
+ * steps (N_vox = owned voxels, n_b = its samples per step), and stops earlier
+ * when loss_threshold > 0 and, at a multiple of check_every steps with at
+ * least `window` steps done, the plain mean of its last `window` losses is
+ * below loss_threshold (min_steps bounds only N_max). */
+typedef struct dvnr_stop_policy {
+  int64_t min_steps;      /* N_train^min, >= 0 */
+  int64_t epochs;         /* N_epoch, >= 0 */
+  double loss_threshold;  /* <= 0 disables the loss criterion */
+  int32_t window;         /* 1 .. 1024 */
+  int32_t check_every;    /* >= 1 */
+} dvnr_stop_policy;
+
+/* Train every block under `policy` with samples_per_step split as in
+ * dvnr_train_steps; blocks stop independently: a stopped block draws no
+ * samples and its parameters and Adam state stay unchanged while the others
+ * continue (the step counter is shared).  steps_out: host int64[n_blocks],
+ * steps each block trained; avg_loss_out: host double[n_blocks] or NULL, the
+ * moving average at the block's last check (NaN if none).  Synchronizes
+ * `stream`; the moving average is read back from the device every
+ * check_every steps. */
+dvnr_status dvnr_train_until(dvnr_t* h, const dvnr_stop_policy* policy, int64_t samples_per_step,
+                             int64_t* steps_out, double* avg_loss_out, void* stream);
+
 /* One optimizer step on caller-given coordinates: coords device float
  * [sum_b n_b][3] grouped by block, n_per_block host int64[n_blocks].
  * loss_out: device float [n_blocks] or NULL. */

@@ -21,6 +21,8 @@ What it computes, per partition block (one implicit neural representation,
   per-block min/max normalization (`training_coords`, `sample_volume`);
 * boundary-centered half-normal samples (Sec. III-E, Eq. (4)) mixed into a
   step's batch (`boundary_coords`, `step_coords`);
+* the step budget and the moving-average early termination (Sec. III-B)
+  (`max_train_steps`, `should_stop`, `train_until`);
 * the L2 or L1 loss (Sec. III-E, Eq. (5)), the encoding backward
   (scatter-add), Adam with L2 weight decay (Sec. III-F) (`train_step`, `adam`);
 * decoding at voxel centers and PSNR over owned voxels (`decode`, `psnr`).
@@ -523,6 +525,66 @@ def train(lay: Layout, params0, vol, dims, ghost, n_steps: int, batch: int, seed
         params, L = train_step(lay, params, st, opt, x, tgt, loss)
         losses.append(L)
     return params, np.array(losses), st
+
+
+# --------------------------------------------------------------------------
+# Training length and early termination (Sec. III-B)
+# --------------------------------------------------------------------------
+@dataclass
+class StopPolicy:
+    min_steps: int = 0            # N_train^min
+    epochs: int = 1               # N_epoch
+    loss_threshold: float = 0.0   # stop when the moving average falls below it; <= 0 disables
+    window: int = 16              # moving-average window, in steps
+    check_every: int = 16         # steps between two checks of the moving average
+
+
+def max_train_steps(n_vox: int, batch: int, pol: StopPolicy) -> int:
+    """N_train^max = max(N_train^min, ceil(N_vox / N_batch) * N_epoch) (Sec. III-B);
+    0 when the block draws no samples."""
+    if batch <= 0:
+        return 0
+    return max(int(pol.min_steps), -(-int(n_vox) // int(batch)) * int(pol.epochs))
+
+
+def moving_average(losses, window: int) -> float:
+    """Plain mean of the last `window` losses."""
+    w = np.asarray(losses[-window:], dtype=np.float64)
+    return float(np.mean(w))
+
+
+def should_stop(losses, pol: StopPolicy) -> bool:
+    """Loss criterion after len(losses) steps: checked only at multiples of
+    check_every steps and once a full window exists; N_train^min bounds only
+    the step budget (the formula above), not this test."""
+    k = len(losses)
+    if pol.loss_threshold <= 0 or k == 0 or k % pol.check_every or k < pol.window:
+        return False
+    return moving_average(losses, pol.window) < pol.loss_threshold
+
+
+def train_until(lay: Layout, params0, vol, dims, ghost, batch: int, seed: int, opt: Optim, pol: StopPolicy,
+                block: int = 0, n_vox: int | None = None, loss: str = "l2", boundary_frac: float = 0.0,
+                sigma: float = 0.005):
+    """Train one block until the loss criterion holds or N_train^max steps are
+    done.  n_vox defaults to the block's owned voxel count.
+    Returns (params, losses, steps done)."""
+    if n_vox is None:
+        n_vox = int(np.prod(dims))
+    n_max = max_train_steps(n_vox, batch, pol)
+    params = np.asarray(params0, dtype=np.float64).copy()
+    st = adam_init(lay.n_params)
+    nbd = boundary_count(batch, boundary_frac)
+    losses = []
+    while len(losses) < n_max:
+        s = len(losses)
+        x = step_coords(seed, block, s, batch, nbd, sigma)
+        tgt = normalized_targets(vol, dims, ghost, x)
+        params, L = train_step(lay, params, st, opt, x, tgt, loss)
+        losses.append(L)
+        if should_stop(losses, pol):
+            break
+    return params, np.array(losses), len(losses)
 
 
 # --------------------------------------------------------------------------

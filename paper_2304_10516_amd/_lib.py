@@ -43,6 +43,11 @@ class Buffers(C.Structure):
                 ("work16", C.c_void_p), ("workspace", C.c_void_p), ("volumes", C.POINTER(C.c_void_p))]
 
 
+class StopPolicy(C.Structure):
+    _fields_ = [("min_steps", C.c_int64), ("epochs", C.c_int64), ("loss_threshold", C.c_double),
+                ("window", C.c_int32), ("check_every", C.c_int32)]
+
+
 class DvnrError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"dvnr error {code}: {msg}")
@@ -80,6 +85,7 @@ SIGNATURES = {
     "dvnr_sync": [P, VP],
     "dvnr_set_option": [P, C.c_char_p, I64],
     "dvnr_set_loss": [P, I32, C.c_double, C.c_double],
+    "dvnr_train_until": [P, C.POINTER(StopPolicy), I64, C.POINTER(C.c_int64), C.POINTER(C.c_double), VP],
     "dvnr_phase_times": [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
     "dvnr_plan_info": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
     "dvnr_autotune": [P, I64, I32, C.POINTER(C.c_double), VP],

@@ -615,7 +615,8 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   }
   HIPCHK(launch_adam(h->prec, h->buf.params, h->buf.grads, h->buf.adam_m, h->buf.adam_v,
                      mixed ? (uint16_t*)h->buf.work16 : nullptr, h->nb, h->stride, h->n_table, h->n_table + h->n_mlp,
-                     h->d_ctr(), h->opt.lr, h->opt.beta1, h->opt.beta2, h->opt.eps, h->opt.weight_decay, s));
+                     h->d_plan(), h->d_ctr(), h->opt.lr, h->opt.beta1, h->opt.beta2, h->opt.eps,
+                     h->opt.weight_decay, s));
   PROF(7);
   return DVNR_OK;
 }
@@ -633,11 +634,71 @@ static dvnr_status copy_losses(dvnr_t* h, int64_t s0, int64_t n, float* out, hip
   return DVNR_OK;
 }
 
+// Host copy of the losses of steps [s0, s0 + n) (n <= kLossRing): out[k][b].  Synchronizes s.
+static dvnr_status copy_losses_host(dvnr_t* h, int64_t s0, int64_t n, float* out, hipStream_t s) {
+  int64_t done = 0;
+  while (done < n) {
+    const int64_t row = (s0 + done) % kLossRing;
+    const int64_t cnt = std::min(n - done, (int64_t)kLossRing - row);
+    HIPCHK(hipMemcpyAsync(out + done * h->nb, h->d_ring() + row * h->nb, sizeof(float) * cnt * h->nb,
+                          hipMemcpyDeviceToHost, s));
+    done += cnt;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return DVNR_OK;
+}
+
 static dvnr_status train_ready(dvnr_t* h) {
   if (!h) return fail(DVNR_E_INVALID, "null handle");
   if (!h->bound) return fail(DVNR_E_STATE, "train before dvnr_bind");
   if (!h->prepared) return fail(DVNR_E_STATE, "train before dvnr_prepare");
   if (h->prec == Prec::F64) return fail(DVNR_E_UNSUPPORTED, "fp64 handles provide the autograd building blocks only");
+  return DVNR_OK;
+}
+
+// n_steps generated-sample steps with the current plan: replays of one
+// captured step (hipGraph, keyed by stream and `plan_key`) on a non-default
+// stream, else eager launches.  Losses of the steps go to loss_out (device
+// float [n_steps][n_blocks]) when given.
+static dvnr_status run_steps(dvnr_t* h, int64_t n_steps, int64_t plan_key, float* loss_out, hipStream_t s) {
+  dvnr_status st = DVNR_OK;
+  const int64_t s0 = h->host_step;
+  int64_t done = 0;
+  while (done < n_steps) {
+    const int64_t chunk = std::min<int64_t>(n_steps - done, kLossRing);
+    const bool graph_ok = h->use_graph && !h->profile && s != nullptr;
+    if (graph_ok && (!h->graph || h->graph_stream != s || h->graph_total != plan_key)) {
+      if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+      }
+      hipGraph_t g;
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      st = enqueue_step(h, 1, s);
+      hipError_t ce = hipStreamEndCapture(s, &g);
+      if (st) return st;
+      if (ce != hipSuccess) return fail(DVNR_E_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+      ce = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ce != hipSuccess) return fail(DVNR_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ce));
+      h->graph_stream = s;
+      h->graph_total = plan_key;
+    }
+    for (int64_t k = 0; k < chunk; ++k) {
+      if (graph_ok) {
+        HIPCHK(hipGraphLaunch(h->graph, s));
+      } else {
+        st = enqueue_step(h, 1, s);
+        if (st) return st;
+      }
+    }
+    h->host_step += chunk;
+    if (loss_out) {
+      st = copy_losses(h, s0 + done, chunk, loss_out + done * h->nb, s);
+      if (st) return st;
+    }
+    done += chunk;
+  }
   return DVNR_OK;
 }
 
@@ -656,43 +717,87 @@ dvnr_status dvnr_train_steps(dvnr_t* h, int32_t n_steps, int64_t samples_per_ste
       if (st) return st;
       h->plan_total = samples_per_step;
     }
-    const int64_t s0 = h->host_step;
-    int64_t done = 0;
-    while (done < n_steps) {
-      const int64_t chunk = std::min<int64_t>(n_steps - done, kLossRing);
-      const bool graph_ok = h->use_graph && !h->profile && s != nullptr;
-      if (graph_ok && (!h->graph || h->graph_stream != s || h->graph_total != samples_per_step)) {
-        if (h->graph) {
-          (void)hipGraphExecDestroy(h->graph);
-          h->graph = nullptr;
-        }
-        hipGraph_t g;
-        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        st = enqueue_step(h, 1, s);
-        hipError_t ce = hipStreamEndCapture(s, &g);
-        if (st) return st;
-        if (ce != hipSuccess) return fail(DVNR_E_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
-        ce = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ce != hipSuccess) return fail(DVNR_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ce));
-        h->graph_stream = s;
-        h->graph_total = samples_per_step;
-      }
-      for (int64_t k = 0; k < chunk; ++k) {
-        if (graph_ok) {
-          HIPCHK(hipGraphLaunch(h->graph, s));
-        } else {
-          st = enqueue_step(h, 1, s);
-          if (st) return st;
-        }
-      }
-      h->host_step += chunk;
-      if (loss_out) {
-        st = copy_losses(h, s0 + done, chunk, loss_out + done * h->nb, s);
-        if (st) return st;
-      }
-      done += chunk;
+    return run_steps(h, n_steps, samples_per_step, loss_out, s);
+  } catch (...) {
+    return fail(DVNR_E_INVALID, "train failed");
+  }
+}
+
+dvnr_status dvnr_train_until(dvnr_t* h, const dvnr_stop_policy* pol, int64_t samples_per_step, int64_t* steps_out,
+                             double* avg_loss_out, void* stream) {
+  try {
+    dvnr_status st = train_ready(h);
+    if (st) return st;
+    if (!pol || !steps_out) return fail(DVNR_E_INVALID, "null argument");
+    if (pol->min_steps < 0 || pol->epochs < 0 || pol->window < 1 || pol->window > kLossRing ||
+        pol->check_every < 1 || !(pol->loss_threshold == pol->loss_threshold))
+      return fail(DVNR_E_INVALID, "bad stop policy");
+    if (samples_per_step < 1 || samples_per_step > h->max_batch)
+      return fail(DVNR_E_INVALID, "samples_per_step must be in [1, max_batch]");
+    if (h->nb > 1 && samples_per_step % kTile)
+      return fail(DVNR_E_INVALID, "with several blocks samples_per_step must be a multiple of 256");
+    hipStream_t s = (hipStream_t)stream;
+    const std::vector<int64_t> n = apportion(h, samples_per_step);
+    // per-block step budget N_max = max(N_min, ceil(N_vox / n_b) * N_epoch)
+    std::vector<int64_t> n_max(h->nb, 0);
+    std::vector<char> active(h->nb, 0);
+    for (int b = 0; b < h->nb; ++b) {
+      steps_out[b] = 0;
+      if (avg_loss_out) avg_loss_out[b] = std::nan("");
+      if (n[b] <= 0) continue;
+      const int64_t nv = (int64_t)h->blocks[b].dims[0] * h->blocks[b].dims[1] * h->blocks[b].dims[2];
+      n_max[b] = std::max<int64_t>(pol->min_steps, (nv + n[b] - 1) / n[b] * pol->epochs);
+      active[b] = n_max[b] > 0;
     }
+    const bool use_loss = pol->loss_threshold > 0.0;
+    std::vector<float> ring;
+    int64_t done = 0;
+    bool replan = true;
+    for (;;) {
+      int64_t next_end = INT64_MAX;
+      for (int b = 0; b < h->nb; ++b)
+        if (active[b]) next_end = std::min(next_end, n_max[b]);
+      if (next_end == INT64_MAX) break;
+      if (replan) {
+        // stopped blocks draw no samples (their updates are skipped); the others keep their n_b
+        std::vector<int64_t> nm(h->nb);
+        for (int b = 0; b < h->nb; ++b) nm[b] = active[b] ? n[b] : 0;
+        st = set_plan(h, nm, s);
+        if (st) return st;
+        h->plan_total = -1;  // the next dvnr_train_steps rebuilds its plan
+        replan = false;
+      }
+      const int64_t next_check = use_loss ? (done / pol->check_every + 1) * pol->check_every : INT64_MAX;
+      const int64_t chunk = std::min(next_end, next_check) - done;
+      st = run_steps(h, chunk, -2, nullptr, s);
+      if (st) return st;
+      done += chunk;
+      for (int b = 0; b < h->nb; ++b)
+        if (active[b] && done >= n_max[b]) {
+          active[b] = 0;
+          steps_out[b] = done;
+          replan = true;
+        }
+      if (use_loss && done % pol->check_every == 0 && done >= pol->window) {
+        // moving average of the last `window` losses of every block (device ring of kLossRing steps)
+        ring.assign((size_t)pol->window * h->nb, 0.0f);
+        st = copy_losses_host(h, h->host_step - pol->window, pol->window, ring.data(), s);
+        if (st) return st;
+        for (int b = 0; b < h->nb; ++b) {
+          if (!active[b] && steps_out[b] != done) continue;
+          double acc = 0.0;
+          for (int k = 0; k < pol->window; ++k) acc += (double)ring[(size_t)k * h->nb + b];
+          const double ma = acc / pol->window;
+          if (avg_loss_out) avg_loss_out[b] = ma;
+          if (active[b] && ma < pol->loss_threshold) {
+            active[b] = 0;
+            steps_out[b] = done;
+            replan = true;
+          }
+        }
+      }
+    }
+    HIPCHK(hipStreamSynchronize(s));
     return DVNR_OK;
   } catch (...) {
     return fail(DVNR_E_INVALID, "train failed");

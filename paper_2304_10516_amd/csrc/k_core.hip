@@ -414,8 +414,8 @@ template <typename P>
 __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restrict__ grad, P* __restrict__ mom,
                                               P* __restrict__ vel, uint16_t* __restrict__ work16,
                                               int64_t n_total, int64_t block_stride, int64_t n_table,
-                                              int64_t n_used, const Counters* __restrict__ ctr, P lr, P b1,
-                                              P b2, P eps, P wd) {
+                                              int64_t n_used, const BlockPlan* __restrict__ plan,
+                                              const Counters* __restrict__ ctr, P lr, P b1, P b2, P eps, P wd) {
   const double t = (double)ctr->step;
   const P bc1 = (P)(1.0 / (1.0 - pow((double)b1, t)));
   const P bc2 = (P)(1.0 / (1.0 - pow((double)b2, t)));
@@ -424,6 +424,7 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
     const int64_t i0 = 4 * q;
     const int64_t j0 = i0 % block_stride;
     if (j0 >= n_used) continue;
+    if (plan && plan[i0 / block_stride].n == 0) continue;  // block drew no sample this step: unchanged
     P th[4], g[4], m[4], v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -470,17 +471,18 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
 }
 
 hipError_t launch_adam(Prec p, void* params, void* grad, void* m, void* v, uint16_t* work16, int n_blocks,
-                       int64_t block_stride, int64_t n_table_params, int64_t n_used, const Counters* ctr,
-                       double lr, double b1, double b2, double eps, double wd, hipStream_t s) {
+                       int64_t block_stride, int64_t n_table_params, int64_t n_used, const BlockPlan* plan,
+                       const Counters* ctr, double lr, double b1, double b2, double eps, double wd, hipStream_t s) {
   const int64_t n_total = (int64_t)n_blocks * block_stride;
   const int64_t n4 = n_total / 4;
   const int grid = (int)std::min<int64_t>((n4 + 255) / 256, 256 * 32);
   if (p == Prec::F64)
     hipLaunchKernelGGL(k_adam<double>, dim3(grid), dim3(256), 0, s, (double*)params, (double*)grad, (double*)m,
-                       (double*)v, nullptr, n_total, block_stride, n_table_params, n_used, ctr, lr, b1, b2, eps, wd);
+                       (double*)v, nullptr, n_total, block_stride, n_table_params, n_used, plan, ctr, lr, b1, b2, eps,
+                       wd);
   else
     hipLaunchKernelGGL(k_adam<float>, dim3(grid), dim3(256), 0, s, (float*)params, (float*)grad, (float*)m,
-                       (float*)v, work16, n_total, block_stride, n_table_params, n_used, ctr, (float)lr, (float)b1,
+                       (float*)v, work16, n_total, block_stride, n_table_params, n_used, plan, ctr, (float)lr, (float)b1,
                        (float)b2, (float)eps, (float)wd);
   return hipGetLastError();
 }

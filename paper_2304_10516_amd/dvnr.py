@@ -187,6 +187,19 @@ class DVNR:
                                           loss.data_ptr() if loss is not None else None, _stream_ptr(stream)))
         return loss
 
+    def train_until(self, samples_per_step: int, min_steps: int = 0, epochs: int = 1, loss_threshold: float = 0.0,
+                    window: int = 16, check_every: int = 16, stream=None):
+        """Train every block up to max(min_steps, ceil(N_vox / n_b) * epochs)
+        steps, stopping a block early when the mean of its last `window`
+        losses, checked every `check_every` steps, is below loss_threshold
+        (Sec. III-B).  Returns (steps per block, last moving average per block)."""
+        pol = L.StopPolicy(int(min_steps), int(epochs), float(loss_threshold), int(window), int(check_every))
+        steps = (C.c_int64 * self.n_blocks)()
+        avg = (C.c_double * self.n_blocks)()
+        L.check(self.lib.dvnr_train_until(self.h, C.byref(pol), int(samples_per_step), steps, avg,
+                                          _stream_ptr(stream)))
+        return list(steps), list(avg)
+
     def train_step_coords(self, coords: torch.Tensor, n_per_block, stream=None):
         coords = coords.to(device=self.device, dtype=torch.float32).contiguous()
         n = (C.c_int64 * self.n_blocks)(*[int(v) for v in n_per_block])

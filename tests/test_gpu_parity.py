@@ -229,18 +229,29 @@ def test_sorted_sampling_gradient_parity_fine_levels(precision):
     loss = model.train(1, 8192, want_loss=True)
     torch.cuda.synchronize()
     assert model.plan_info() == (2, 16)
-    pref = model.block_params(0).cpu().numpy().astype(np.float64) if precision == "fp32" else p
+    if precision == "fp32":
+        pref = model.block_params(0).cpu().numpy().astype(np.float64)
+    else:  # the mixed path computes with the fp16 table / bf16 weight working copy
+        nt = lay.n_table_params
+        w = torch.tensor(p[nt:]).to(torch.bfloat16).to(torch.float64).numpy()
+        pref = np.concatenate([p[:nt].astype(np.float16).astype(np.float64), w])
     x = o.training_coords(91, 0, 0, 8192)
     tgt = o.normalized_targets(vol, (64, 64, 64), 0, x)
     L, g, _ = o.loss_and_grad(lay, pref, x, tgt)
     gg = model.block_grads(0).cpu().numpy()
     nt = lay.n_table_params
-    tol = 1e-5 if precision == "fp32" else 3e-2
     assert abs(loss[0, 0].item() - L) <= (1e-5 if precision == "fp32" else 1e-2) * L
+    # fp32: max-element bar.  mixed: the scatter is the same fp32 code (pinned by the
+    # fp32 case); what differs is the bf16 MLP backward, whose per-sample rounding
+    # (~2^-8) meets heavy cancellation in the coarse-level vertex sums, so the bar
+    # there is on the 2-norm relative error
+    err = normwise if precision == "fp32" else (
+        lambda a, b: float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b)))
+    tol = 1e-5 if precision == "fp32" else 3e-2
     for l, lvl in enumerate(lay.levels):
         a, b_ = lvl.off * 2, (lvl.off + lvl.E) * 2
-        assert normwise(gg[a:b_], g[a:b_]) <= tol, f"level {l} table gradient"
-    assert normwise(gg[nt:], g[nt:]) <= tol, "weight gradient"
+        assert err(gg[a:b_], g[a:b_]) <= tol, f"level {l} table gradient"
+    assert err(gg[nt:], g[nt:]) <= tol, "weight gradient"
 
 
 def test_adam_update_parity_c1():
@@ -371,11 +382,12 @@ def test_batched_ordered_training_gradients(precision):
     model.load_params(ps)
     model.set_option("apply_update", 0)
     model.set_option("spatial_sort", 1)
+    model.set_option("priv_levels", 2)
     total = 4096
     loss = model.train(1, total, want_loss=True)
     torch.cuda.synchronize()
     bins, priv = model.plan_info()
-    assert bins >= 1 and 0 < priv < lay.enc.n_levels  # both scatter paths are exercised
+    assert bins >= 1 and priv == 2  # both scatter paths are exercised
     n = o.apportion([d[0] * d[1] * d[2] for d, _ in blocks], total)
     tol = 1e-5 if precision == "fp32" else 3e-2
     for b, ((d, g), v) in enumerate(zip(blocks, vols)):
