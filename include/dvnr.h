@@ -211,6 +211,34 @@ dvnr_status dvnr_sample(dvnr_t* h, int32_t block, int64_t n, const float* coords
 /* Decode block b to its owned voxel grid at voxel centers (i+1/2)/n:
  * out device float [nz][ny][nx] (x fastest), de-normalized. */
 dvnr_status dvnr_decode(dvnr_t* h, int32_t block, float* out, void* stream);
+/* Sliding-window model cache (Sec. III-E weight caching; Sec. IV temporal
+ * caching): snapshots of the trained models of past timesteps, kept on the
+ * device so that any cached timestep can be decoded or sampled on demand.
+ * A snapshot holds the inference parameters of every block (fp16 tables and
+ * bf16 weights for mixed precision, fp32 otherwise) and the blocks' value
+ * ranges at push time; decoding it runs the same kernels as dvnr_decode.
+ *
+ * dvnr_cache_snapshot_bytes : bytes of one snapshot (*bytes).
+ * dvnr_cache_bind           : caller-owned device buffer of capacity snapshots
+ *                             (256-byte aligned, capacity * snapshot bytes);
+ *                             clears the cache.  capacity 0 unbinds.
+ * dvnr_cache_push           : snapshot the current model under `key` (e.g. the
+ *                             timestep), stream-ordered after earlier work;
+ *                             when full, the oldest snapshot is dropped.
+ *                             DVNR_E_INVALID if `key` is already cached.
+ * dvnr_cache_keys           : cached keys, oldest first (host int64[capacity],
+ *                             may be NULL), and their count.
+ * dvnr_cache_decode / _sample : as dvnr_decode / dvnr_sample on the snapshot
+ *                             of `key`; DVNR_E_INVALID if it is not cached.
+ * Block geometry is the handle's; the volumes need not be bound any more. */
+dvnr_status dvnr_cache_snapshot_bytes(const dvnr_t* h, int64_t* bytes);
+dvnr_status dvnr_cache_bind(dvnr_t* h, int32_t capacity, void* buffer);
+dvnr_status dvnr_cache_push(dvnr_t* h, int64_t key, void* stream);
+dvnr_status dvnr_cache_keys(const dvnr_t* h, int64_t* keys, int32_t* count);
+dvnr_status dvnr_cache_decode(dvnr_t* h, int64_t key, int32_t block, float* out, void* stream);
+dvnr_status dvnr_cache_sample(dvnr_t* h, int64_t key, int32_t block, int64_t n, const float* coords, float* out,
+                              void* stream);
+
 /* Sum of squared differences (fp64 accumulation) between a decoded block and
  * the block's owned stored voxels: host *sse, *count.  Synchronizes `stream`. */
 dvnr_status dvnr_mse_fp64(dvnr_t* h, int32_t block, const float* decoded, double* sse, int64_t* count,

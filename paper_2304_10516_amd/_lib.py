@@ -85,6 +85,12 @@ SIGNATURES = {
     "dvnr_sync": [P, VP],
     "dvnr_set_option": [P, C.c_char_p, I64],
     "dvnr_set_loss": [P, I32, C.c_double, C.c_double],
+    "dvnr_cache_snapshot_bytes": [P, C.POINTER(C.c_int64)],
+    "dvnr_cache_bind": [P, I32, VP],
+    "dvnr_cache_push": [P, I64, VP],
+    "dvnr_cache_keys": [P, C.POINTER(C.c_int64), C.POINTER(C.c_int32)],
+    "dvnr_cache_decode": [P, I64, I32, VP, VP],
+    "dvnr_cache_sample": [P, I64, I32, I64, VP, VP, VP],
     "dvnr_train_until": [P, C.POINTER(StopPolicy), I64, C.POINTER(C.c_int64), C.POINTER(C.c_double), VP],
     "dvnr_phase_times": [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
     "dvnr_plan_info": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],

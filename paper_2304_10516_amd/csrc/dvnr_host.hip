@@ -70,6 +70,11 @@ struct dvnr {
   int mlp_cap = kMlpGrid;  // workgroups of the persistent MLP kernel (autotuned)
   int decode_fused = 1;    // decode with the fused brick kernel (else encode + MLP over chunks)
   int apply_update = 1;
+  // sliding-window model cache: capacity snapshots of the inference parameters
+  // and block ranges in a caller buffer, oldest first from cache_head
+  char* cache_buf = nullptr;
+  int cache_cap = 0, cache_head = 0, cache_count = 0;
+  std::vector<int64_t> cache_keys;
   // loss (Sec. III-E): 0 L2, 1 L1; fraction and spread of boundary-centered samples
   int loss_l1 = 0;
   double bnd_frac = 0.0, bnd_sigma = 0.005;
@@ -114,6 +119,7 @@ struct dvnr {
   int32_t* d_binstart() const { return (int32_t*)(ws() + o_binstart); }
   uint32_t* d_totals() const { return (uint32_t*)(ws() + o_totals); }
   size_t pelem() const { return prec == Prec::F64 ? 8 : 4; }
+  size_t ielem() const { return prec == Prec::MIXED ? 2 : pelem(); }  // inference copy element
 
   ~dvnr() {
     if (graph) (void)hipGraphExecDestroy(graph);
@@ -848,17 +854,30 @@ dvnr_status dvnr_draw_training_samples(dvnr_t* h, int32_t block, int64_t step, i
 }
 
 // INR output at `n` coordinates of block b (chunks of max_batch), de-normalized.
-static dvnr_status infer_coords(dvnr_t* h, int b, int64_t n, const float* coords, float* out, hipStream_t s) {
+// Parameters a query reads: the inference copy of every block (the fp16 / bf16
+// working copy for mixed precision, fp32 masters otherwise) and the block
+// value ranges; the live model or a cached snapshot.
+struct ModelSrc {
+  const void* params;
+  const BlockRange* range;
+};
+
+static ModelSrc live_src(const dvnr_t* h) {
+  return ModelSrc{h->prec == Prec::MIXED ? (const void*)h->buf.work16 : (const void*)h->buf.params, h->d_range()};
+}
+
+static dvnr_status infer_coords(dvnr_t* h, int b, int64_t n, const float* coords, float* out, hipStream_t s,
+                                const ModelSrc& src) {
   const bool mixed = h->prec == Prec::MIXED;
   const int64_t F = h->enc.n_features;
-  const void* table = mixed ? h->buf.work16 : h->buf.params;
-  const void* wsrc = mixed ? (const void*)((const uint16_t*)h->buf.work16 + h->n_table)
-                           : (const void*)((const float*)h->buf.params + h->n_table);
+  const void* table = src.params;
+  const void* wsrc = mixed ? (const void*)((const uint16_t*)src.params + h->n_table)
+                           : (const void*)((const float*)src.params + h->n_table);
   for (int64_t c0 = 0; c0 < n; c0 += h->max_batch) {
     const int64_t cn = std::min(h->max_batch, n - c0);
     HIPCHK(launch_encode(h->prec, mixed ? 1 : 0, h->ld, h->d_meta(), nullptr, (int)cn, b, nullptr, coords + 3 * c0,
                          table, h->d_feat(), F, h->max_batch * F, h->xcd_map, s));
-    HIPCHK(launch_mlp_infer(h->prec, h->md, h->ld, h->d_meta(), h->d_range(), nullptr, nullptr, (int)cn, b,
+    HIPCHK(launch_mlp_infer(h->prec, h->md, h->ld, h->d_meta(), src.range, nullptr, nullptr, (int)cn, b,
                             h->d_feat(), wsrc, h->max_batch, out + c0, s));
   }
   return DVNR_OK;
@@ -876,36 +895,134 @@ dvnr_status dvnr_sample(dvnr_t* h, int32_t block, int64_t n, const float* coords
   dvnr_status st = access_ready(h, block);
   if (st) return st;
   if (n < 0 || (n > 0 && (!coords || !out))) return fail(DVNR_E_INVALID, "bad arguments");
-  return infer_coords(h, block, n, coords, out, (hipStream_t)stream);
+  return infer_coords(h, block, n, coords, out, (hipStream_t)stream, live_src(h));
 }
 
-dvnr_status dvnr_decode(dvnr_t* h, int32_t block, float* out, void* stream) {
-  if (!out) return fail(DVNR_E_INVALID, "null output");
-  const int b0 = block < 0 ? 0 : block, b1 = block < 0 ? (h ? h->nb : 0) : block + 1;
-  dvnr_status st = access_ready(h, b0);
-  if (st) return st;
-  if (block >= h->nb) return fail(DVNR_E_INVALID, "bad block");
-  hipStream_t s = (hipStream_t)stream;
+static dvnr_status decode_impl(dvnr_t* h, int32_t block, float* out, hipStream_t s, const ModelSrc& src) {
+  const int b0 = block < 0 ? 0 : block, b1 = block < 0 ? h->nb : block + 1;
   int64_t out_off = 0;
-  const bool mixed = h->prec == Prec::MIXED;
+  dvnr_status st = DVNR_OK;
   for (int b = b0; b < b1; ++b) {
     const int64_t nvox = owned_voxels(h->blocks[b]);
     if (h->decode_fused) {
-      const void* table = mixed ? h->buf.work16 : h->buf.params;
-      HIPCHK(launch_decode_fused(h->prec, h->ld, h->md, h->d_meta(), h->d_range(), b, h->blocks[b].dims, table,
-                                 table, h->n_table, out + out_off, s));
+      HIPCHK(launch_decode_fused(h->prec, h->ld, h->md, h->d_meta(), src.range, b, h->blocks[b].dims, src.params,
+                                 src.params, h->n_table, out + out_off, s));
       out_off += nvox;
       continue;
     }
     for (int64_t c0 = 0; c0 < nvox; c0 += h->max_batch) {
       const int64_t cn = std::min(h->max_batch, nvox - c0);
       HIPCHK(launch_voxel_coords(h->d_meta(), b, c0, cn, h->d_coords(), s));
-      st = infer_coords(h, b, cn, h->d_coords(), out + out_off + c0, s);
+      st = infer_coords(h, b, cn, h->d_coords(), out + out_off + c0, s, src);
       if (st) return st;
     }
     out_off += nvox;
   }
   return DVNR_OK;
+}
+
+dvnr_status dvnr_decode(dvnr_t* h, int32_t block, float* out, void* stream) {
+  if (!out) return fail(DVNR_E_INVALID, "null output");
+  dvnr_status st = access_ready(h, block < 0 ? 0 : block);
+  if (st) return st;
+  if (block >= h->nb) return fail(DVNR_E_INVALID, "bad block");
+  return decode_impl(h, block, out, (hipStream_t)stream, live_src(h));
+}
+
+// ---------------------------------------------------------------------------
+// Sliding-window model cache
+// ---------------------------------------------------------------------------
+static int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
+static int64_t snap_param_bytes(const dvnr_t* h) { return align256((int64_t)h->nb * h->stride * h->ielem()); }
+
+static int64_t snap_bytes(const dvnr_t* h) {
+  return snap_param_bytes(h) + align256((int64_t)sizeof(BlockRange) * h->nb);
+}
+
+dvnr_status dvnr_cache_snapshot_bytes(const dvnr_t* h, int64_t* bytes) {
+  if (!h || !bytes) return fail(DVNR_E_INVALID, "null argument");
+  if (h->prec == Prec::F64) return fail(DVNR_E_UNSUPPORTED, "fp64 handles have no model cache");
+  *bytes = snap_bytes(h);
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_cache_bind(dvnr_t* h, int32_t capacity, void* buffer) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (h->prec == Prec::F64) return fail(DVNR_E_UNSUPPORTED, "fp64 handles have no model cache");
+  if (capacity < 0 || (capacity > 0 && !buffer)) return fail(DVNR_E_INVALID, "bad cache buffer");
+  if (((uintptr_t)buffer) % 256) return fail(DVNR_E_INVALID, "cache buffer must be 256-byte aligned");
+  h->cache_buf = (char*)buffer;
+  h->cache_cap = capacity;
+  h->cache_head = 0;
+  h->cache_count = 0;
+  h->cache_keys.assign(capacity, 0);
+  return DVNR_OK;
+}
+
+static int cache_slot_of(const dvnr_t* h, int64_t key) {
+  for (int k = 0; k < h->cache_count; ++k) {
+    const int slot = (h->cache_head + k) % h->cache_cap;
+    if (h->cache_keys[slot] == key) return slot;
+  }
+  return -1;
+}
+
+static ModelSrc cache_src(const dvnr_t* h, int slot) {
+  const char* base = h->cache_buf + (int64_t)slot * snap_bytes(h);
+  return ModelSrc{base, (const BlockRange*)(base + snap_param_bytes(h))};
+}
+
+dvnr_status dvnr_cache_push(dvnr_t* h, int64_t key, void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (!h->prepared) return fail(DVNR_E_STATE, "call dvnr_prepare first");
+  if (h->cache_cap < 1) return fail(DVNR_E_STATE, "no cache bound");
+  if (cache_slot_of(h, key) >= 0) return fail(DVNR_E_INVALID, "key already cached");
+  hipStream_t s = (hipStream_t)stream;
+  int slot;
+  if (h->cache_count < h->cache_cap) {
+    slot = (h->cache_head + h->cache_count) % h->cache_cap;
+    ++h->cache_count;
+  } else {  // full: the oldest snapshot makes room
+    slot = h->cache_head;
+    h->cache_head = (h->cache_head + 1) % h->cache_cap;
+  }
+  h->cache_keys[slot] = key;
+  const ModelSrc live = live_src(h);
+  char* dst = h->cache_buf + (int64_t)slot * snap_bytes(h);
+  HIPCHK(hipMemcpyAsync(dst, live.params, (size_t)((int64_t)h->nb * h->stride * h->ielem()), hipMemcpyDeviceToDevice,
+                        s));
+  HIPCHK(hipMemcpyAsync(dst + snap_param_bytes(h), live.range, sizeof(BlockRange) * h->nb, hipMemcpyDeviceToDevice,
+                        s));
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_cache_keys(const dvnr_t* h, int64_t* keys, int32_t* count) {
+  if (!h || !count) return fail(DVNR_E_INVALID, "null argument");
+  *count = h->cache_count;
+  if (keys)
+    for (int k = 0; k < h->cache_count; ++k) keys[k] = h->cache_keys[(h->cache_head + k) % h->cache_cap];
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_cache_decode(dvnr_t* h, int64_t key, int32_t block, float* out, void* stream) {
+  if (!out) return fail(DVNR_E_INVALID, "null output");
+  dvnr_status st = access_ready(h, block < 0 ? 0 : block);
+  if (st) return st;
+  if (block >= h->nb) return fail(DVNR_E_INVALID, "bad block");
+  const int slot = h->cache_cap > 0 ? cache_slot_of(h, key) : -1;
+  if (slot < 0) return fail(DVNR_E_INVALID, "key not cached");
+  return decode_impl(h, block, out, (hipStream_t)stream, cache_src(h, slot));
+}
+
+dvnr_status dvnr_cache_sample(dvnr_t* h, int64_t key, int32_t block, int64_t n, const float* coords, float* out,
+                              void* stream) {
+  dvnr_status st = access_ready(h, block);
+  if (st) return st;
+  if (n < 0 || (n > 0 && (!coords || !out))) return fail(DVNR_E_INVALID, "bad arguments");
+  const int slot = h->cache_cap > 0 ? cache_slot_of(h, key) : -1;
+  if (slot < 0) return fail(DVNR_E_INVALID, "key not cached");
+  return infer_coords(h, block, n, coords, out, (hipStream_t)stream, cache_src(h, slot));
 }
 
 dvnr_status dvnr_mse_fp64(dvnr_t* h, int32_t block, const float* decoded, double* sse, int64_t* count,

@@ -254,6 +254,40 @@ class DVNR:
         L.check(self.lib.dvnr_decode(self.h, block, out.data_ptr(), _stream_ptr(stream)))
         return out
 
+    # -- sliding-window model cache -------------------------------------------------
+    def cache_bind(self, capacity: int):
+        """Device buffer for `capacity` model snapshots (clears the cache)."""
+        nb = C.c_int64()
+        L.check(self.lib.dvnr_cache_snapshot_bytes(self.h, C.byref(nb)))
+        self._cache, off = _aligned_empty(int(capacity) * nb.value, self.device)
+        L.check(self.lib.dvnr_cache_bind(self.h, int(capacity), self._cache.data_ptr() + off if capacity else None))
+        return nb.value
+
+    def cache_push(self, key: int, stream=None):
+        L.check(self.lib.dvnr_cache_push(self.h, int(key), _stream_ptr(stream)))
+
+    def cache_keys(self):
+        """Cached keys, oldest first."""
+        n = C.c_int32()
+        L.check(self.lib.dvnr_cache_keys(self.h, None, C.byref(n)))
+        keys = (C.c_int64 * max(n.value, 1))()
+        L.check(self.lib.dvnr_cache_keys(self.h, keys, C.byref(n)))
+        return list(keys)[:n.value]
+
+    def cache_decode(self, key: int, block: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        d, _ = self.blocks[block]
+        if out is None:
+            out = torch.empty((d[2], d[1], d[0]), dtype=torch.float32, device=self.device)
+        L.check(self.lib.dvnr_cache_decode(self.h, int(key), block, out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def cache_sample(self, key: int, block: int, coords: torch.Tensor, stream=None) -> torch.Tensor:
+        coords = coords.to(device=self.device, dtype=torch.float32).contiguous()
+        out = torch.empty(coords.shape[0], dtype=torch.float32, device=self.device)
+        L.check(self.lib.dvnr_cache_sample(self.h, int(key), block, coords.shape[0], coords.data_ptr(),
+                                           out.data_ptr(), _stream_ptr(stream)))
+        return out
+
     def squared_error(self, block: int, decoded: torch.Tensor, stream=None):
         sse, cnt = C.c_double(), C.c_int64()
         L.check(self.lib.dvnr_mse_fp64(self.h, block, decoded.data_ptr(), C.byref(sse), C.byref(cnt),

@@ -136,3 +136,36 @@ def test_set_loss_validates_arguments():
         assert lib.dvnr_set_loss(h, 1, 0.15, 2.0) == 1
     finally:
         lib.dvnr_destroy(h)
+
+
+def test_model_cache_host_logic():
+    from paper_2304_10516_amd import _lib as L
+    for prec, elem in (("fp32", 4), ("mixed", 2)):
+        lib, code, h = _make(o.Encoding(4, 2, 12, 4, 2.0), o.MLP(1, 16),
+                             blocks=(((8, 8, 8), 0), ((5, 6, 7), 1)), precision=prec)
+        assert code == 0
+        try:
+            lib.dvnr_cache_snapshot_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+            lib.dvnr_cache_bind.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
+            lib.dvnr_cache_push.argtypes = [C.c_void_p, C.c_int64, C.c_void_p]
+            lib.dvnr_cache_keys.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+            sz = L.Sizes()
+            assert lib.dvnr_get_sizes(h, C.byref(sz)) == 0
+            nb = C.c_int64()
+            assert lib.dvnr_cache_snapshot_bytes(h, C.byref(nb)) == 0
+            align = lambda v: (v + 255) // 256 * 256
+            assert nb.value == align(sz.n_params * elem) + align(16 * 2)
+            assert lib.dvnr_cache_bind(h, 3, None) == 1          # buffer required
+            assert lib.dvnr_cache_bind(h, 3, 4096 + 8) == 1      # 256-byte alignment
+            assert lib.dvnr_cache_bind(h, -1, 4096) == 1
+            assert lib.dvnr_cache_bind(h, 3, 4096) == 0          # the pointer is only stored here
+            assert lib.dvnr_cache_push(h, 0, None) == 4          # not prepared: state error
+            n = C.c_int32(-1)
+            assert lib.dvnr_cache_keys(h, None, C.byref(n)) == 0 and n.value == 0
+            assert lib.dvnr_cache_bind(h, 0, None) == 0
+        finally:
+            lib.dvnr_destroy(h)
+    lib, code, h = _make(o.Encoding(3, 2, 6, 2, 2.0), o.MLP(1, 16), precision="fp64")
+    nb = C.c_int64()
+    assert lib.dvnr_cache_snapshot_bytes(h, C.byref(nb)) == 2
+    lib.dvnr_destroy(h)
