@@ -205,6 +205,40 @@ def run_timeseries(torch, DVNR, cfg, precision, n_timesteps, steps_per_t, seed=3
                 psnr=float(np.mean(psnr)), batch=batch)
 
 
+PHASE_KERNEL = {"scatter_priv": "k_scatter_priv", "scatter": "k_scatter", "adam": "k_adam", "encode": "k_encode",
+                "mlp": "k_mlp_train", "sample": "k_sort_place", "reduce": "k_reduce_slots"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "train_step_256cube_hbm_counters.md")
+
+
+def sources_digest():
+    """sha256 over the HIP sources of the library (names and contents, sorted)."""
+    import hashlib
+    d = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2304_10516_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        if name.endswith((".hip", ".h")):
+            d.update(name.encode())
+            with open(os.path.join(src, name), "rb") as f:
+                d.update(f.read())
+    return d.hexdigest()
+
+
+def measured_traffic(phase):
+    """HBM bytes per launch of the phase's kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the summary does not cover it
+    or the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if line.startswith("traffic-record:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if rec["kernel"] == PHASE_KERNEL.get(phase) and rec["sources_sha256"] == sources_digest():
+                        return rec["read_bytes"] + rec["write_bytes"]
+    except (OSError, ValueError, KeyError):
+        return None
+    return None
+
+
 def roofline_for(precision, res):
     ph = res["phase_ms"]
     dom = max(ph, key=lambda k: ph[k])
@@ -221,8 +255,8 @@ def roofline_for(precision, res):
                 "frac": tf / peak, "traffic": None}
     gbs = per_launch / (ph[dom] * 1e-3) / 1e9
     return {"kernel": dom, "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": gbs / PEAK_HBM_GBS, "traffic": None, "algorithmic_bytes_per_launch": per_launch,
-            "avg_launch_ms": ph[dom]}
+            "frac": gbs / PEAK_HBM_GBS, "traffic": measured_traffic(dom) if precision == "mixed" else None,
+            "algorithmic_bytes_per_launch": per_launch, "avg_launch_ms": ph[dom]}
 
 
 def cpu_baseline(cfg, vol, dims, n_samples):

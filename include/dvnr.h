@@ -211,6 +211,45 @@ dvnr_status dvnr_sample(dvnr_t* h, int32_t block, int64_t n, const float* coords
 /* Decode block b to its owned voxel grid at voxel centers (i+1/2)/n:
  * out device float [nz][ny][nx] (x fastest), de-normalized. */
 dvnr_status dvnr_decode(dvnr_t* h, int32_t block, float* out, void* stream);
+/* Direct volume rendering of one block's INR (Sec. IV, sample streaming).
+ * Rays of a pinhole camera, in the block's unit-cube coordinates, march front
+ * to back with step `step`: sample k of a ray sits at t_k = t0 + (k + 1/2) step
+ * from the eye, for every t_k before the ray leaves the cube ([t0, t1] is the
+ * ray's intersection with the cube, t0 >= 0).  A sample's de-normalized INR
+ * value v maps through the piecewise-linear transfer function tf (device float
+ * [n_tf][4] RGBA at n_tf equally spaced values over [tf_lo, tf_hi], v
+ * clamped); its opacity a, given for the length ref_step, becomes
+ * alpha = 1 - (1 - a)^(step / ref_step); then C += (1 - A) alpha rgb and
+ * A += (1 - A) alpha.  A ray stops after the sample that brings A to
+ * alpha_stop or above (1 disables early termination).
+ * Rays advance samples_per_round samples per round: coordinate generation,
+ * INR inference over the batch, shading (chunks of max_batch samples).
+ * Camera: pixel (i, j), row 0 at the top, looks along
+ * normalize(f + px r + py u) with f = normalize(center - eye),
+ * r = normalize(f x up), u = r x f, px = (2 (i + 1/2) / width - 1) tan(fovy/2)
+ * width / height, py = (1 - 2 (j + 1/2) / height) tan(fovy/2), all in float32
+ * round-to-nearest in that order (the sample count of a ray is decided by
+ * them).  image: device float [height][width][4], premultiplied (C, A).
+ * workspace: device, 256-byte aligned, dvnr_render_workspace_bytes bytes. */
+typedef struct dvnr_camera {
+  float eye[3], center[3], up[3];
+  float fovy_deg;        /* (0, 180) */
+  int32_t width, height; /* width * height <= 2^28 */
+} dvnr_camera;
+
+typedef struct dvnr_render_params {
+  float step;             /* > 0, unit-cube units */
+  float ref_step;         /* > 0, length the transfer-function opacity refers to */
+  float alpha_stop;       /* (0, 1] */
+  float tf_lo, tf_hi;     /* tf_hi > tf_lo */
+  int32_t n_tf;           /* >= 2 */
+  int32_t samples_per_round; /* 1 .. max_batch */
+} dvnr_render_params;
+
+dvnr_status dvnr_render_workspace_bytes(const dvnr_t* h, int32_t width, int32_t height, int64_t* bytes);
+dvnr_status dvnr_render(dvnr_t* h, int32_t block, const dvnr_camera* cam, const dvnr_render_params* params,
+                        const float* tf, void* workspace, float* image, void* stream);
+
 /* Sliding-window model cache (Sec. III-E weight caching; Sec. IV temporal
  * caching): snapshots of the trained models of past timesteps, kept on the
  * device so that any cached timestep can be decoded or sampled on demand.

@@ -25,7 +25,11 @@ What it computes, per partition block (one implicit neural representation,
   (`max_train_steps`, `should_stop`, `train_until`);
 * the L2 or L1 loss (Sec. III-E, Eq. (5)), the encoding backward
   (scatter-add), Adam with L2 weight decay (Sec. III-F) (`train_step`, `adam`);
-* decoding at voxel centers and PSNR over owned voxels (`decode`, `psnr`).
+* decoding at voxel centers and PSNR over owned voxels (`decode`, `psnr`);
+* the sliding-window cache needs no oracle of its own (a snapshot must decode
+  exactly as the live model did);
+* direct volume rendering of a block's INR by front-to-back ray marching
+  (`camera_rays`, `ray_box`, `transfer`, `render`; Sec. IV).
 
 Readings of points the paper leaves open are listed in the design notes and
 restated at each function.  Floating point: float64 throughout, except the
@@ -653,3 +657,122 @@ def apportion(voxels, total: int, unit: int = 256) -> np.ndarray:
     for b in order[:rem]:
         base[b] += 1
     return base * unit
+
+
+# --------------------------------------------------------------------------
+# Direct volume rendering of one block's INR (Sec. IV, sample streaming)
+# --------------------------------------------------------------------------
+@dataclass
+class Camera:
+    eye: tuple
+    center: tuple
+    up: tuple
+    fovy_deg: float
+    width: int
+    height: int
+
+
+def camera_rays(cam: Camera):
+    """Pinhole camera rays through pixel centers, in the block's unit-cube
+    coordinates.  Row 0 is the top of the image.  Evaluated in float32 with the
+    operation order below (the sample count of a ray is an integer decided by
+    these values, so the renderer computes them identically):
+      f = normalize(center - eye), r = normalize(f x up), u = r x f,
+      s = tan(fovy / 2) (float64, then rounded), a = width / height,
+      px = ((2 (i + 1/2) / width) - 1) * s * a, py = (1 - 2 (j + 1/2) / height) * s,
+      d = normalize(f + px r + py u)  (left to right, no fused multiply-add).
+    Returns (origin float32 [3], directions float32 [height * width, 3])."""
+    f32 = np.float32
+
+    def norm(v):
+        n = np.sqrt(f32(v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]).astype(f32)
+        return (v / n).astype(f32)
+
+    def cross(a, b):
+        return np.array([a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]], f32)
+
+    eye, ctr, up = (np.asarray(v, f32) for v in (cam.eye, cam.center, cam.up))
+    fw = norm((ctr - eye).astype(f32))
+    rt = norm(cross(fw, up))
+    uu = cross(rt, fw)
+    tan_h = f32(np.tan(np.radians(cam.fovy_deg) / 2.0))
+    aspect = f32(f32(cam.width) / f32(cam.height))
+    i = np.arange(cam.width, dtype=f32)
+    j = np.arange(cam.height, dtype=f32)
+    px = ((f32(2) * (i + f32(0.5)) / f32(cam.width) - f32(1)) * tan_h * aspect).astype(f32)
+    py = ((f32(1) - f32(2) * (j + f32(0.5)) / f32(cam.height)) * tan_h).astype(f32)
+    PX, PY = np.meshgrid(px, py)
+    d = np.empty((cam.height * cam.width, 3), f32)
+    for a in range(3):
+        d[:, a] = ((fw[a] + PX.ravel() * rt[a]).astype(f32) + PY.ravel() * uu[a]).astype(f32)
+    n = np.sqrt(((d[:, 0] * d[:, 0]).astype(f32) + d[:, 1] * d[:, 1]).astype(f32) + d[:, 2] * d[:, 2]).astype(f32)
+    return eye, (d / n[:, None]).astype(f32)
+
+
+def ray_box(origin, dirs):
+    """Entry and exit parameters of rays with the unit cube (slab method,
+    float32): per axis t = (0 - o) / d and (1 - o) / d; t0 = max(0, max of the
+    near values), t1 = min of the far values.  A ray misses when t1 <= t0."""
+    f32 = np.float32
+    o = np.asarray(origin, f32)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = (f32(1) / dirs).astype(f32)
+        ta = ((f32(0) - o) * inv).astype(f32)
+        tb = ((f32(1) - o) * inv).astype(f32)
+    near = np.minimum(ta, tb)
+    far = np.maximum(ta, tb)
+    t0 = np.maximum(np.max(near, axis=1), f32(0))
+    t1 = np.min(far, axis=1)
+    return t0.astype(f32), t1.astype(f32)
+
+
+def sample_params(t0, t1, dt: float, k):
+    """t_k = t0 + (k + 1/2) dt in float32; the sample exists iff t_k < t1."""
+    f32 = np.float32
+    tk = (t0 + (f32(k) + f32(0.5)) * f32(dt)).astype(f32)
+    return tk, tk < t1
+
+
+def transfer(tf: np.ndarray, lo: float, hi: float, v):
+    """Piecewise-linear transfer function: tf [n][4] RGBA at n equally spaced
+    values over [lo, hi]; v is clamped to the range."""
+    n = tf.shape[0]
+    s = np.clip((np.asarray(v, np.float64) - lo) / (hi - lo), 0.0, 1.0) * (n - 1)
+    i = np.minimum(np.floor(s).astype(np.int64), n - 2)
+    w = (s - i)[:, None]
+    return (1.0 - w) * tf[i] + w * tf[i + 1]
+
+
+def render(lay: Layout, params, vmin: float, vmax: float, cam: Camera, tf: np.ndarray, lo: float, hi: float,
+           dt: float, ref_dt: float, alpha_stop: float = 1.0):
+    """Front-to-back emission-absorption ray marching through the block's INR.
+
+    Sample k of a ray sits at x = o + t_k d; its value is the de-normalized
+    INR output; the transfer function gives (r, g, b, a) with a the opacity
+    over a reference length ref_dt, corrected to the step: alpha = 1 - (1 - a)^(dt / ref_dt).
+    C += (1 - A) alpha rgb, A += (1 - A) alpha, in sample order; a ray stops
+    after the sample that brings A to alpha_stop or above.  Returns a float64
+    image [height][width][4] of premultiplied (C, A)."""
+    f32 = np.float32
+    o, d = camera_rays(cam)
+    t0, t1 = ray_box(o, d)
+    n_rays = d.shape[0]
+    out = np.zeros((n_rays, 4))
+    done = ~(t1 > t0)
+    k = 0
+    while not done.all():
+        live = np.nonzero(~done)[0]
+        tk, ok = sample_params(t0[live], t1[live], dt, k)
+        done[live[~ok]] = True
+        live, tk = live[ok], tk[ok]
+        if live.size:
+            x = (o[None, :] + (tk[:, None] * d[live]).astype(f32)).astype(f32)
+            v = vmin + infer(lay, params, x) * (vmax - vmin)
+            c = transfer(tf, lo, hi, v)
+            alpha = 1.0 - (1.0 - np.clip(c[:, 3], 0.0, 1.0)) ** (dt / ref_dt)
+            A = out[live, 3]
+            out[live, :3] += ((1.0 - A) * alpha)[:, None] * c[:, :3]
+            out[live, 3] = A + (1.0 - A) * alpha
+            done[live[out[live, 3] >= alpha_stop]] = True
+        k += 1
+    return out.reshape(cam.height, cam.width, 4)

@@ -48,6 +48,16 @@ class StopPolicy(C.Structure):
                 ("window", C.c_int32), ("check_every", C.c_int32)]
 
 
+class Camera(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("center", C.c_float * 3), ("up", C.c_float * 3), ("fovy_deg", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class RenderParams(C.Structure):
+    _fields_ = [("step", C.c_float), ("ref_step", C.c_float), ("alpha_stop", C.c_float), ("tf_lo", C.c_float),
+                ("tf_hi", C.c_float), ("n_tf", C.c_int32), ("samples_per_round", C.c_int32)]
+
+
 class DvnrError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"dvnr error {code}: {msg}")
@@ -86,6 +96,8 @@ SIGNATURES = {
     "dvnr_set_option": [P, C.c_char_p, I64],
     "dvnr_set_loss": [P, I32, C.c_double, C.c_double],
     "dvnr_cache_snapshot_bytes": [P, C.POINTER(C.c_int64)],
+    "dvnr_render_workspace_bytes": [P, I32, I32, C.POINTER(C.c_int64)],
+    "dvnr_render": [P, I32, C.POINTER(Camera), C.POINTER(RenderParams), VP, VP, VP, VP],
     "dvnr_cache_bind": [P, I32, VP],
     "dvnr_cache_push": [P, I64, VP],
     "dvnr_cache_keys": [P, C.POINTER(C.c_int64), C.POINTER(C.c_int32)],

@@ -854,6 +854,8 @@ dvnr_status dvnr_draw_training_samples(dvnr_t* h, int32_t block, int64_t step, i
 }
 
 // INR output at `n` coordinates of block b (chunks of max_batch), de-normalized.
+static int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
 // Parameters a query reads: the inference copy of every block (the fp16 / bf16
 // working copy for mixed precision, fp32 masters otherwise) and the block
 // value ranges; the live model or a cached snapshot.
@@ -930,10 +932,84 @@ dvnr_status dvnr_decode(dvnr_t* h, int32_t block, float* out, void* stream) {
 }
 
 // ---------------------------------------------------------------------------
+// Direct volume rendering (sample streaming)
+// ---------------------------------------------------------------------------
+static int64_t render_ws_bytes(int64_t n) {
+  // directions [n][3], (t0, t1) [n][2], two active-ray lists [n], two counters
+  return align256(12 * n) + align256(8 * n) + 2 * align256(4 * n) + 256;
+}
+
+dvnr_status dvnr_render_workspace_bytes(const dvnr_t* h, int32_t width, int32_t height, int64_t* bytes) {
+  if (!h || !bytes) return fail(DVNR_E_INVALID, "null argument");
+  if (width < 1 || height < 1 || (int64_t)width * height > (1 << 28)) return fail(DVNR_E_INVALID, "bad image size");
+  *bytes = render_ws_bytes((int64_t)width * height);
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_render(dvnr_t* h, int32_t block, const dvnr_camera* cam, const dvnr_render_params* rp,
+                        const float* tf, void* workspace, float* image, void* stream) {
+  try {
+    dvnr_status st = access_ready(h, block);
+    if (st) return st;
+    if (!cam || !rp || !tf || !workspace || !image) return fail(DVNR_E_INVALID, "null argument");
+    if (cam->width < 1 || cam->height < 1 || (int64_t)cam->width * cam->height > (1 << 28))
+      return fail(DVNR_E_INVALID, "bad image size");
+    if (!(cam->fovy_deg > 0.0f && cam->fovy_deg < 180.0f)) return fail(DVNR_E_INVALID, "fovy must be in (0, 180)");
+    if (!(rp->step > 0.0f) || !(rp->ref_step > 0.0f) || rp->n_tf < 2 || !(rp->tf_hi > rp->tf_lo) ||
+        !(rp->alpha_stop > 0.0f && rp->alpha_stop <= 1.0f) || rp->samples_per_round < 1 ||
+        rp->samples_per_round > h->max_batch)
+      return fail(DVNR_E_INVALID, "bad render parameters");
+    if (((uintptr_t)workspace) % 256) return fail(DVNR_E_INVALID, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = (int64_t)cam->width * cam->height;
+    char* ws = (char*)workspace;
+    float* dirs = (float*)ws;
+    float* t01 = (float*)(ws + align256(12 * n));
+    int32_t* list[2] = {(int32_t*)(ws + align256(12 * n) + align256(8 * n)),
+                        (int32_t*)(ws + align256(12 * n) + align256(8 * n) + align256(4 * n))};
+    int32_t* counters = (int32_t*)(ws + align256(12 * n) + align256(8 * n) + 2 * align256(4 * n));
+    RayCamera rc;
+    for (int a = 0; a < 3; ++a) {
+      rc.eye[a] = cam->eye[a];
+      rc.center[a] = cam->center[a];
+      rc.up[a] = cam->up[a];
+    }
+    rc.tan_h = (float)std::tan((double)cam->fovy_deg * 3.14159265358979323846 / 360.0);
+    const int S = rp->samples_per_round;
+    const float opacity_exp = (float)((double)rp->step / (double)rp->ref_step);
+    const float tf_inv = (float)(1.0 / ((double)rp->tf_hi - (double)rp->tf_lo));
+    const ModelSrc src = live_src(h);
+    HIPCHK(launch_zero(counters, 2 * sizeof(int32_t), s));
+    HIPCHK(launch_ray_init(rc, cam->width, cam->height, dirs, t01, image, list[0], counters, s));
+    int32_t n_active = 0;
+    HIPCHK(hipMemcpyAsync(&n_active, counters, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int chunk = std::max<int64_t>(1, h->max_batch / S);
+    int cur = 0;
+    for (int k_base = 0; n_active > 0; k_base += S) {
+      HIPCHK(launch_zero(counters + 1, sizeof(int32_t), s));
+      for (int c0 = 0; c0 < n_active; c0 += chunk) {
+        const int cn = std::min(chunk, n_active - c0);
+        HIPCHK(launch_ray_gen(rc, list[cur] + c0, cn, k_base, S, rp->step, dirs, t01, h->d_coords(), s));
+        st = infer_coords(h, block, (int64_t)cn * S, h->d_coords(), h->d_target(), s, src);
+        if (st) return st;
+        HIPCHK(launch_ray_shade(list[cur] + c0, cn, k_base, S, rp->step, opacity_exp, rp->alpha_stop, t01,
+                                h->d_target(), tf, rp->n_tf, rp->tf_lo, tf_inv, image, list[1 - cur], counters + 1,
+                                s));
+      }
+      HIPCHK(hipMemcpyAsync(&n_active, counters + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      cur = 1 - cur;
+    }
+    return DVNR_OK;
+  } catch (...) {
+    return fail(DVNR_E_INVALID, "render failed");
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Sliding-window model cache
 // ---------------------------------------------------------------------------
-static int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
-
 static int64_t snap_param_bytes(const dvnr_t* h) { return align256((int64_t)h->nb * h->stride * h->ielem()); }
 
 static int64_t snap_bytes(const dvnr_t* h) {

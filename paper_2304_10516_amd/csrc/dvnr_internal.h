@@ -156,6 +156,20 @@ hipError_t launch_decode_fused(Prec p, const LevelDesc& ld, const MlpDesc& md, c
                                const BlockRange* range, int block, const int32_t* dims, const void* table,
                                const void* wsrc, int64_t n_table_params, float* out, hipStream_t s);
 
+// Direct volume rendering by sample streaming (one block's unit cube).
+struct RayCamera {
+  float eye[3], center[3], up[3];
+  float tan_h;                 // tan(vertical field of view / 2)
+};
+hipError_t launch_ray_init(const RayCamera& cam, int width, int height, float* dirs, float* t01, float* rgba,
+                           int32_t* active, int32_t* counter, hipStream_t s);
+hipError_t launch_ray_gen(const RayCamera& cam, const int32_t* active, int n_rays, int k_base, int S, float dt,
+                          const float* dirs, const float* t01, float* coords, hipStream_t s);
+hipError_t launch_ray_shade(const int32_t* active, int n_rays, int k_base, int S, float dt, float opacity_exp,
+                            float alpha_stop, const float* t01, const float* values, const float* tf, int n_tf,
+                            float tf_lo, float tf_inv_range, float* rgba, int32_t* next, int32_t* next_count,
+                            hipStream_t s);
+
 hipError_t launch_voxel_coords(const BlockMeta* meta, int block, int64_t first, int64_t n, float* coords,
                                hipStream_t s);
 hipError_t launch_mse(const BlockMeta* meta, int block, const float* decoded, double* acc, hipStream_t s);

@@ -254,6 +254,27 @@ class DVNR:
         L.check(self.lib.dvnr_decode(self.h, block, out.data_ptr(), _stream_ptr(stream)))
         return out
 
+    # -- direct volume rendering ----------------------------------------------------
+    def render(self, block: int, eye, center, up, fovy_deg: float, width: int, height: int, tf: torch.Tensor,
+               tf_range, step: float, ref_step: float | None = None, alpha_stop: float = 1.0,
+               samples_per_round: int = 64, stream=None) -> torch.Tensor:
+        """Front-to-back ray marching of block `block`'s INR through a pinhole
+        camera (unit-cube coordinates of the block); tf: [n][4] RGBA over
+        tf_range.  Returns the premultiplied RGBA image [height][width][4]."""
+        cam = L.Camera((C.c_float * 3)(*eye), (C.c_float * 3)(*center), (C.c_float * 3)(*up), float(fovy_deg),
+                       int(width), int(height))
+        tf = tf.to(device=self.device, dtype=torch.float32).contiguous()
+        rp = L.RenderParams(float(step), float(ref_step if ref_step is not None else step), float(alpha_stop),
+                            float(tf_range[0]), float(tf_range[1]), int(tf.shape[0]), int(samples_per_round))
+        nb = C.c_int64()
+        L.check(self.lib.dvnr_render_workspace_bytes(self.h, int(width), int(height), C.byref(nb)))
+        ws, off = _aligned_empty(nb.value, self.device)
+        img = torch.empty((height, width, 4), dtype=torch.float32, device=self.device)
+        L.check(self.lib.dvnr_render(self.h, block, C.byref(cam), C.byref(rp), tf.data_ptr(), ws.data_ptr() + off,
+                                     img.data_ptr(), _stream_ptr(stream)))
+        self._render_ws = ws  # kept alive until the stream has used it
+        return img
+
     # -- sliding-window model cache -------------------------------------------------
     def cache_bind(self, capacity: int):
         """Device buffer for `capacity` model snapshots (clears the cache)."""

@@ -241,17 +241,26 @@ def test_sorted_sampling_gradient_parity_fine_levels(precision):
     gg = model.block_grads(0).cpu().numpy()
     nt = lay.n_table_params
     assert abs(loss[0, 0].item() - L) <= (1e-5 if precision == "fp32" else 1e-2) * L
-    # fp32: max-element bar.  mixed: the scatter is the same fp32 code (pinned by the
-    # fp32 case); what differs is the bf16 MLP backward, whose per-sample rounding
-    # (~2^-8) meets heavy cancellation in the coarse-level vertex sums, so the bar
-    # there is on the 2-norm relative error
-    err = normwise if precision == "fp32" else (
-        lambda a, b: float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b)))
-    tol = 1e-5 if precision == "fp32" else 3e-2
-    for l, lvl in enumerate(lay.levels):
-        a, b_ = lvl.off * 2, (lvl.off + lvl.E) * 2
-        assert err(gg[a:b_], g[a:b_]) <= tol, f"level {l} table gradient"
-    assert err(gg[nt:], g[nt:]) <= tol, "weight gradient"
+    if precision == "fp32":
+        for l, lvl in enumerate(lay.levels):
+            a, b_ = lvl.off * 2, (lvl.off + lvl.E) * 2
+            assert normwise(gg[a:b_], g[a:b_]) <= 1e-5, f"level {l} table gradient"
+        assert normwise(gg[nt:], g[nt:]) <= 1e-5, "weight gradient"
+        return
+    # mixed: the scatter is the same fp32 code (pinned by the fp32 case); what
+    # differs is the bf16 MLP backward, each dL/dy carrying a relative error of
+    # order 1e-2.  A table entry sums w * dL/dy over its samples with heavy
+    # cancellation on coarse levels, so the bar is the conditioning bound of a
+    # sum: |error| <= 2e-2 * sum |w * dL/dy| (the oracle's encoding backward of |dL/dy|)
+    W = o.mlp_weights(lay, pref)
+    y = o.encode(lay, pref, x)
+    out, acts = o.mlp_forward(W, y)
+    dy, _ = o.mlp_backward(W, acts, (2.0 / len(x)) * (out[:, 0] - tgt)[:, None])
+    bound = o.encode_backward(lay, x, np.abs(dy))
+    excess = np.abs(gg[:nt].astype(np.float64) - g[:nt]) - 2e-2 * bound
+    say(f"mixed table gradient: worst excess over the bound {excess.max():.3e} (bound max {bound.max():.3e})")
+    assert np.all(excess <= 1e-12), "table gradient outside the conditioning bound"
+    assert normwise(gg[nt:], g[nt:]) <= 3e-2, "weight gradient"
 
 
 def test_adam_update_parity_c1():
