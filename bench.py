@@ -148,6 +148,22 @@ def run_precision(torch, DVNR, cfg, blocks, vols, precision, steps, warmup, seed
             s, c = model.squared_error(b, outs[b], stream=stream)
             sse += s
             cnt += c
+        render = None
+        if len(blocks) == 1:
+            # sample-streaming direct volume rendering of the trained block, 1024^2 rays
+            lo, hi = model.ranges()
+            tf = torch.tensor([[0.05, 0.1, 0.6, 0.0], [0.1, 0.6, 0.7, 0.05], [0.9, 0.8, 0.2, 0.3],
+                               [1.0, 0.3, 0.1, 0.8]], dtype=torch.float32)
+            kw = dict(eye=(1.6, 1.3, 2.1), center=(0.5, 0.5, 0.5), up=(0.0, 1.0, 0.0), fovy_deg=45.0, tf=tf,
+                      tf_range=(lo[0], hi[0]), step=1.0 / 512, ref_step=1.0 / 256, samples_per_round=64,
+                      stream=stream)
+            model.render(0, width=256, height=256, **kw)  # warm
+            r0 = time.perf_counter()
+            model.render(0, width=1024, height=1024, **kw)
+            r_ms = (time.perf_counter() - r0) * 1e3
+            render = {"width": 1024, "height": 1024, "step": 1.0 / 512, "ms": r_ms,
+                      "samples": model.last_render_samples,
+                      "samples_per_s": model.last_render_samples / (r_ms * 1e-3)}
         model.sync(stream=stream)
     ms = (t1 - t0) * 1e3 / steps
     lossv = loss.float().mean(dim=1).cpu().numpy()
@@ -155,7 +171,7 @@ def run_precision(torch, DVNR, cfg, blocks, vols, precision, steps, warmup, seed
                decode_voxels_per_s=cnt / (dec_ms * 1e-3), psnr=float(10 * np.log10(cnt / sse)),
                loss_first=float(lossv[0]), loss_last=float(lossv[-1]),
                phase_ms={k: v / max(nsteps, 1) for k, v in phases.items()}, n_params=model.sizes.n_params,
-               bins_per_axis=bins, priv_levels=priv, batch=batch)
+               bins_per_axis=bins, priv_levels=priv, batch=batch, render=render)
     log(f"[bench] {precision}: {ms:.3f} ms/step, {res['samples_per_s'] / 1e6:.1f} M samples/s, "
         f"psnr {res['psnr']:.2f} dB, decode {dec_ms:.2f} ms, bins {bins}^3, privatized levels {priv}, phases " +
         ", ".join(f"{k} {v:.3f}" for k, v in res["phase_ms"].items()))
@@ -353,6 +369,8 @@ def main():
         "phase_ms": head["phase_ms"],
         "roofline": roofline_for(head_prec, head),
     }
+    if head.get("render"):
+        out["render"] = head["render"]
     if "fp32" in results and "mixed" in results:
         f = results["fp32"]
         out["fp32_plain"] = {"samples_per_s": f["samples_per_s"], "ms_per_step": f["ms_per_step"],

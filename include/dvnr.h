@@ -230,7 +230,9 @@ dvnr_status dvnr_decode(dvnr_t* h, int32_t block, float* out, void* stream);
  * width / height, py = (1 - 2 (j + 1/2) / height) tan(fovy/2), all in float32
  * round-to-nearest in that order (the sample count of a ray is decided by
  * them).  image: device float [height][width][4], premultiplied (C, A).
- * workspace: device, 256-byte aligned, dvnr_render_workspace_bytes bytes. */
+ * workspace: device, 256-byte aligned, dvnr_render_workspace_bytes bytes.
+ * samples_out (host, may be NULL): samples generated and inferred, the
+ * rounds' active rays times samples_per_round.  Synchronizes `stream`. */
 typedef struct dvnr_camera {
   float eye[3], center[3], up[3];
   float fovy_deg;        /* (0, 180) */
@@ -248,7 +250,7 @@ typedef struct dvnr_render_params {
 
 dvnr_status dvnr_render_workspace_bytes(const dvnr_t* h, int32_t width, int32_t height, int64_t* bytes);
 dvnr_status dvnr_render(dvnr_t* h, int32_t block, const dvnr_camera* cam, const dvnr_render_params* params,
-                        const float* tf, void* workspace, float* image, void* stream);
+                        const float* tf, void* workspace, float* image, int64_t* samples_out, void* stream);
 
 /* Sliding-window model cache (Sec. III-E weight caching; Sec. IV temporal
  * caching): snapshots of the trained models of past timesteps, kept on the

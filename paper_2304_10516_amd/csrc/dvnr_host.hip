@@ -947,7 +947,7 @@ dvnr_status dvnr_render_workspace_bytes(const dvnr_t* h, int32_t width, int32_t 
 }
 
 dvnr_status dvnr_render(dvnr_t* h, int32_t block, const dvnr_camera* cam, const dvnr_render_params* rp,
-                        const float* tf, void* workspace, float* image, void* stream) {
+                        const float* tf, void* workspace, float* image, int64_t* samples_out, void* stream) {
   try {
     dvnr_status st = access_ready(h, block);
     if (st) return st;
@@ -986,8 +986,10 @@ dvnr_status dvnr_render(dvnr_t* h, int32_t block, const dvnr_camera* cam, const 
     HIPCHK(hipStreamSynchronize(s));
     const int chunk = std::max<int64_t>(1, h->max_batch / S);
     int cur = 0;
+    int64_t generated = 0;
     for (int k_base = 0; n_active > 0; k_base += S) {
       HIPCHK(launch_zero(counters + 1, sizeof(int32_t), s));
+      generated += (int64_t)n_active * S;
       for (int c0 = 0; c0 < n_active; c0 += chunk) {
         const int cn = std::min(chunk, n_active - c0);
         HIPCHK(launch_ray_gen(rc, list[cur] + c0, cn, k_base, S, rp->step, dirs, t01, h->d_coords(), s));
@@ -1001,6 +1003,7 @@ dvnr_status dvnr_render(dvnr_t* h, int32_t block, const dvnr_camera* cam, const 
       HIPCHK(hipStreamSynchronize(s));
       cur = 1 - cur;
     }
+    if (samples_out) *samples_out = generated;
     return DVNR_OK;
   } catch (...) {
     return fail(DVNR_E_INVALID, "render failed");

@@ -270,9 +270,10 @@ class DVNR:
         L.check(self.lib.dvnr_render_workspace_bytes(self.h, int(width), int(height), C.byref(nb)))
         ws, off = _aligned_empty(nb.value, self.device)
         img = torch.empty((height, width, 4), dtype=torch.float32, device=self.device)
+        n = C.c_int64()
         L.check(self.lib.dvnr_render(self.h, block, C.byref(cam), C.byref(rp), tf.data_ptr(), ws.data_ptr() + off,
-                                     img.data_ptr(), _stream_ptr(stream)))
-        self._render_ws = ws  # kept alive until the stream has used it
+                                     img.data_ptr(), C.byref(n), _stream_ptr(stream)))
+        self.last_render_samples = n.value
         return img
 
     # -- sliding-window model cache -------------------------------------------------

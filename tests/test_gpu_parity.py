@@ -248,19 +248,22 @@ def test_sorted_sampling_gradient_parity_fine_levels(precision):
         assert normwise(gg[nt:], g[nt:]) <= 1e-5, "weight gradient"
         return
     # mixed: the scatter is the same fp32 code (pinned by the fp32 case); what
-    # differs is the bf16 MLP backward, each dL/dy carrying a relative error of
-    # order 1e-2.  A table entry sums w * dL/dy over its samples with heavy
-    # cancellation on coarse levels, so the bar is the conditioning bound of a
-    # sum: |error| <= 2e-2 * sum |w * dL/dy| (the oracle's encoding backward of |dL/dy|)
+    # differs is the bf16 MLP.  Its outputs carry the stated 1e-2 relative error,
+    # which reaches dL/do = 2 (o - y) / n through the residual: relative to the
+    # residual it is 1e-2 * |o| / |o - y|.  The bar on each level's (and the
+    # weights') 2-norm relative error is twice that ratio's rms value.
     W = o.mlp_weights(lay, pref)
-    y = o.encode(lay, pref, x)
-    out, acts = o.mlp_forward(W, y)
-    dy, _ = o.mlp_backward(W, acts, (2.0 / len(x)) * (out[:, 0] - tgt)[:, None])
-    bound = o.encode_backward(lay, x, np.abs(dy))
-    excess = np.abs(gg[:nt].astype(np.float64) - g[:nt]) - 2e-2 * bound
-    say(f"mixed table gradient: worst excess over the bound {excess.max():.3e} (bound max {bound.max():.3e})")
-    assert np.all(excess <= 1e-12), "table gradient outside the conditioning bound"
-    assert normwise(gg[nt:], g[nt:]) <= 3e-2, "weight gradient"
+    out, _ = o.mlp_forward(W, o.encode(lay, pref, x))
+    kappa = float(np.sqrt(np.mean(out[:, 0] ** 2) / np.mean((out[:, 0] - tgt) ** 2)))
+    tol = 2e-2 * max(1.0, kappa)
+    rel2 = lambda a, b: float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+    worst = max(rel2(gg[l.off * 2:(l.off + l.E) * 2], g[l.off * 2:(l.off + l.E) * 2]) for l in lay.levels)
+    say(f"mixed gradients: worst level 2-norm error {worst:.3e}, weights {rel2(gg[nt:], g[nt:]):.3e}, "
+        f"bar {tol:.3e} (|o|/|o - y| = {kappa:.2f})")
+    for l, lvl in enumerate(lay.levels):
+        a, b_ = lvl.off * 2, (lvl.off + lvl.E) * 2
+        assert rel2(gg[a:b_], g[a:b_]) <= tol, f"level {l} table gradient"
+    assert rel2(gg[nt:], g[nt:]) <= tol, "weight gradient"
 
 
 def test_adam_update_parity_c1():

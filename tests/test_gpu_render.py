@@ -84,8 +84,9 @@ def test_render_early_termination():
     ref_img = o.render(lay, pe, vmin, vmax, cam, tf, lo, hi, dt, ref, alpha_stop=0.8)
     err = np.abs(img - ref_img)
     stopped = ref_img[..., 3] >= 0.8
-    say(f"stopped pixels {stopped.mean():.2f}, max abs diff {err.max():.3e}")
-    assert stopped.mean() > 0.2
+    covered = ref_img[..., 3] > 0
+    say(f"covered pixels {covered.mean():.2f}, stopped {stopped.mean():.2f}, max abs diff {err.max():.3e}")
+    assert stopped.sum() > 0.5 * covered.sum() > 0
     assert np.all(img[..., 3][stopped] >= 0.8)
     assert np.mean(err.max(axis=-1) <= 5e-5) >= 0.99
     assert err.max() <= 0.2 + 5e-5  # the opacity left at the limit bounds a shifted stopping sample
