@@ -136,6 +136,7 @@ __device__ __forceinline__ uint32_t xcc_id() {
 // Returns false for idle workgroups.  Levels of the launch are [l0, l0 + L).
 __device__ __forceinline__ bool level_major_item(int wg, int l0, int L, int n_tiles, int xcd_map, int& tile,
                                                  int& level) {
+  if (L <= 0) return false;
   if (xcd_map && L >= 8) {
     const int lp = (L + 7) / 8;
     const int x = wg & 7, r = wg >> 3;
@@ -162,6 +163,7 @@ __device__ __forceinline__ bool level_major_item(int wg, int l0, int L, int n_ti
 }
 
 __host__ __device__ inline int level_major_grid(int L, int n_tiles, int xcd_map) {
+  if (L <= 0 || n_tiles <= 0) return 0;
   if (xcd_map && L >= 8) return 8 * ((L + 7) / 8) * n_tiles;
   if (xcd_map) {
     const int nx_min = 8 / L;  // XCDs of the least-served level

@@ -408,6 +408,7 @@ hipError_t launch_scatter_priv(const LevelDesc& ld, int l0, int l1, int B, int n
   const int nlev = l1 - l0;
   if (nlev <= 0) return hipSuccess;
   const int grid = level_major_grid(nlev, n_blocks * B * B * B, xcd_map);
+  if (grid <= 0) return hipSuccess;
   switch (ld.F) {
     case 1: hipLaunchKernelGGL(k_scatter_priv<1>, dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, n_blocks, meta, plan, bin_start, coords, dfeat, ls, grad, xcd_map); break;
     case 2: hipLaunchKernelGGL(k_scatter_priv<2>, dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, n_blocks, meta, plan, bin_start, coords, dfeat, ls, grad, xcd_map); break;
