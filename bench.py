@@ -226,16 +226,18 @@ PHASE_KERNEL = {"scatter_priv": "k_scatter_priv", "scatter": "k_scatter", "adam"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "train_step_256cube_hbm_counters.md")
 
 
-def sources_digest():
-    """sha256 over the HIP sources of the library (names and contents, sorted)."""
+KERNEL_SOURCES = {"k_scatter_priv": ["k_sort.hip", "dvnr_device.h", "dvnr_internal.h"]}
+
+
+def sources_digest(kernel):
+    """sha256 over the source files that define `kernel` (names and contents)."""
     import hashlib
     d = hashlib.sha256()
     src = os.path.join(ROOT, "paper_2304_10516_amd", "csrc")
-    for name in sorted(os.listdir(src)):
-        if name.endswith((".hip", ".h")):
-            d.update(name.encode())
-            with open(os.path.join(src, name), "rb") as f:
-                d.update(f.read())
+    for name in KERNEL_SOURCES[kernel]:
+        d.update(name.encode())
+        with open(os.path.join(src, name), "rb") as f:
+            d.update(f.read())
     return d.hexdigest()
 
 
@@ -248,7 +250,7 @@ def measured_traffic(phase):
             for line in f:
                 if line.startswith("traffic-record:"):
                     rec = json.loads(line.split(":", 1)[1])
-                    if rec["kernel"] == PHASE_KERNEL.get(phase) and rec["sources_sha256"] == sources_digest():
+                    if rec["kernel"] == PHASE_KERNEL.get(phase) and rec["sources_sha256"] == sources_digest(rec["kernel"]):
                         return rec["read_bytes"] + rec["write_bytes"]
     except (OSError, ValueError, KeyError):
         return None

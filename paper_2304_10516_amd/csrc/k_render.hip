@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_ray_gen(RayCamera cam, const int32_t* _
                                                  const float* __restrict__ t01, float* __restrict__ coords) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int64_t)n_rays * S) return;
-  const int r = (int)(q / S), jj = (int)(q % S);
+  const int jj = (int)(q / n_rays), r = (int)(q % n_rays);  // sample-major: shading reads coalesced
   const int p = active[r];
   const float tk = sample_t(t01[2 * p], k_base + jj, dt);
   const bool ok = tk < t01[2 * p + 1];
@@ -100,8 +100,9 @@ __global__ __launch_bounds__(256) void k_ray_gen(RayCamera cam, const int32_t* _
     coords[3 * q + a] = ok ? __fadd_rn(cam.eye[a], __fmul_rn(tk, dirs[3 * p + a])) : 0.5f;
 }
 
-// One lane per ray; values[r * S + jj] is the de-normalized INR output of
-// sample k_base + jj of active ray r.
+// One lane per ray; values[jj * n_rays + r] is the de-normalized INR output of
+// sample k_base + jj of active ray r (sample-major, so a wave's reads of one
+// sample index are contiguous).
 __global__ __launch_bounds__(256) void k_ray_shade(const int32_t* __restrict__ active, int n_rays, int k_base, int S,
                                                    float dt, float opacity_exp, float alpha_stop,
                                                    const float* __restrict__ t01, const float* __restrict__ values,
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(256) void k_ray_shade(const int32_t* __restrict__ a
       done = true;
       break;
     }
-    const float v = values[(int64_t)r * S + jj];
+    const float v = values[(int64_t)jj * n_rays + r];
     const float s = fminf(fmaxf((v - tf_lo) * tf_inv_range, 0.0f), 1.0f) * (float)(n_tf - 1);
     const int i = min((int)floorf(s), n_tf - 2);
     const float w = s - (float)i;
