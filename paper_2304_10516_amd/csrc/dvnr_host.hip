@@ -83,6 +83,7 @@ struct dvnr {
   int spatial_sort = 0;
   int priv_levels = -1;  // -1: chosen per plan
   int sort_B = 0, priv_L = 0, n_groups = 0;
+  int priv_small = 0, priv_direct = 0;  // LDS classes: small [0, priv_small), large up to priv_direct, then direct
   std::vector<Tile> hgroups;
   std::vector<int32_t> hgrange;
   int64_t o_groups = 0, o_grange = 0, o_counts = 0, o_binstart = 0, o_totals = 0, max_groups = 0;
@@ -121,17 +122,9 @@ struct dvnr {
   size_t pelem() const { return prec == Prec::F64 ? 8 : 4; }
   size_t ielem() const { return prec == Prec::MIXED ? 2 : pelem(); }  // inference copy element
 
-  // second stream (default priority) on which the fine levels' backward runs
-  // concurrently with the coarse levels', forked and joined with events
-  int scatter_split = 0;  // first level of the concurrent part; -1: the 5 finest, 0: off (default: measured faster)
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~dvnr() {
     if (graph) (void)hipGraphExecDestroy(graph);
     for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_join) (void)hipEventDestroy(ev_join);
-    if (side) (void)hipStreamDestroy(side);
   }
 };
 
@@ -529,6 +522,26 @@ static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_
   // XCD on its own levels' tables (a separate direct launch over the fine
   // levels would spread them over every XCD).
   const int pl = h->enc.n_levels;
+  // LDS class of each level from a bound on its bin box: ceil((R - 1) / B) + 2
+  // cells per axis (the analytic box spans at most ceil((R - 1) / B) + 1)
+  // levels are ordered by resolution: the small class is a prefix, direct a suffix
+  {
+    int a = 0;
+    while (a < h->enc.n_levels) {
+      const int64_t side = (h->ld.R[a] - 1 + B - 1) / B + 2, F = h->enc.n_features;
+      if (side * side * side > kPrivCellsSmall || (side + 1) * (side + 1) * (side + 1) * F > kPrivVertFloatsSmall)
+        break;
+      ++a;
+    }
+    h->priv_small = a;
+    int c = a;
+    while (c < h->enc.n_levels) {
+      const int64_t side = (h->ld.R[c] - 1 + B - 1) / B + 2, F = h->enc.n_features;
+      if (side * side * side > kPrivCells || (side + 1) * (side + 1) * (side + 1) * F > kPrivVertFloats) break;
+      ++c;
+    }
+    h->priv_direct = c;
+  }
   h->priv_L = h->priv_levels >= 0 ? std::min(h->priv_levels, h->enc.n_levels) : pl;
   HIPCHK(hipMemcpyAsync(h->d_plan(), h->hplan.data(), sizeof(BlockPlan) * h->nb, hipMemcpyHostToDevice, s));
   if (h->n_tiles)
@@ -612,30 +625,20 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
                           h->loss_l1, s));
   PROF(3);
   const int lp = sorted ? h->priv_L : 0;
-  // privatized levels [0, lp): levels [ls, lp) run on the side stream, concurrently
-  // with [0, ls) (they write disjoint gradient ranges and only read the step's samples)
-  int ls = lp;
-  if (lp > 0 && h->scatter_split != 0) {
-    ls = h->scatter_split > 0 ? std::min(h->scatter_split, lp) : std::max(0, lp - 5);
-    if (ls <= 0) ls = lp;
+  // privatized levels [0, lp) in up to three launches by LDS class: small boxes
+  // (coarse levels, high occupancy), large boxes, and levels whose boxes never
+  // fit (direct atomics over each bin's samples, no LDS).  Plain workgroup
+  // mapping: each launch spreads its levels over every XCD (balance measured
+  // to matter more than per-XCD table locality here).
+  {
+    const int a = std::min(h->priv_small, lp), c = std::min(std::max(h->priv_direct, a), lp);
+    const int cls[3][3] = {{0, a, 1}, {a, c, 2}, {c, lp, 0}};
+    for (const auto& r : cls)
+      if (r[1] > r[0])
+        HIPCHK(launch_scatter_priv(h->ld, r[0], r[1], h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(),
+                                   h->d_coords(), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, 0, r[2],
+                                   s));
   }
-  if (ls < lp) {
-    if (!h->side) {
-      HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-      HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-      HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
-    }
-    HIPCHK(hipEventRecord(h->ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-    HIPCHK(launch_scatter_priv(h->ld, ls, lp, h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(),
-                               h->d_coords(), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, h->xcd_map,
-                               h->side));
-    HIPCHK(hipEventRecord(h->ev_join, h->side));
-  }
-  if (ls > 0)
-    HIPCHK(launch_scatter_priv(h->ld, 0, ls, h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(),
-                               h->d_coords(), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, h->xcd_map, s));
-  if (ls < lp) HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
   PROF(4);
   HIPCHK(launch_scatter(Prec::F32, h->ld, lp, h->enc.n_levels, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
                         h->d_coords(), h->d_dfeat(), F, h->max_batch * F, h->buf.grads, h->scatter_grouped,
@@ -1327,8 +1330,6 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
     h->scatter_grouped = value ? 1 : 0;
   } else if (n == "use_graph") {
     h->use_graph = value ? 1 : 0;
-  } else if (n == "scatter_split") {
-    h->scatter_split = (int)std::max<int64_t>(-1, std::min<int64_t>(value, kMaxLevels));
   } else if (n == "scatter_strided") {
     h->scatter_strided = value ? 1 : 0;
   } else if (n == "xcd_map") {

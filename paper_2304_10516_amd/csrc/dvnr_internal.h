@@ -15,6 +15,8 @@ constexpr int kMaxBins = 512;     // spatial bins per block (B^3, B <= 8) of the
 constexpr int kSortGroup = 1024;  // samples per counting-sort group
 constexpr int kPrivCells = 4096;  // cells of a bin's box in the privatized backward (LDS counters)
 constexpr int kPrivVertFloats = 8192;  // box vertices x features accumulated in LDS
+constexpr int kPrivCellsSmall = 512;   // the small LDS class (coarse levels, higher occupancy)
+constexpr int kPrivVertFloatsSmall = 2048;
 
 // Level table, passed by value to kernels.
 struct LevelDesc {
@@ -117,10 +119,12 @@ hipError_t launch_sorted_sample(const Tile* groups, int n_groups, const int32_t*
                                 uint64_t seed, SampleDist dist, const Counters* ctr, uint32_t* counts, uint32_t* totals,
                                 int32_t* bin_start, const BlockMeta* meta, const BlockRange* range,
                                 const BlockPlan* plan, float* coords, float* target, hipStream_t s);
-// Bin-privatized encoding backward of levels [l0, l1) (needs the ordered sampler).
+// Bin-privatized encoding backward of levels [l0, l1) (needs the ordered
+// sampler); size_class 0: direct atomics only, 1: small LDS boxes, 2: large.
 hipError_t launch_scatter_priv(const LevelDesc& ld, int l0, int l1, int B, int n_blocks, const BlockMeta* meta,
                                const BlockPlan* plan, const int32_t* bin_start, const float* coords,
-                               const float* dfeat, int64_t ls, float* grad, int xcd_map, hipStream_t s);
+                               const float* dfeat, int64_t ls, float* grad, int xcd_map, int size_class,
+                               hipStream_t s);
 
 // MLP training pass (forward, L2 loss, backward) on MFMA; writes dfeat
 // (level-major f32) and per-wave dW/loss partials into slots.

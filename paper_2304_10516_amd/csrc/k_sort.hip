@@ -198,7 +198,7 @@ hipError_t launch_sorted_sample(const Tile* groups, int n_groups, const int32_t*
 //   1. the cell box touched by the bin's samples (min/max of cell origins);
 //   2. a counting sort of the samples by cell inside the box (one integer LDS
 //      atomic per sample) that stores each sample's fractions t and dL/dy in
-//      cell order (chunks of kPrivRecs samples);
+//      cell order (chunks of RECS samples);
 //   3. cell pass: the lanes of a cell (1..8, more when the box has few cells)
 //      sum w_c * dy over the cell's samples for its 8 corners and F features
 //      in registers, then add them to an LDS accumulator of the box vertices
@@ -209,9 +209,10 @@ hipError_t launch_sorted_sample(const Tile* groups, int n_groups, const int32_t*
 //      levels, whose x prime is 1).
 // A bin whose box exceeds the LDS budget falls back to grouped direct atomics.
 // ===========================================================================
-constexpr int kPrivRecs = 1024;   // samples per chunk held in LDS
-
-template <int F>
+// LDS budget classes: CELLS box cells, VFLOATS box vertices x F accumulators,
+// RECS samples per chunk.  CELLS == 0 is the direct class (no LDS: levels
+// whose boxes never fit take the direct path at full occupancy).
+template <int F, int CELLS, int VFLOATS, int RECS>
 __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int nlev, int B, int n_blocks,
                                                       const BlockMeta* __restrict__ meta,
                                                       const BlockPlan* __restrict__ plan,
@@ -219,11 +220,12 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
                                                       const float* __restrict__ coords,
                                                       const float* __restrict__ dfeat, int64_t ls,
                                                       float* __restrict__ grad, int xcd_map) {
-  __shared__ int cstart[kPrivCells + 1];
-  __shared__ float vacc[kPrivVertFloats];
-  __shared__ float4 rt[kPrivRecs];       // tx, ty, tz of each placed sample
-  __shared__ float rd[kPrivRecs * F];    // dL/dy of each placed sample
-  __shared__ int part[256];
+  constexpr int kPrivRecs = RECS > 0 ? RECS : 256;
+  __shared__ int cstart[CELLS + 1];
+  __shared__ float vacc[VFLOATS > 0 ? VFLOATS : 1];
+  __shared__ float4 rt[RECS > 0 ? RECS : 1];            // tx, ty, tz of each placed sample
+  __shared__ float rd[RECS > 0 ? RECS * F : 1];         // dL/dy of each placed sample
+  __shared__ int part[CELLS > 0 ? 256 : 1];
   constexpr int PER = kPrivRecs / 256;   // samples per thread in a chunk
   const int nbins = B * B * B;
   int unit, l;  // unit = block * nbins + bin
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
   const int vx_n = cx_n + 1, vy_n = cy_n + 1, vz_n = cz_n + 1;                           // vertices per axis
   const int64_t C = (int64_t)cx_n * cy_n * cz_n;
   const int64_t NV = (int64_t)vx_n * vy_n * vz_n;
-  if (C > kPrivCells || NV * F > kPrivVertFloats) {
+  if (CELLS == 0 || C > CELLS || NV * F > VFLOATS) {
     // box too large for LDS: grouped direct atomics (2F lanes per x-neighbour pair)
     constexpr int G = 2 * F;
     const int q = tid % G;
@@ -404,18 +406,28 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
 
 hipError_t launch_scatter_priv(const LevelDesc& ld, int l0, int l1, int B, int n_blocks, const BlockMeta* meta,
                                const BlockPlan* plan, const int32_t* bin_start, const float* coords,
-                               const float* dfeat, int64_t ls, float* grad, int xcd_map, hipStream_t s) {
+                               const float* dfeat, int64_t ls, float* grad, int xcd_map, int size_class,
+                               hipStream_t s) {
   const int nlev = l1 - l0;
   if (nlev <= 0) return hipSuccess;
   const int grid = level_major_grid(nlev, n_blocks * B * B * B, xcd_map);
   if (grid <= 0) return hipSuccess;
+#define DVNR_PRIV_LAUNCH(FF, CC, VV, RR)                                                                         \
+  hipLaunchKernelGGL((k_scatter_priv<FF, CC, VV, RR>), dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, n_blocks, meta, \
+                     plan, bin_start, coords, dfeat, ls, grad, xcd_map)
+#define DVNR_PRIV_CLASSES(FF)                                                                                 \
+  if (size_class == 0) DVNR_PRIV_LAUNCH(FF, 0, 0, 0);                                                         \
+  else if (size_class == 1) DVNR_PRIV_LAUNCH(FF, kPrivCellsSmall, kPrivVertFloatsSmall, 512);                 \
+  else DVNR_PRIV_LAUNCH(FF, kPrivCells, kPrivVertFloats, 1024);
   switch (ld.F) {
-    case 1: hipLaunchKernelGGL(k_scatter_priv<1>, dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, n_blocks, meta, plan, bin_start, coords, dfeat, ls, grad, xcd_map); break;
-    case 2: hipLaunchKernelGGL(k_scatter_priv<2>, dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, n_blocks, meta, plan, bin_start, coords, dfeat, ls, grad, xcd_map); break;
-    case 4: hipLaunchKernelGGL(k_scatter_priv<4>, dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, n_blocks, meta, plan, bin_start, coords, dfeat, ls, grad, xcd_map); break;
-    case 8: hipLaunchKernelGGL(k_scatter_priv<8>, dim3(grid), dim3(256), 0, s, ld, l0, nlev, B, n_blocks, meta, plan, bin_start, coords, dfeat, ls, grad, xcd_map); break;
+    case 1: DVNR_PRIV_CLASSES(1) break;
+    case 2: DVNR_PRIV_CLASSES(2) break;
+    case 4: DVNR_PRIV_CLASSES(4) break;
+    case 8: DVNR_PRIV_CLASSES(8) break;
     default: return hipErrorInvalidValue;
   }
+#undef DVNR_PRIV_CLASSES
+#undef DVNR_PRIV_LAUNCH
   return hipGetLastError();
 }
 
