@@ -374,6 +374,9 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *                          (default 1 for mixed, 0 for fp32); enables the
  *                          bin-privatized backward of the coarse levels
  *  "priv_levels"     n   : privatize levels [0, n) (-1: chosen per plan)
+ *  "priv_classes"    0/1 : launch the privatized levels in three LDS-size
+ *                          classes (small boxes, large boxes, direct) instead
+ *                          of one launch (default 0)
  *  "scatter_strided" 0/1 : direct backward over ordered samples takes each
  *                          tile's samples strided across the block (default 1)
  *  "decode_fused"    0/1 : decode with the fused brick kernel (default 1)

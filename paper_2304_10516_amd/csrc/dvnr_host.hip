@@ -84,6 +84,7 @@ struct dvnr {
   int priv_levels = -1;  // -1: chosen per plan
   int sort_B = 0, priv_L = 0, n_groups = 0;
   int priv_small = 0, priv_direct = 0;  // LDS classes: small [0, priv_small), large up to priv_direct, then direct
+  int priv_classes = 0;                 // launch the privatized levels by LDS class (else one launch)
   std::vector<Tile> hgroups;
   std::vector<int32_t> hgrange;
   int64_t o_groups = 0, o_grange = 0, o_counts = 0, o_binstart = 0, o_totals = 0, max_groups = 0;
@@ -631,7 +632,10 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   // mapping: each launch spreads its levels over every XCD (balance measured
   // to matter more than per-XCD table locality here).
   {
-    const int a = std::min(h->priv_small, lp), c = std::min(std::max(h->priv_direct, a), lp);
+    // priv_classes 0: one launch (large class) for all privatized levels, so that
+    // the LDS-bound coarse and the atomic-bound fine levels overlap on the chip
+    const int a = h->priv_classes ? std::min(h->priv_small, lp) : 0;
+    const int c = h->priv_classes ? std::min(std::max(h->priv_direct, a), lp) : lp;
     const int cls[3][3] = {{0, a, 1}, {a, c, 2}, {c, lp, 0}};
     for (const auto& r : cls)
       if (r[1] > r[0])
@@ -1330,6 +1334,8 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
     h->scatter_grouped = value ? 1 : 0;
   } else if (n == "use_graph") {
     h->use_graph = value ? 1 : 0;
+  } else if (n == "priv_classes") {
+    h->priv_classes = value ? 1 : 0;
   } else if (n == "scatter_strided") {
     h->scatter_strided = value ? 1 : 0;
   } else if (n == "xcd_map") {

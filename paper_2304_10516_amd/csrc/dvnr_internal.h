@@ -73,7 +73,7 @@ struct Tile {
 struct Counters {
   int64_t step;                // optimizer steps taken (Adam t = step after the update)
   int32_t nonfinite;           // set when a non-finite loss was reduced
-  int32_t pad;
+  int32_t done;                // blocks whose loss the slot reduction has written this step (reset to 0)
   uint32_t minmax[2 * 1024];   // scratch for order-preserving float min/max keys (up to 1024 blocks per pass)
 };
 
@@ -138,7 +138,8 @@ hipError_t launch_mlp_infer(Prec p, const MlpDesc& md, const LevelDesc& ld, cons
                             int direct_block, const void* feat, const void* weights_src, int64_t plane, float* out,
                             hipStream_t s);
 
-// Sum slots into gradients and per-block losses; bump the step counter.
+// Sum slots into gradients and per-block losses; with bump, the last block to
+// finish advances the step counter.
 hipError_t launch_reduce_slots(const float* slots, int64_t slot_stride, const int32_t* slot_ranges, int n_blocks,
                                int64_t n_mlp, int64_t mlp_rel_off, int64_t block_stride, Prec gp, void* grad,
                                float* loss_ring, Counters* ctr, int bump, hipStream_t s);

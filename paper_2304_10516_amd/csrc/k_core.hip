@@ -362,7 +362,7 @@ __global__ __launch_bounds__(256) void k_reduce_slots(const float* __restrict__ 
                                                       const int32_t* __restrict__ ranges, int64_t n_mlp,
                                                       int64_t mlp_rel_off, int64_t block_stride,
                                                       GT* __restrict__ grad, float* __restrict__ loss_ring,
-                                                      Counters* __restrict__ ctr, int n_blocks) {
+                                                      Counters* __restrict__ ctr, int n_blocks, int bump) {
   __shared__ float part[8][33];
   const int b = blockIdx.y;
   const int c = threadIdx.x % 32, r = threadIdx.x / 32;
@@ -380,13 +380,20 @@ __global__ __launch_bounds__(256) void k_reduce_slots(const float* __restrict__ 
   if (e < n_mlp) {
     grad[(int64_t)b * block_stride + mlp_rel_off + e] = (GT)sum;
   } else {
+    // one lane per block reads the step counter; the last of them to finish
+    // advances it (all reads precede every arrival on the done counter)
     const int64_t step = ctr->step;
     loss_ring[(step % kLossRing) * n_blocks + b] = sum;
     if (!isfinite(sum)) ctr->nonfinite = 1;
+    if (bump) {
+      __threadfence();
+      if (atomicAdd(&ctr->done, 1) == n_blocks - 1) {
+        ctr->done = 0;
+        ctr->step = step + 1;
+      }
+    }
   }
 }
-
-__global__ void k_bump(Counters* ctr) { ctr->step += 1; }
 
 hipError_t launch_reduce_slots(const float* slots, int64_t slot_stride, const int32_t* slot_ranges, int n_blocks,
                                int64_t n_mlp, int64_t mlp_rel_off, int64_t block_stride, Prec gp, void* grad,
@@ -394,11 +401,10 @@ hipError_t launch_reduce_slots(const float* slots, int64_t slot_stride, const in
   dim3 grid((unsigned)((n_mlp + 1 + 31) / 32), (unsigned)n_blocks);
   if (gp == Prec::F64)
     hipLaunchKernelGGL(k_reduce_slots<double>, grid, dim3(256), 0, s, slots, slot_stride, slot_ranges, n_mlp,
-                       mlp_rel_off, block_stride, (double*)grad, loss_ring, ctr, n_blocks);
+                       mlp_rel_off, block_stride, (double*)grad, loss_ring, ctr, n_blocks, bump);
   else
     hipLaunchKernelGGL(k_reduce_slots<float>, grid, dim3(256), 0, s, slots, slot_stride, slot_ranges, n_mlp,
-                       mlp_rel_off, block_stride, (float*)grad, loss_ring, ctr, n_blocks);
-  if (bump) hipLaunchKernelGGL(k_bump, dim3(1), dim3(1), 0, s, ctr);
+                       mlp_rel_off, block_stride, (float*)grad, loss_ring, ctr, n_blocks, bump);
   return hipGetLastError();
 }
 

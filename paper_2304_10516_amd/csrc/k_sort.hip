@@ -199,10 +199,11 @@ hipError_t launch_sorted_sample(const Tile* groups, int n_groups, const int32_t*
 //   2. a counting sort of the samples by cell inside the box (one integer LDS
 //      atomic per sample) that stores each sample's fractions t and dL/dy in
 //      cell order (chunks of RECS samples);
-//   3. cell pass: the lanes of a cell (1..8, more when the box has few cells)
-//      sum w_c * dy over the cell's samples for its 8 corners and F features
-//      in registers, then add them to an LDS accumulator of the box vertices
-//      (8 F LDS atomics per cell and lane instead of per sample);
+//   3. cell pass: the lanes of a cell (1, 2, 4 or 8, more when the box has few
+//      cells) sum w_c * dy over the cell's samples for its 8 corners and F
+//      features in registers, combine their sums with shuffles, and the cell's
+//      first lane adds them to an LDS accumulator of the box vertices (8 F LDS
+//      atomics per occupied cell instead of per sample);
 //   4. vertex pass: one global atomic per nonzero (box vertex, feature) sum;
 //      lanes walk vertices x fastest, so an atomic instruction covers
 //      contiguous entries (dense levels) or a few aligned segments (hashed
@@ -286,7 +287,9 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
   }
   const int nc = (int)C, nvf = (int)NV * F;
   for (int i = tid; i < nvf; i += 256) vacc[i] = 0.0f;
-  const int sub = nc >= 256 ? 1 : min(8, 256 / nc);  // lanes per cell in the cell pass
+  // lanes per cell in the cell pass: the largest power of two <= min(8, 256 / nc),
+  // so that a cell's lanes are aligned neighbours within one wave
+  const int sub = nc > 128 ? 1 : (nc > 64 ? 2 : (nc > 32 ? 4 : 8));
   for (int c0 = s0; c0 < s1; c0 += kPrivRecs) {
     const int cn = min(kPrivRecs, s1 - c0);
     for (int i = tid; i <= nc; i += 256) cstart[i] = 0;
@@ -359,11 +362,15 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
     }
     __syncthreads();
     // ---- 3. cell pass: corner sums in registers, one LDS atomic per (corner, feature)
-    for (int q = tid; q < nc * sub; q += 256) {
-      const int c = q / sub, s = q - c * sub;
-      const int p1 = cstart[c + 1];
-      int p = cstart[c] + s;
-      if (p >= p1) continue;
+    for (int q0 = 0; q0 < nc * sub; q0 += 256) {  // uniform trip count: the whole wave shuffles
+      const int q = q0 + tid;
+      const bool live = q < nc * sub;
+      const int c = live ? q / sub : 0, s = q & (sub - 1);
+      int p = 0, p1 = 0;
+      if (live) {
+        p1 = cstart[c + 1];
+        p = cstart[c] + s;
+      }
       float acc[8][F];
 #pragma unroll
       for (int k = 0; k < 8; ++k)
@@ -382,6 +389,13 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
           for (int f = 0; f < F; ++f) acc[k][f] += w * d[f];
         }
       }
+      // the cell's sub lanes combine their partial sums; its first lane adds them
+      for (int o = 1; o < sub; o <<= 1)
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+          for (int f = 0; f < F; ++f) acc[k][f] += __shfl_xor(acc[k][f], o, 64);
+      if (!live || s != 0 || cstart[c] == p1) continue;
       const int lx = c % cx_n, ly = (c / cx_n) % cy_n, lz = c / (cx_n * cy_n);
 #pragma unroll
       for (int k = 0; k < 8; ++k) {

@@ -181,11 +181,12 @@ def test_one_step_gradient_parity_c1(precision, grouped):
     assert normwise(gg[nt:], g[nt:]) <= tol, "weight gradient"
 
 
-@pytest.mark.parametrize("precision,priv", [("fp32", -1), ("fp32", 0), ("mixed", -1), ("mixed", 2)])
-def test_sorted_sampling_gradient_parity(precision, priv):
+@pytest.mark.parametrize("precision,priv,classes", [("fp32", -1, 0), ("fp32", -1, 1), ("fp32", 0, 0),
+                                                    ("mixed", -1, 0), ("mixed", -1, 1), ("mixed", 2, 0)])
+def test_sorted_sampling_gradient_parity(precision, priv, classes):
     """Spatially ordered sampling stores the same Philox draws grouped by bin; the
     gradient (a sum over samples) must match the oracle's on the unordered draws."""
-    say(f"ordered sampling + privatized scatter {precision} priv_levels={priv}")
+    say(f"ordered sampling + privatized scatter {precision} priv_levels={priv} LDS classes {classes}")
     vol, lay, p0, model = _setup_c1_block(precision)
     model.bind_volumes([dev(vol)])
     p = p0.astype(np.float64).copy()
@@ -193,6 +194,7 @@ def test_sorted_sampling_gradient_parity(precision, priv):
     model.load_params([p])
     model.set_option("spatial_sort", 1)
     model.set_option("priv_levels", priv)
+    model.set_option("priv_classes", classes)
     model.set_option("apply_update", 0)
     model.set_option("use_graph", 0)
     loss = model.train(1, 4096, want_loss=True)
@@ -209,12 +211,12 @@ def test_sorted_sampling_gradient_parity(precision, priv):
     assert normwise(gg[nt:], g[nt:]) <= tol, "weight gradient"
 
 
-@pytest.mark.parametrize("precision", ["fp32", "mixed"])
-def test_sorted_sampling_gradient_parity_fine_levels(precision):
+@pytest.mark.parametrize("precision,classes", [("fp32", 0), ("fp32", 1), ("mixed", 0)])
+def test_sorted_sampling_gradient_parity_fine_levels(precision, classes):
     """16 levels up to R = 256 with 8192 samples (2^3 bins of ~1024): coarse
     levels accumulate in LDS, levels whose bin box exceeds the LDS budget take
     the in-kernel direct-atomic path; bins above 1024 samples take two chunks."""
-    say(f"ordered sampling, all levels privatized, c2 levels {precision}")
+    say(f"ordered sampling, all levels privatized, c2 levels {precision}, LDS classes {classes}")
     vol = gaussian_sum_field(64, seed=3)
     lay = o.layout(*C2)
     p = init_param_draws(lay.n_table_params, lay.mlp_shapes, seed=2).astype(np.float64)
@@ -224,6 +226,7 @@ def test_sorted_sampling_gradient_parity_fine_levels(precision):
     model.load_params([p])
     model.set_option("spatial_sort", 1)
     model.set_option("priv_levels", -1)
+    model.set_option("priv_classes", classes)
     model.set_option("apply_update", 0)
     model.set_option("use_graph", 0)
     loss = model.train(1, 8192, want_loss=True)
