@@ -419,59 +419,64 @@ hipError_t launch_reduce_slots(const float* slots, int64_t slot_stride, const in
 template <typename P>
 __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restrict__ grad, P* __restrict__ mom,
                                               P* __restrict__ vel, uint16_t* __restrict__ work16,
-                                              int64_t n_total, int64_t block_stride, int64_t n_table,
-                                              int64_t n_used, const BlockPlan* __restrict__ plan,
-                                              const Counters* __restrict__ ctr, P lr, P b1, P b2, P eps, P wd) {
-  const double t = (double)ctr->step;
-  const P bc1 = (P)(1.0 / (1.0 - pow((double)b1, t)));
-  const P bc2 = (P)(1.0 / (1.0 - pow((double)b2, t)));
-  const int64_t n4 = n_total / 4;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n4; q += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i0 = 4 * q;
-    const int64_t j0 = i0 % block_stride;
-    if (j0 >= n_used) continue;
-    if (plan && plan[i0 / block_stride].n == 0) continue;  // block drew no sample this step: unchanged
-    P th[4], g[4], m[4], v[4];
+                                              int64_t block_stride, int64_t n_table, int64_t n_used,
+                                              const BlockPlan* __restrict__ plan, const Counters* __restrict__ ctr,
+                                              P lr, P b1, P b2, P eps, P wd) {
+  // grid (element groups of the block, blocks): no division per element, one
+  // uniform skip for a block that drew no sample this step
+  const int b = blockIdx.y;
+  if (plan && plan[b].n == 0) return;
+  __shared__ P bc[2];
+  if (threadIdx.x == 0) {
+    const double t = (double)ctr->step;
+    bc[0] = (P)(1.0 / (1.0 - pow((double)b1, t)));
+    bc[1] = (P)(1.0 / (1.0 - pow((double)b2, t)));
+  }
+  __syncthreads();
+  const P bc1 = bc[0], bc2 = bc[1];
+  const int64_t j0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (j0 >= n_used) return;
+  const int64_t i0 = (int64_t)b * block_stride + j0;
+  P th[4], g[4], m[4], v[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      th[k] = params[i0 + k];
-      g[k] = grad[i0 + k];
-      m[k] = mom[i0 + k];
-      v[k] = vel[i0 + k];
-    }
+  for (int k = 0; k < 4; ++k) {
+    th[k] = params[i0 + k];
+    g[k] = grad[i0 + k];
+    m[k] = mom[i0 + k];
+    v[k] = vel[i0 + k];
+  }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (j0 + k >= n_used) {
-        g[k] = 0;
-        continue;
-      }
-      const P gg = g[k] + wd * th[k];
-      m[k] = b1 * m[k] + (P(1) - b1) * gg;
-      v[k] = b2 * v[k] + (P(1) - b2) * gg * gg;
-      th[k] = th[k] - lr * (m[k] * bc1) / (sqrt(v[k] * bc2) + eps);
+  for (int k = 0; k < 4; ++k) {
+    if (j0 + k >= n_used) {
       g[k] = 0;
+      continue;
     }
+    const P gg = g[k] + wd * th[k];
+    m[k] = b1 * m[k] + (P(1) - b1) * gg;
+    v[k] = b2 * v[k] + (P(1) - b2) * gg * gg;
+    th[k] = th[k] - lr * (m[k] * bc1) / (sqrt(v[k] * bc2) + eps);
+    g[k] = 0;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    params[i0 + k] = th[k];
+    grad[i0 + k] = g[k];
+    mom[i0 + k] = m[k];
+    vel[i0 + k] = v[k];
+  }
+  if (work16) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      params[i0 + k] = th[k];
-      grad[i0 + k] = g[k];
-      mom[i0 + k] = m[k];
-      vel[i0 + k] = v[k];
-    }
-    if (work16) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float f = (float)th[k];
-        uint16_t bits;
-        if (j0 + k < n_table) {
-          const __half h = __float2half_rn(f);
-          bits = *reinterpret_cast<const uint16_t*>(&h);
-        } else {
-          const __bf16 h = (__bf16)f;
-          bits = *reinterpret_cast<const uint16_t*>(&h);
-        }
-        work16[i0 + k] = bits;
+      const float f = (float)th[k];
+      uint16_t bits;
+      if (j0 + k < n_table) {
+        const __half h = __float2half_rn(f);
+        bits = *reinterpret_cast<const uint16_t*>(&h);
+      } else {
+        const __bf16 h = (__bf16)f;
+        bits = *reinterpret_cast<const uint16_t*>(&h);
       }
+      work16[i0 + k] = bits;
     }
   }
 }
@@ -479,17 +484,16 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
 hipError_t launch_adam(Prec p, void* params, void* grad, void* m, void* v, uint16_t* work16, int n_blocks,
                        int64_t block_stride, int64_t n_table_params, int64_t n_used, const BlockPlan* plan,
                        const Counters* ctr, double lr, double b1, double b2, double eps, double wd, hipStream_t s) {
-  const int64_t n_total = (int64_t)n_blocks * block_stride;
-  const int64_t n4 = n_total / 4;
-  const int grid = (int)std::min<int64_t>((n4 + 255) / 256, 256 * 32);
+  if (n_blocks <= 0 || n_used <= 0) return hipSuccess;
+  if (n_blocks > 65535) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((n_used + 1023) / 1024), (unsigned)n_blocks);
   if (p == Prec::F64)
-    hipLaunchKernelGGL(k_adam<double>, dim3(grid), dim3(256), 0, s, (double*)params, (double*)grad, (double*)m,
-                       (double*)v, nullptr, n_total, block_stride, n_table_params, n_used, plan, ctr, lr, b1, b2, eps,
-                       wd);
+    hipLaunchKernelGGL(k_adam<double>, grid, dim3(256), 0, s, (double*)params, (double*)grad, (double*)m, (double*)v,
+                       nullptr, block_stride, n_table_params, n_used, plan, ctr, lr, b1, b2, eps, wd);
   else
-    hipLaunchKernelGGL(k_adam<float>, dim3(grid), dim3(256), 0, s, (float*)params, (float*)grad, (float*)m,
-                       (float*)v, work16, n_total, block_stride, n_table_params, n_used, plan, ctr, (float)lr, (float)b1,
-                       (float)b2, (float)eps, (float)wd);
+    hipLaunchKernelGGL(k_adam<float>, grid, dim3(256), 0, s, (float*)params, (float*)grad, (float*)m, (float*)v,
+                       work16, block_stride, n_table_params, n_used, plan, ctr, (float)lr, (float)b1, (float)b2,
+                       (float)eps, (float)wd);
   return hipGetLastError();
 }
 

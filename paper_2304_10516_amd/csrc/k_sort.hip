@@ -41,8 +41,9 @@ __device__ __forceinline__ void bin_x_range(int k, int B, float& lo, float& hi) 
   }
 }
 
-// groups: Tile entries with count <= kSortGroup samples of one block.
-__global__ __launch_bounds__(256) void k_sort_count(const Tile* __restrict__ groups, int B, uint64_t seed,
+// groups: Tile entries with count <= kSortGroup samples of one block; one
+// workgroup of kSortGroup threads per group (one sample per thread).
+__global__ __launch_bounds__(kSortGroup) void k_sort_count(const Tile* __restrict__ groups, int B, uint64_t seed,
                                                     SampleDist dist, const BlockPlan* __restrict__ plan,
                                                     const Counters* __restrict__ ctr, uint32_t* __restrict__ counts) {
   __shared__ uint32_t hist[kMaxBins];
@@ -105,7 +106,7 @@ __device__ __forceinline__ void cell_pos_s(float x, int n, int g, int N, int& i0
 // Bin starts are the exclusive scan of the block's bin totals; every
 // workgroup computes them in LDS, the block's first group also stores them
 // (bin_start[b][0..nbins], last = sample count) for the privatized scatter.
-__global__ __launch_bounds__(256) void k_sort_place(const Tile* __restrict__ groups, const int32_t* __restrict__ grange,
+__global__ __launch_bounds__(kSortGroup) void k_sort_place(const Tile* __restrict__ groups, const int32_t* __restrict__ grange,
                                                     int B, uint64_t seed, SampleDist dist,
                                                     const Counters* __restrict__ ctr,
                                                     const uint32_t* __restrict__ prefix,
@@ -121,29 +122,36 @@ __global__ __launch_bounds__(256) void k_sort_place(const Tile* __restrict__ gro
   const Tile gr = groups[blockIdx.x];
   const uint32_t* pre = prefix + (int64_t)blockIdx.x * nbins;
   const uint32_t* tot = totals + gr.block * kMaxBins;
-  // exclusive scan of the bin totals: each thread owns 2 consecutive bins
+  // exclusive scan of the bin totals: threads 0..255 own 2 consecutive bins each
   const int t = threadIdx.x;
-  const uint32_t a0 = 2 * t < nbins ? tot[2 * t] : 0u, a1 = 2 * t + 1 < nbins ? tot[2 * t + 1] : 0u;
-  scan[t] = a0 + a1;
+  const bool scanner = t < 256;
+  uint32_t a0 = 0u, a1 = 0u;
+  if (scanner) {
+    a0 = 2 * t < nbins ? tot[2 * t] : 0u;
+    a1 = 2 * t + 1 < nbins ? tot[2 * t + 1] : 0u;
+    scan[t] = a0 + a1;
+  }
   __syncthreads();
   for (int o = 1; o < 256; o <<= 1) {
-    const uint32_t v = t >= o ? scan[t - o] : 0u;
+    const uint32_t v = scanner && t >= o ? scan[t - o] : 0u;
     __syncthreads();
-    scan[t] += v;
+    if (scanner) scan[t] += v;
     __syncthreads();
   }
-  const uint32_t ex = scan[t] - a0 - a1;  // start of bin 2t
   const bool first = grange[2 * gr.block] == (int)blockIdx.x;
   int32_t* bs = bin_start + gr.block * (kMaxBins + 1);
-  if (2 * t < nbins) {
-    cursor[2 * t] = ex + pre[2 * t];
-    if (first) bs[2 * t] = (int32_t)ex;
+  if (scanner) {
+    const uint32_t ex = scan[t] - a0 - a1;  // start of bin 2t
+    if (2 * t < nbins) {
+      cursor[2 * t] = ex + pre[2 * t];
+      if (first) bs[2 * t] = (int32_t)ex;
+    }
+    if (2 * t + 1 < nbins) {
+      cursor[2 * t + 1] = ex + a0 + pre[2 * t + 1];
+      if (first) bs[2 * t + 1] = (int32_t)(ex + a0);
+    }
+    if (first && t == 255) bs[nbins] = (int32_t)scan[255];
   }
-  if (2 * t + 1 < nbins) {
-    cursor[2 * t + 1] = ex + a0 + pre[2 * t + 1];
-    if (first) bs[2 * t + 1] = (int32_t)(ex + a0);
-  }
-  if (first && t == 255) bs[nbins] = (int32_t)scan[255];
   __syncthreads();
   const uint32_t step = (uint32_t)ctr->step;
   const BlockMeta bm = meta[gr.block];
@@ -184,10 +192,10 @@ hipError_t launch_sorted_sample(const Tile* groups, int n_groups, const int32_t*
   if (n_groups <= 0) return hipSuccess;
   if (B < 1 || B * B * B > kMaxBins) return hipErrorInvalidValue;
   const int nbins = B * B * B;
-  hipLaunchKernelGGL(k_sort_count, dim3(n_groups), dim3(256), 0, s, groups, B, seed, dist, plan, ctr, counts);
+  hipLaunchKernelGGL(k_sort_count, dim3(n_groups), dim3(kSortGroup), 0, s, groups, B, seed, dist, plan, ctr, counts);
   hipLaunchKernelGGL(k_sort_scan, dim3(n_blocks, (nbins + 63) / 64), dim3(1024), 0, s, group_range, B, counts,
                      totals);
-  hipLaunchKernelGGL(k_sort_place, dim3(n_groups), dim3(256), 0, s, groups, group_range, B, seed, dist, ctr, counts,
+  hipLaunchKernelGGL(k_sort_place, dim3(n_groups), dim3(kSortGroup), 0, s, groups, group_range, B, seed, dist, ctr, counts,
                      totals, bin_start, meta, range, plan, coords, target);
   return hipGetLastError();
 }
