@@ -438,12 +438,28 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
   if (j0 >= n_used) return;
   const int64_t i0 = (int64_t)b * block_stride + j0;
   P th[4], g[4], m[4], v[4];
+  if constexpr (sizeof(P) == 4) {
+    // each stream is touched once per step: non-temporal 16-byte accesses
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 a = __builtin_nontemporal_load(reinterpret_cast<const f4*>(params + i0));
+    const f4 bg = __builtin_nontemporal_load(reinterpret_cast<const f4*>(grad + i0));
+    const f4 bm = __builtin_nontemporal_load(reinterpret_cast<const f4*>(mom + i0));
+    const f4 bv = __builtin_nontemporal_load(reinterpret_cast<const f4*>(vel + i0));
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    th[k] = params[i0 + k];
-    g[k] = grad[i0 + k];
-    m[k] = mom[i0 + k];
-    v[k] = vel[i0 + k];
+    for (int k = 0; k < 4; ++k) {
+      th[k] = a[k];
+      g[k] = bg[k];
+      m[k] = bm[k];
+      v[k] = bv[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      th[k] = params[i0 + k];
+      g[k] = grad[i0 + k];
+      m[k] = mom[i0 + k];
+      v[k] = vel[i0 + k];
+    }
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -457,12 +473,20 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
     th[k] = th[k] - lr * (m[k] * bc1) / (sqrt(v[k] * bc2) + eps);
     g[k] = 0;
   }
+  if constexpr (sizeof(P) == 4) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    __builtin_nontemporal_store(f4{th[0], th[1], th[2], th[3]}, reinterpret_cast<f4*>(params + i0));
+    __builtin_nontemporal_store(f4{g[0], g[1], g[2], g[3]}, reinterpret_cast<f4*>(grad + i0));
+    __builtin_nontemporal_store(f4{m[0], m[1], m[2], m[3]}, reinterpret_cast<f4*>(mom + i0));
+    __builtin_nontemporal_store(f4{v[0], v[1], v[2], v[3]}, reinterpret_cast<f4*>(vel + i0));
+  } else {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    params[i0 + k] = th[k];
-    grad[i0 + k] = g[k];
-    mom[i0 + k] = m[k];
-    vel[i0 + k] = v[k];
+    for (int k = 0; k < 4; ++k) {
+      params[i0 + k] = th[k];
+      grad[i0 + k] = g[k];
+      mom[i0 + k] = m[k];
+      vel[i0 + k] = v[k];
+    }
   }
   if (work16) {
 #pragma unroll
