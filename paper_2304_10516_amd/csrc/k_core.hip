@@ -440,6 +440,7 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
   P th[4], g[4], m[4], v[4];
   if constexpr (sizeof(P) == 4) {
     // each stream is touched once per step: non-temporal 16-byte accesses
+    // (except the gradient store below)
     typedef float f4 __attribute__((ext_vector_type(4)));
     const f4 a = __builtin_nontemporal_load(reinterpret_cast<const f4*>(params + i0));
     const f4 bg = __builtin_nontemporal_load(reinterpret_cast<const f4*>(grad + i0));
@@ -476,7 +477,8 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
   if constexpr (sizeof(P) == 4) {
     typedef float f4 __attribute__((ext_vector_type(4)));
     __builtin_nontemporal_store(f4{th[0], th[1], th[2], th[3]}, reinterpret_cast<f4*>(params + i0));
-    __builtin_nontemporal_store(f4{g[0], g[1], g[2], g[3]}, reinterpret_cast<f4*>(grad + i0));
+    // the zeroed gradient stays cached: the next step's scatter atomics land on it
+    *reinterpret_cast<f4*>(grad + i0) = f4{g[0], g[1], g[2], g[3]};
     __builtin_nontemporal_store(f4{m[0], m[1], m[2], m[3]}, reinterpret_cast<f4*>(mom + i0));
     __builtin_nontemporal_store(f4{v[0], v[1], v[2], v[3]}, reinterpret_cast<f4*>(vel + i0));
   } else {
