@@ -122,17 +122,13 @@ def run_precision(torch, DVNR, cfg, blocks, vols, precision, steps, warmup, seed
         if warmup:
             model.train(warmup, batch, stream=stream)
         model.init_params(1, stream=stream)  # the timed run starts from the initial state
-        model.set_option("profile_phases", 1)
-        model.phase_times()
         stream.synchronize()
         log(f"[bench] {precision}: timing {steps} steps of {batch} samples over {len(blocks)} block(s)")
         t0 = time.perf_counter()
-        loss = model.train(steps, batch, want_loss=True, stream=stream)
+        loss = model.train(steps, batch, want_loss=True, stream=stream)  # hipGraph replays
         stream.synchronize()
         t1 = time.perf_counter()
-        phases, nsteps = model.phase_times()
         bins, priv = model.plan_info()
-        model.set_option("profile_phases", 0)
         outs = [torch.empty((d[2], d[1], d[0]), dtype=torch.float32, device="cuda") for d, _ in blocks]
         for b in range(len(blocks)):  # warm
             model.decode(b, out=outs[b], stream=stream)
@@ -148,6 +144,14 @@ def run_precision(torch, DVNR, cfg, blocks, vols, precision, steps, warmup, seed
             s, c = model.squared_error(b, outs[b], stream=stream)
             sse += s
             cnt += c
+        # per-phase device times: a further short run with HIP events between the
+        # phases (eager launches), after the quality of the timed run was measured
+        model.set_option("profile_phases", 1)
+        model.phase_times()
+        model.train(min(steps, 200), batch, stream=stream)
+        stream.synchronize()
+        phases, nsteps = model.phase_times()
+        model.set_option("profile_phases", 0)
         render = None
         if len(blocks) == 1:
             # sample-streaming direct volume rendering of the trained block, 1024^2 rays
