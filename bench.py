@@ -73,7 +73,7 @@ def make_workload(name, torch):
         blocks = [((256, 256, 256), 0)]
         vols = [torch.tensor(vol, device="cuda")]
         desc = ("single 256^3 block of a seeded k^-5/3 field; hash grid L=16, T=2^19, F=2, base 16, finest 256; "
-                "MLP 2x64 ReLU; L2 loss; Adam lr 1e-2")
+                "MLP 2x64 ReLU; L2 loss")
         return cfg, blocks, vols, desc, vol
     if name in ("c3", "c5"):
         from fixtures import kolmogorov_field_torch, uneven_block_sizes
@@ -313,6 +313,9 @@ def main():
     ap.add_argument("--timesteps", type=int, default=40, help="c4: timesteps of the series")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="mixed,fp32")
+    ap.add_argument("--lr-final", type=float, default=0.1,
+                    help="c2/c3: learning rate at the last timed step as a fraction of the initial 1e-2 "
+                         "(exponential decay over the run; 1 keeps it constant)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy kernel (counter calibration for profiles)")
     args = ap.parse_args()
@@ -343,6 +346,12 @@ def main():
         print(json.dumps(out), flush=True)
         return
     cfg, blocks, vols, desc, host_vol = make_workload(args.workload, torch)
+    if args.workload in ("c2", "c3") and args.lr_final != 1.0:
+        # Adam with exponential learning-rate decay (Sec. III-F): lr 1e-2 * lr_final^(t / steps)
+        import dataclasses
+        cfg["optim"] = dataclasses.replace(cfg["optim"], lr_decay_base=args.lr_final, lr_decay_start=0,
+                                           lr_decay_interval=steps)
+        desc += f"; Adam lr 1e-2 decaying exponentially to {args.lr_final:g} x over the {steps} timed steps"
     if args.calibrate_copy:
         a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

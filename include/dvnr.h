@@ -82,9 +82,16 @@ typedef struct dvnr_mlp {
   int32_t out_dim;         /* must be 1 (scalar fields) */
 } dvnr_mlp;
 
-/* Adam with L2 weight decay added to the gradient (Sec. III-F). */
+/* Adam with L2 weight decay added to the gradient and an optional exponential
+ * learning-rate decay (Sec. III-F): update t (t = 1, 2, ... since the last
+ * optimizer reset) uses lr * lr_decay_base^(max(0, t - lr_decay_start) /
+ * lr_decay_interval); lr_decay_interval <= 0 keeps lr constant (the default
+ * when the fields are zero). */
 typedef struct dvnr_optim {
   double lr, beta1, beta2, eps, weight_decay;
+  double lr_decay_base;       /* (0, 1] when lr_decay_interval > 0 */
+  int64_t lr_decay_start;     /* >= 0 */
+  int64_t lr_decay_interval;  /* <= 0: no decay */
 } dvnr_optim;
 
 typedef enum dvnr_precision {

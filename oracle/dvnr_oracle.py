@@ -444,6 +444,18 @@ class Optim:
     beta2: float = 0.999
     eps: float = 1e-8
     weight_decay: float = 1e-9
+    lr_decay_base: float = 1.0
+    lr_decay_start: int = 0
+    lr_decay_interval: int = 0   # 0: constant learning rate
+
+
+def learning_rate(opt: Optim, t: int) -> float:
+    """Learning rate of Adam update t (1, 2, ...): exponential decay
+    lr * base^(max(0, t - start) / interval) (Sec. III-F names the decay; its
+    form is this reading); constant when the interval is 0."""
+    if opt.lr_decay_interval <= 0 or t <= opt.lr_decay_start:
+        return opt.lr
+    return opt.lr * opt.lr_decay_base ** ((t - opt.lr_decay_start) / opt.lr_decay_interval)
 
 
 @dataclass
@@ -461,7 +473,8 @@ def adam(params: np.ndarray, grad: np.ndarray, st: AdamState, opt: Optim) -> np.
     """One Adam step on every parameter (dense: untouched entries still decay).
 
     g <- g + wd * theta; m <- b1 m + (1 - b1) g; v <- b2 v + (1 - b2) g^2;
-    theta <- theta - lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+    theta <- theta - lr_t * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
+    lr_t = learning_rate(opt, t).
     Returns the new parameters (float64); st is updated in place.
     """
     th = np.asarray(params, dtype=np.float64)
@@ -471,7 +484,7 @@ def adam(params: np.ndarray, grad: np.ndarray, st: AdamState, opt: Optim) -> np.
     st.v = opt.beta2 * st.v + (1.0 - opt.beta2) * g * g
     mhat = st.m / (1.0 - opt.beta1 ** st.t)
     vhat = st.v / (1.0 - opt.beta2 ** st.t)
-    return th - opt.lr * mhat / (np.sqrt(vhat) + opt.eps)
+    return th - learning_rate(opt, st.t) * mhat / (np.sqrt(vhat) + opt.eps)
 
 
 def loss_and_grad(lay: Layout, params: np.ndarray, x: np.ndarray, target: np.ndarray, loss: str = "l2"):

@@ -25,7 +25,8 @@ class Mlp(C.Structure):
 
 class Optim(C.Structure):
     _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
-                ("weight_decay", C.c_double)]
+                ("weight_decay", C.c_double), ("lr_decay_base", C.c_double), ("lr_decay_start", C.c_int64),
+                ("lr_decay_interval", C.c_int64)]
 
 
 class Block(C.Structure):

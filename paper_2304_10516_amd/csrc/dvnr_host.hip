@@ -210,7 +210,9 @@ dvnr_status dvnr_create(const dvnr_encoding* enc, const dvnr_mlp* mlp, const dvn
     if (n_blocks < 1 || n_blocks > 1024) return fail(DVNR_E_INVALID, "n_blocks must be in [1, 1024]");
     if (max_batch < 256 || max_batch > ((int64_t)1 << 28)) return fail(DVNR_E_INVALID, "max_batch must be in [256, 2^28]");
     if (!(opt->lr > 0) || !(opt->beta1 >= 0 && opt->beta1 < 1) || !(opt->beta2 >= 0 && opt->beta2 < 1) ||
-        !(opt->eps > 0) || !(opt->weight_decay >= 0))
+        !(opt->eps > 0) || !(opt->weight_decay >= 0) ||
+        (opt->lr_decay_interval > 0 && !(opt->lr_decay_base > 0 && opt->lr_decay_base <= 1)) ||
+        opt->lr_decay_start < 0)
       return fail(DVNR_E_INVALID, "bad optimizer settings");
     for (int b = 0; b < n_blocks; ++b) {
       const dvnr_block& bl = blocks[b];
@@ -658,7 +660,8 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   HIPCHK(launch_adam(h->prec, h->buf.params, h->buf.grads, h->buf.adam_m, h->buf.adam_v,
                      mixed ? (uint16_t*)h->buf.work16 : nullptr, h->nb, h->stride, h->n_table, h->n_table + h->n_mlp,
                      h->d_plan(), h->d_ctr(), h->opt.lr, h->opt.beta1, h->opt.beta2, h->opt.eps,
-                     h->opt.weight_decay, s));
+                     h->opt.weight_decay, h->opt.lr_decay_interval > 0 ? h->opt.lr_decay_base : 1.0,
+                     h->opt.lr_decay_start, h->opt.lr_decay_interval > 0 ? h->opt.lr_decay_interval : 0, s));
   PROF(7);
   return DVNR_OK;
 }

@@ -146,7 +146,8 @@ hipError_t launch_reduce_slots(const float* slots, int64_t slot_stride, const in
 
 hipError_t launch_adam(Prec p, void* params, void* grad, void* m, void* v, uint16_t* work16, int n_blocks,
                        int64_t block_stride, int64_t n_table_params, int64_t n_used, const BlockPlan* plan,
-                       const Counters* ctr, double lr, double b1, double b2, double eps, double wd, hipStream_t s);
+                       const Counters* ctr, double lr, double b1, double b2, double eps, double wd,
+                       double decay_base, int64_t decay_start, int64_t decay_interval, hipStream_t s);
 
 // Reference-style building blocks (thread per sample) for the autograd pieces.
 hipError_t launch_mlp_simple_fwd(Prec p, const MlpDesc& md, int64_t n, const void* feats, const void* w,

@@ -411,7 +411,9 @@ hipError_t launch_reduce_slots(const float* slots, int64_t slot_stride, const in
 // ===========================================================================
 // Adam with L2 weight decay (every parameter, every step):
 //   g += wd*theta; m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
-//   theta -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps); g = 0.
+//   theta -= lr_t * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps); g = 0,
+// lr_t = lr * base^(max(0, t - start) / interval) (exponential decay; interval
+// 0: constant).
 // Mixed precision also refreshes the 16-bit working copy (fp16 tables, bf16
 // weights, round to nearest even).  4 elements per thread (block_stride is
 // a multiple of 64, so a group of 4 never straddles two blocks).
@@ -421,19 +423,25 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
                                               P* __restrict__ vel, uint16_t* __restrict__ work16,
                                               int64_t block_stride, int64_t n_table, int64_t n_used,
                                               const BlockPlan* __restrict__ plan, const Counters* __restrict__ ctr,
-                                              P lr, P b1, P b2, P eps, P wd) {
+                                              P lr0, P b1, P b2, P eps, P wd, double decay_base, int64_t decay_start,
+                                              int64_t decay_interval) {
   // grid (element groups of the block, blocks): no division per element, one
   // uniform skip for a block that drew no sample this step
   const int b = blockIdx.y;
   if (plan && plan[b].n == 0) return;
-  __shared__ P bc[2];
+  __shared__ P bc[3];
   if (threadIdx.x == 0) {
-    const double t = (double)ctr->step;
+    const int64_t ti = ctr->step;  // this update's index t (1, 2, ...)
+    const double t = (double)ti;
     bc[0] = (P)(1.0 / (1.0 - pow((double)b1, t)));
     bc[1] = (P)(1.0 / (1.0 - pow((double)b2, t)));
+    double lr = (double)lr0;
+    if (decay_interval > 0 && ti > decay_start)
+      lr *= pow(decay_base, (double)(ti - decay_start) / (double)decay_interval);
+    bc[2] = (P)lr;
   }
   __syncthreads();
-  const P bc1 = bc[0], bc2 = bc[1];
+  const P bc1 = bc[0], bc2 = bc[1], lr = bc[2];
   const int64_t j0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
   if (j0 >= n_used) return;
   const int64_t i0 = (int64_t)b * block_stride + j0;
@@ -509,17 +517,19 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
 
 hipError_t launch_adam(Prec p, void* params, void* grad, void* m, void* v, uint16_t* work16, int n_blocks,
                        int64_t block_stride, int64_t n_table_params, int64_t n_used, const BlockPlan* plan,
-                       const Counters* ctr, double lr, double b1, double b2, double eps, double wd, hipStream_t s) {
+                       const Counters* ctr, double lr, double b1, double b2, double eps, double wd,
+                       double decay_base, int64_t decay_start, int64_t decay_interval, hipStream_t s) {
   if (n_blocks <= 0 || n_used <= 0) return hipSuccess;
   if (n_blocks > 65535) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((n_used + 1023) / 1024), (unsigned)n_blocks);
   if (p == Prec::F64)
     hipLaunchKernelGGL(k_adam<double>, grid, dim3(256), 0, s, (double*)params, (double*)grad, (double*)m, (double*)v,
-                       nullptr, block_stride, n_table_params, n_used, plan, ctr, lr, b1, b2, eps, wd);
+                       nullptr, block_stride, n_table_params, n_used, plan, ctr, lr, b1, b2, eps, wd, decay_base,
+                       decay_start, decay_interval);
   else
     hipLaunchKernelGGL(k_adam<float>, grid, dim3(256), 0, s, (float*)params, (float*)grad, (float*)m, (float*)v,
                        work16, block_stride, n_table_params, n_used, plan, ctr, (float)lr, (float)b1, (float)b2,
-                       (float)eps, (float)wd);
+                       (float)eps, (float)wd, decay_base, decay_start, decay_interval);
   return hipGetLastError();
 }
 

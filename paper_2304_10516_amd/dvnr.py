@@ -34,6 +34,9 @@ class OptimCfg:
     beta2: float = 0.999
     eps: float = 1e-8
     weight_decay: float = 1e-9
+    lr_decay_base: float = 1.0      # exponential decay: lr * base^(max(0, t - start) / interval)
+    lr_decay_start: int = 0
+    lr_decay_interval: int = 0      # 0: constant learning rate
 
 
 PRECISIONS = {"fp32": L.DVNR_FP32, "mixed": L.DVNR_MIXED_BF16, "bf16": L.DVNR_MIXED_BF16, "fp64": L.DVNR_FP64}
@@ -74,7 +77,8 @@ class DVNR:
         e = L.Encoding(enc.n_levels, enc.n_features, enc.log2_table_size, enc.base_resolution,
                        float(enc.per_level_scale), enc.finest_resolution)
         m = L.Mlp(mlp.n_hidden_layers, mlp.width, mlp.out_dim)
-        o = L.Optim(self.optim.lr, self.optim.beta1, self.optim.beta2, self.optim.eps, self.optim.weight_decay)
+        o = L.Optim(self.optim.lr, self.optim.beta1, self.optim.beta2, self.optim.eps, self.optim.weight_decay,
+                    self.optim.lr_decay_base, self.optim.lr_decay_start, self.optim.lr_decay_interval)
         h = C.c_void_p()
         L.check(self.lib.dvnr_create(C.byref(e), C.byref(m), C.byref(o), PRECISIONS[precision], nb, barr,
                                      int(max_batch), int(seed), C.byref(h)))

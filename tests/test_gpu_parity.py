@@ -268,14 +268,23 @@ def test_sorted_sampling_gradient_parity_fine_levels(precision, classes):
     assert rel2(gg[nt:], g[nt:]) <= 3e-2, "weight gradient"
 
 
-def test_adam_update_parity_c1():
-    say("adam update c1 fp32")
+@pytest.mark.parametrize("decay", [False, True])
+def test_adam_update_parity_c1(decay):
+    say(f"adam update c1 fp32, learning-rate decay {decay}")
     vol, lay, p0, model = _setup_c1_block("fp32")
+    if decay:  # exponential decay: lr 1e-2 * 0.5^((t - 1) / 1) from the second update on
+        from paper_2304_10516_amd.dvnr import DVNR, EncodingCfg, MlpCfg, OptimCfg
+        enc, mlp = C1
+        model = DVNR(EncodingCfg(enc.n_levels, enc.n_features, enc.log2_table_size, enc.base_resolution,
+                                 enc.per_level_scale, enc.finest_resolution),
+                     MlpCfg(mlp.n_hidden_layers, mlp.width), [((64, 64, 64), 0)],
+                     OptimCfg(lr=1e-2, lr_decay_base=0.5, lr_decay_start=1, lr_decay_interval=1),
+                     precision="fp32", max_batch=1 << 14, seed=77)
     model.bind_volumes([dev(vol)])
     p = p0.astype(np.float64)
     model.load_params([p])
     st = o.adam_init(lay.n_params)
-    opt = o.Optim(lr=1e-2)
+    opt = o.Optim(lr=1e-2, lr_decay_base=0.5, lr_decay_start=1, lr_decay_interval=1) if decay else o.Optim(lr=1e-2)
     pr = model.block_params(0).cpu().numpy().astype(np.float64)
     gmax_hist = []
     small = np.zeros(lay.n_params, bool)

@@ -161,6 +161,21 @@ def test_adam_matches_torch():
     np.testing.assert_allclose(p, tp.detach().numpy(), rtol=1e-13, atol=1e-15)
 
 
+def test_learning_rate_decay_closed_form():
+    # under a constant gradient g, Adam's bias-corrected moments are exactly g
+    # and g^2, so update t moves theta by lr_t * |g| / (|g| + eps): the schedule
+    opt = o.Optim(lr=1e-2, weight_decay=0.0, lr_decay_base=0.1, lr_decay_start=3, lr_decay_interval=8)
+    st = o.adam_init(1)
+    g = np.array([0.5])
+    th = np.zeros(1)
+    for t in range(1, 30):
+        new = o.adam(th, g, st, opt)
+        want = 1e-2 * (0.1 ** (max(0, t - 3) / 8)) * 0.5 / (0.5 + 1e-8)
+        assert abs((th - new)[0] - want) <= 1e-15 + 1e-12 * want, t
+        th = new
+    assert o.learning_rate(opt, 11) == 1e-3 and o.learning_rate(o.Optim(lr=2e-2), 500) == 2e-2
+
+
 def test_psnr_closed_form():
     truth = np.random.default_rng(1).random((8, 8, 8))
     for e in (1e-1, 1e-2, 3e-4):
