@@ -68,6 +68,7 @@ struct dvnr {
   int use_graph = 1;
   int xcd_map = 1;
   int mlp_cap = kMlpGrid;  // workgroups of the persistent MLP kernel (autotuned)
+  int mlp_waves = 1;       // waves per SIMD the mixed-precision MLP kernel is compiled for (1 or 2)
   int decode_fused = 1;    // decode with the fused brick kernel (else encode + MLP over chunks)
   int apply_update = 1;
   // sliding-window model cache: capacity snapshots of the inference parameters
@@ -625,7 +626,7 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
                            : (const void*)((const float*)h->buf.params + h->n_table);
   HIPCHK(launch_mlp_train(h->prec, h->md, h->ld, h->d_meta(), h->d_plan(), h->d_tiles(), h->n_tiles, h->d_feat(),
                           h->d_target(), wsrc, h->d_dfeat(), h->max_batch, h->d_slots(), h->slot_stride, h->mlp_grid,
-                          h->loss_l1, s));
+                          h->loss_l1, h->mlp_waves, s));
   PROF(3);
   const int lp = sorted ? h->priv_L : 0;
   // privatized levels [0, lp) in up to three launches by LDS class: small boxes
@@ -1337,6 +1338,11 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
     h->scatter_grouped = value ? 1 : 0;
   } else if (n == "use_graph") {
     h->use_graph = value ? 1 : 0;
+  } else if (n == "mlp_waves") {
+    h->mlp_waves = value >= 2 ? 2 : 1;
+  } else if (n == "mlp_grid") {
+    h->mlp_cap = (int)std::max<int64_t>(1, std::min<int64_t>(value, 2 * kMlpGrid));
+    h->plan_total = -1;
   } else if (n == "priv_classes") {
     h->priv_classes = value ? 1 : 0;
   } else if (n == "scatter_strided") {

@@ -131,7 +131,7 @@ hipError_t launch_scatter_priv(const LevelDesc& ld, int l0, int l1, int B, int n
 hipError_t launch_mlp_train(Prec p, const MlpDesc& md, const LevelDesc& ld, const BlockMeta* meta,
                             const BlockPlan* plan, const Tile* tiles, int n_tiles, const void* feat,
                             const float* target, const void* weights_src, float* dfeat, int64_t plane,
-                            float* slots, int64_t slot_stride, int grid, int loss_l1, hipStream_t s);
+                            float* slots, int64_t slot_stride, int grid, int loss_l1, int min_waves, hipStream_t s);
 // MLP inference: out[i] = INR output de-normalized with the block range.
 hipError_t launch_mlp_infer(Prec p, const MlpDesc& md, const LevelDesc& ld, const BlockMeta* meta,
                             const BlockRange* range, const BlockPlan* plan, const Tile* tiles, int n_tiles,

@@ -148,8 +148,10 @@ __device__ __forceinline__ float load_feat(const FT* __restrict__ feat, int64_t 
 // workgroup writes its partial dW and loss of the finished block into slot
 // (w + block) and loads the new block's weights.
 // ---------------------------------------------------------------------------
-template <class TR, int W, int NH, typename FT, typename WSRC>
-__global__ __launch_bounds__(256) void k_mlp_train(MlpDesc md, int F, const BlockMeta* __restrict__ meta,
+// MINW: waves per SIMD the register allocation must allow (2 trades spills
+// for latency hiding; selected at run time, measured by the autotuner).
+template <class TR, int W, int NH, typename FT, typename WSRC, int MINW>
+__global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, const BlockMeta* __restrict__ meta,
                                                    const BlockPlan* __restrict__ plan,
                                                    const Tile* __restrict__ tiles, int n_tiles,
                                                    const FT* __restrict__ feat, const float* __restrict__ target,
@@ -523,13 +525,13 @@ static size_t infer_smem() {
   return sizeof(typename TR::op_t) * S::N_SLOTS * 64 + sizeof(float) * 64;
 }
 
-template <class TR, int W, int NH, typename FT, typename WSRC>
+template <class TR, int W, int NH, typename FT, typename WSRC, int MINW = 1>
 static hipError_t run_train(const MlpDesc& md, int F, const BlockMeta* meta, const BlockPlan* plan, const Tile* tiles,
                             int n_tiles, const void* feat, const float* target, const void* wsrc, float* dfeat,
                             int64_t plane, float* slots, int64_t slot_stride, int grid, int64_t n_table, int l1,
                             hipStream_t s) {
   const size_t sm = train_smem<TR, W, NH>();
-  auto kern = k_mlp_train<TR, W, NH, FT, WSRC>;
+  auto kern = k_mlp_train<TR, W, NH, FT, WSRC, MINW>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), sm, s, md, F, meta, plan, tiles, n_tiles, (const FT*)feat, target,
@@ -558,11 +560,15 @@ static hipError_t run_infer(const MlpDesc& md, int F, const BlockMeta* meta, con
 hipError_t launch_mlp_train(Prec p, const MlpDesc& md, const LevelDesc& ld, const BlockMeta* meta,
                             const BlockPlan* plan, const Tile* tiles, int n_tiles, const void* feat,
                             const float* target, const void* weights_src, float* dfeat, int64_t plane,
-                            float* slots, int64_t slot_stride, int grid, int loss_l1, hipStream_t s) {
+                            float* slots, int64_t slot_stride, int grid, int loss_l1, int min_waves, hipStream_t s) {
   // weights_src points at the MLP weights of block 0 (element n_table_params);
   // the kernel adds each block's parameter offset.
 #define X(WW, NN)                                                                                                   \
   if (md.width == WW && md.n_hidden == NN) {                                                                        \
+    if (p == Prec::MIXED && min_waves >= 2)                                                                         \
+      return run_train<TrBF16, WW, NN, __bf16, __bf16, 2>(md, ld.F, meta, plan, tiles, n_tiles, feat, target,       \
+                                                           weights_src, dfeat, plane, slots, slot_stride, grid,     \
+                                                           (int64_t)0, loss_l1, s);                                 \
     if (p == Prec::MIXED)                                                                                           \
       return run_train<TrBF16, WW, NN, __bf16, __bf16>(md, ld.F, meta, plan, tiles, n_tiles, feat, target,          \
                                                         weights_src, dfeat, plane, slots, slot_stride, grid,        \

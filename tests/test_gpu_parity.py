@@ -157,10 +157,12 @@ def _setup_c1_block(precision, n=64, seed=0, blocks=None):
     return vol, lay, p0, model
 
 
-@pytest.mark.parametrize("precision,grouped", [("fp32", 0), ("fp32", 1), ("mixed", 1)])
-def test_one_step_gradient_parity_c1(precision, grouped):
-    say(f"one-step gradient c1 {precision} grouped={grouped}")
+@pytest.mark.parametrize("precision,grouped,waves", [("fp32", 0, 1), ("fp32", 1, 1), ("mixed", 1, 1),
+                                                     ("mixed", 1, 2)])
+def test_one_step_gradient_parity_c1(precision, grouped, waves):
+    say(f"one-step gradient c1 {precision} grouped={grouped} mlp_waves={waves}")
     vol, lay, p0, model = _setup_c1_block(precision)
+    model.set_option("mlp_waves", waves)
     model.bind_volumes([dev(vol)])
     p = p0.astype(np.float64).copy()
     p[:lay.n_table_params] *= 1e3  # table values O(0.1) so that the encoding matters
@@ -211,8 +213,9 @@ def test_sorted_sampling_gradient_parity(precision, priv, classes):
     assert normwise(gg[nt:], g[nt:]) <= tol, "weight gradient"
 
 
-@pytest.mark.parametrize("precision,classes", [("fp32", 0), ("fp32", 1), ("mixed", 0)])
-def test_sorted_sampling_gradient_parity_fine_levels(precision, classes):
+@pytest.mark.parametrize("precision,classes,waves", [("fp32", 0, 1), ("fp32", 1, 1), ("mixed", 0, 1),
+                                                     ("mixed", 0, 2)])
+def test_sorted_sampling_gradient_parity_fine_levels(precision, classes, waves):
     """16 levels up to R = 256 with 8192 samples (2^3 bins of ~1024): coarse
     levels accumulate in LDS, levels whose bin box exceeds the LDS budget take
     the in-kernel direct-atomic path; bins above 1024 samples take two chunks."""
@@ -227,6 +230,7 @@ def test_sorted_sampling_gradient_parity_fine_levels(precision, classes):
     model.set_option("spatial_sort", 1)
     model.set_option("priv_levels", -1)
     model.set_option("priv_classes", classes)
+    model.set_option("mlp_waves", waves)
     model.set_option("apply_update", 0)
     model.set_option("use_graph", 0)
     loss = model.train(1, 8192, want_loss=True)
