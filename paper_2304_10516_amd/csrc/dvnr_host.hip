@@ -86,6 +86,8 @@ struct dvnr {
   int sort_B = 0, priv_L = 0, n_groups = 0;
   int priv_small = 0, priv_direct = 0;  // LDS classes: small [0, priv_small), large up to priv_direct, then direct
   int priv_classes = 0;                 // launch the privatized levels by LDS class (else one launch)
+  int encode_binned = 1;                // ordered samples: LDS-staged encoding of the levels whose box fits
+  int enc_binned = 0;                   // levels [0, enc_binned) of the current plan
   std::vector<Tile> hgroups;
   std::vector<int32_t> hgrange;
   int64_t o_groups = 0, o_grange = 0, o_counts = 0, o_binstart = 0, o_totals = 0, max_groups = 0;
@@ -528,6 +530,19 @@ static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_
   const int pl = h->enc.n_levels;
   // LDS class of each level from a bound on its bin box: ceil((R - 1) / B) + 2
   // cells per axis (the analytic box spans at most ceil((R - 1) / B) + 1)
+  // binned encoding: leading levels whose bin box ((ceil((R-1)/B) + 2)^3
+  // vertices at most) fits the LDS budget
+  {
+    const int64_t vbytes = (int64_t)h->enc.n_features * (h->prec == Prec::MIXED ? 2 : 4);
+    const int64_t boxv = kEncBoxBytes / vbytes;
+    int le = 0;
+    while (le < h->enc.n_levels) {
+      const int64_t side = (h->ld.R[le] - 1 + B - 1) / B + 2;
+      if (side * side * side > boxv) break;
+      ++le;
+    }
+    h->enc_binned = le;
+  }
   // levels are ordered by resolution: the small class is a prefix, direct a suffix
   {
     int a = 0;
@@ -619,8 +634,14 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   }
   PROF(1);
   const void* table = mixed ? h->buf.work16 : h->buf.params;
+  // ordered samples: levels [0, enc_binned) interpolate from LDS-staged bin boxes
+  const int le = sorted && h->encode_binned ? h->enc_binned : 0;
+  if (le > 0)
+    HIPCHK(launch_encode_binned(h->prec, mixed ? 1 : 0, h->ld, 0, le, h->sort_B, h->nb, h->d_meta(), h->d_plan(),
+                                h->d_binstart(), h->d_coords(), table, h->d_feat(), F, h->max_batch * F, s));
   HIPCHK(launch_encode(h->prec, mixed ? 1 : 0, h->ld, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
-                       h->d_coords(), table, h->d_feat(), F, h->max_batch * F, h->xcd_map, s));
+                       h->d_coords(), table, h->d_feat(), F, h->max_batch * F, h->xcd_map, s, le,
+                       h->enc.n_levels));
   PROF(2);
   const void* wsrc = mixed ? (const void*)((const uint16_t*)h->buf.work16 + h->n_table)
                            : (const void*)((const float*)h->buf.params + h->n_table);
@@ -1343,6 +1364,8 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
   } else if (n == "mlp_grid") {
     h->mlp_cap = (int)std::max<int64_t>(1, std::min<int64_t>(value, 2 * kMlpGrid));
     h->plan_total = -1;
+  } else if (n == "encode_binned") {
+    h->encode_binned = value ? 1 : 0;
   } else if (n == "priv_classes") {
     h->priv_classes = value ? 1 : 0;
   } else if (n == "scatter_strided") {

@@ -105,7 +105,17 @@ hipError_t launch_sample(const BlockMeta* meta, const BlockRange* range, const B
 // at one block's table.
 hipError_t launch_encode(Prec tp, int out_kind, const LevelDesc& ld, const BlockMeta* meta, const Tile* tiles,
                          int n_tiles, int direct_block, const BlockPlan* plan, const float* coords, const void* table,
-                         void* out, int64_t ss, int64_t ls, int xcd_map, hipStream_t s);
+                         void* out, int64_t ss, int64_t ls, int xcd_map, hipStream_t s, int l0 = 0, int l1 = -1);
+// Encoding forward of levels [l0, l1) over ordered samples (needs the ordered
+// sampler): one workgroup per (block, bin, level) stages the bin's vertex box
+// in LDS with coalesced rows and interpolates every sample of the bin from
+// it; a bin whose box exceeds the LDS budget gathers directly.
+hipError_t launch_encode_binned(Prec tp, int out_kind, const LevelDesc& ld, int l0, int l1, int B, int n_blocks,
+                                const BlockMeta* meta, const BlockPlan* plan, const int32_t* bin_start,
+                                const float* coords, const void* table, void* out, int64_t ss, int64_t ls,
+                                hipStream_t s);
+// Vertices of the LDS box budget of the binned encoding per table element size (bytes of F features).
+constexpr int kEncBoxBytes = 65536;
 
 // Encoding backward (scatter-add into gradient tables) of levels [l0, l1).
 hipError_t launch_scatter(Prec gp, const LevelDesc& ld, int l0, int l1, const BlockMeta* meta, const Tile* tiles,

@@ -133,9 +133,10 @@ __global__ __launch_bounds__(256) void k_encode(LevelDesc ld, const BlockMeta* _
                                                 const Tile* __restrict__ tiles, int n_tiles, int64_t n_direct,
                                                 int direct_block, const BlockPlan* __restrict__ plan,
                                                 const float* __restrict__ coords, const TT* __restrict__ table,
-                                                OT* __restrict__ out, int64_t ss, int64_t ls, int xcd_map) {
+                                                OT* __restrict__ out, int64_t ss, int64_t ls, int xcd_map,
+                                                int l0, int nl) {
   int tile, l;
-  if (!level_major_item(blockIdx.x, 0, ld.L, n_tiles, xcd_map, tile, l)) return;
+  if (!level_major_item(blockIdx.x, l0, nl, n_tiles, xcd_map, tile, l)) return;
   const SampleRef r = sample_ref(tiles, plan, tile, n_direct, direct_block, threadIdx.x);
   if (!r.valid) return;
   const float x = coords[3 * r.gi + 0], y = coords[3 * r.gi + 1], z = coords[3 * r.gi + 2];
@@ -175,16 +176,16 @@ __global__ __launch_bounds__(256) void k_encode(LevelDesc ld, const BlockMeta* _
 template <typename TT, typename WT, typename OT>
 static hipError_t enc_dispatch(const LevelDesc& ld, const BlockMeta* meta, const Tile* tiles, int n_tiles,
                                int64_t n_direct, int direct_block, const BlockPlan* plan, const float* coords, const void* table,
-                               void* out, int64_t ss, int64_t ls, int xcd_map, hipStream_t s) {
-  const int grid = level_major_grid(ld.L, n_tiles, xcd_map);
+                               void* out, int64_t ss, int64_t ls, int xcd_map, int l0, int nl, hipStream_t s) {
+  const int grid = level_major_grid(nl, n_tiles, xcd_map);
   if (grid <= 0) return hipSuccess;
   const TT* t = (const TT*)table;
   OT* o = (OT*)out;
   switch (ld.F) {
-    case 1: hipLaunchKernelGGL((k_encode<TT, WT, OT, 1>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map); break;
-    case 2: hipLaunchKernelGGL((k_encode<TT, WT, OT, 2>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map); break;
-    case 4: hipLaunchKernelGGL((k_encode<TT, WT, OT, 4>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map); break;
-    case 8: hipLaunchKernelGGL((k_encode<TT, WT, OT, 8>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map); break;
+    case 1: hipLaunchKernelGGL((k_encode<TT, WT, OT, 1>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
+    case 2: hipLaunchKernelGGL((k_encode<TT, WT, OT, 2>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
+    case 4: hipLaunchKernelGGL((k_encode<TT, WT, OT, 4>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
+    case 8: hipLaunchKernelGGL((k_encode<TT, WT, OT, 8>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -194,19 +195,22 @@ static hipError_t enc_dispatch(const LevelDesc& ld, const BlockMeta* meta, const
 // (then n_tiles is the sample count).
 hipError_t launch_encode(Prec tp, int out_kind, const LevelDesc& ld, const BlockMeta* meta, const Tile* tiles,
                          int n_tiles, int direct_block, const BlockPlan* plan, const float* coords, const void* table,
-                         void* out, int64_t ss, int64_t ls, int xcd_map, hipStream_t s) {
+                         void* out, int64_t ss, int64_t ls, int xcd_map, hipStream_t s, int l0, int l1) {
+  if (l1 < 0) l1 = ld.L;
+  const int nl = l1 - l0;
+  if (nl <= 0) return hipSuccess;
   int64_t n_direct = 0;
   int nt = n_tiles;
   if (!tiles) {
     n_direct = n_tiles;
     nt = (int)((n_direct + kTile - 1) / kTile);
   }
-  if (tp == Prec::F64) return enc_dispatch<double, double, double>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, table, out, ss, ls, xcd_map, s);
+  if (tp == Prec::F64) return enc_dispatch<double, double, double>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, table, out, ss, ls, xcd_map, l0, nl, s);
   if (tp == Prec::MIXED) {
-    if (out_kind == 1) return enc_dispatch<__half, float, __bf16>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, table, out, ss, ls, xcd_map, s);
-    return enc_dispatch<__half, float, float>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, table, out, ss, ls, xcd_map, s);
+    if (out_kind == 1) return enc_dispatch<__half, float, __bf16>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, table, out, ss, ls, xcd_map, l0, nl, s);
+    return enc_dispatch<__half, float, float>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, table, out, ss, ls, xcd_map, l0, nl, s);
   }
-  return enc_dispatch<float, float, float>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, table, out, ss, ls, xcd_map, s);
+  return enc_dispatch<float, float, float>(ld, meta, tiles, nt, n_direct, direct_block, plan, coords, table, out, ss, ls, xcd_map, l0, nl, s);
 }
 
 // ===========================================================================

@@ -183,9 +183,10 @@ def test_one_step_gradient_parity_c1(precision, grouped, waves):
     assert normwise(gg[nt:], g[nt:]) <= tol, "weight gradient"
 
 
-@pytest.mark.parametrize("precision,priv,classes", [("fp32", -1, 0), ("fp32", -1, 1), ("fp32", 0, 0),
-                                                    ("mixed", -1, 0), ("mixed", -1, 1), ("mixed", 2, 0)])
-def test_sorted_sampling_gradient_parity(precision, priv, classes):
+@pytest.mark.parametrize("precision,priv,classes,binned", [("fp32", -1, 0, 1), ("fp32", -1, 1, 1), ("fp32", 0, 0, 0),
+                                                           ("mixed", -1, 0, 1), ("mixed", -1, 1, 0),
+                                                           ("mixed", 2, 0, 1)])
+def test_sorted_sampling_gradient_parity(precision, priv, classes, binned):
     """Spatially ordered sampling stores the same Philox draws grouped by bin; the
     gradient (a sum over samples) must match the oracle's on the unordered draws."""
     say(f"ordered sampling + privatized scatter {precision} priv_levels={priv} LDS classes {classes}")
@@ -197,6 +198,7 @@ def test_sorted_sampling_gradient_parity(precision, priv, classes):
     model.set_option("spatial_sort", 1)
     model.set_option("priv_levels", priv)
     model.set_option("priv_classes", classes)
+    model.set_option("encode_binned", binned)
     model.set_option("apply_update", 0)
     model.set_option("use_graph", 0)
     loss = model.train(1, 4096, want_loss=True)
