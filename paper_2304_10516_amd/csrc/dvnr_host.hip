@@ -531,14 +531,16 @@ static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_
   // LDS class of each level from a bound on its bin box: ceil((R - 1) / B) + 2
   // cells per axis (the analytic box spans at most ceil((R - 1) / B) + 1)
   // binned encoding: leading levels whose bin box ((ceil((R-1)/B) + 2)^3
-  // vertices at most) fits the LDS budget
+  // vertices at most) fits the LDS budget and holds at most half as many
+  // vertices as the bin's samples would gather directly (8 per sample)
   {
     const int64_t vbytes = (int64_t)h->enc.n_features * (h->prec == Prec::MIXED ? 2 : 4);
     const int64_t boxv = kEncBoxBytes / vbytes;
+    const int64_t per_bin = min_n / ((int64_t)B * B * B);
     int le = 0;
     while (le < h->enc.n_levels) {
       const int64_t side = (h->ld.R[le] - 1 + B - 1) / B + 2;
-      if (side * side * side > boxv) break;
+      if (side * side * side > boxv || side * side * side > 4 * per_bin) break;
       ++le;
     }
     h->enc_binned = le;

@@ -115,7 +115,7 @@ hipError_t launch_encode_binned(Prec tp, int out_kind, const LevelDesc& ld, int 
                                 const float* coords, const void* table, void* out, int64_t ss, int64_t ls,
                                 hipStream_t s);
 // Vertices of the LDS box budget of the binned encoding per table element size (bytes of F features).
-constexpr int kEncBoxBytes = 65536;
+constexpr int kEncBoxBytes = 16384;
 
 // Encoding backward (scatter-add into gradient tables) of levels [l0, l1).
 hipError_t launch_scatter(Prec gp, const LevelDesc& ld, int l0, int l1, const BlockMeta* meta, const Tile* tiles,
