@@ -114,6 +114,27 @@ __device__ __forceinline__ void level_corners(const LevelDesc& ld, int l, float 
   }
 }
 
+// Spatial bins of the ordered sampler: B bins per axis of the unit cube.
+__device__ __forceinline__ int bin_1d(float x, int B) { return min((int)(x * (float)B), B - 1); }
+
+__device__ __forceinline__ int bin_of(float x, float y, float z, int B) {
+  return bin_1d(x, B) + B * (bin_1d(y, B) + B * bin_1d(z, B));
+}
+
+// Smallest and largest float32 x in [0, 1] that bin_1d puts in bin k (bin_1d
+// is monotone in x; k / B rounded is within an ulp of the boundary).
+__device__ __forceinline__ void bin_x_range(int k, int B, float& lo, float& hi) {
+  lo = (float)k / (float)B;
+  for (int it = 0; it < 4 && lo > 0.0f && bin_1d(nextafterf(lo, -1.0f), B) >= k; ++it) lo = nextafterf(lo, -1.0f);
+  for (int it = 0; it < 4 && bin_1d(lo, B) < k; ++it) lo = nextafterf(lo, 2.0f);
+  hi = 1.0f;
+  if (k < B - 1) {
+    hi = (float)(k + 1) / (float)B;
+    for (int it = 0; it < 4 && bin_1d(hi, B) > k; ++it) hi = nextafterf(hi, -1.0f);
+    for (int it = 0; it < 4 && hi < 1.0f && bin_1d(nextafterf(hi, 2.0f), B) <= k; ++it) hi = nextafterf(hi, 2.0f);
+  }
+}
+
 // Wave-level helpers
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
