@@ -381,6 +381,9 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *                          (default 1 for mixed, 0 for fp32); enables the
  *                          bin-privatized backward of the coarse levels
  *  "priv_levels"     n   : privatize levels [0, n) (-1: chosen per plan)
+ *  "scatter_concurrent" 0/1 : run the privatized levels whose bin boxes never
+ *                          fit LDS (direct atomics) on a second stream,
+ *                          concurrently with the others (default 0)
  *  "encode_binned"   0/1 : with ordered sampling, interpolate the coarse levels
  *                          (bin box within 16 KB and at most half the bin's
  *                          direct gathers) from LDS-staged boxes (default 1)

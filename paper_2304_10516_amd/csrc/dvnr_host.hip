@@ -126,9 +126,18 @@ struct dvnr {
   size_t pelem() const { return prec == Prec::F64 ? 8 : 4; }
   size_t ielem() const { return prec == Prec::MIXED ? 2 : pelem(); }  // inference copy element
 
+  // second stream (default priority): the direct-class levels of the
+  // privatized backward run on it concurrently with the LDS-class levels,
+  // forked and joined with events inside the step (also under graph capture)
+  int scatter_concurrent = 0;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~dvnr() {
     if (graph) (void)hipGraphExecDestroy(graph);
     for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
   }
 };
 
@@ -659,15 +668,31 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   // to matter more than per-XCD table locality here).
   {
     // priv_classes 0: one launch (large class) for all privatized levels, so that
-    // the LDS-bound coarse and the atomic-bound fine levels overlap on the chip
+    // the LDS-bound coarse and the atomic-bound fine levels overlap on the chip;
+    // scatter_concurrent: the direct-class levels on the second stream instead
+    const bool conc = h->scatter_concurrent != 0;
     const int a = h->priv_classes ? std::min(h->priv_small, lp) : 0;
-    const int c = h->priv_classes ? std::min(std::max(h->priv_direct, a), lp) : lp;
-    const int cls[3][3] = {{0, a, 1}, {a, c, 2}, {c, lp, 0}};
+    const int c = h->priv_classes || conc ? std::min(std::max(h->priv_direct, a), lp) : lp;
+    if (conc && c < lp) {
+      if (!h->side) {
+        HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+      }
+      HIPCHK(hipEventRecord(h->ev_fork, s));
+      HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+      HIPCHK(launch_scatter_priv(h->ld, c, lp, h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(),
+                                 h->d_coords(), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, 0, 0,
+                                 h->side));
+      HIPCHK(hipEventRecord(h->ev_join, h->side));
+    }
+    const int cls[3][3] = {{0, a, 1}, {a, c, 2}, {c, conc ? c : lp, 0}};
     for (const auto& r : cls)
       if (r[1] > r[0])
         HIPCHK(launch_scatter_priv(h->ld, r[0], r[1], h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(),
                                    h->d_coords(), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, 0, r[2],
                                    s));
+    if (conc && c < lp) HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
   }
   PROF(4);
   HIPCHK(launch_scatter(Prec::F32, h->ld, lp, h->enc.n_levels, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
@@ -1366,6 +1391,8 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
   } else if (n == "mlp_grid") {
     h->mlp_cap = (int)std::max<int64_t>(1, std::min<int64_t>(value, 2 * kMlpGrid));
     h->plan_total = -1;
+  } else if (n == "scatter_concurrent") {
+    h->scatter_concurrent = value ? 1 : 0;
   } else if (n == "encode_binned") {
     h->encode_binned = value ? 1 : 0;
   } else if (n == "priv_classes") {
