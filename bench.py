@@ -42,24 +42,39 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def phase_bytes(precision, phase, n_levels_priv):
-    """Algorithmic bytes per training sample of a phase (per launch = this x samples per step).
+def phase_bytes(precision, phase, res):
+    """Algorithmic bytes of one launch of a phase's kernel (None: not a byte-bound phase).
 
+    Per sample (x samples per step), with lp the bin-privatized levels [0, lp),
+    lf the first destination-partitioned level and nd = lf - lp direct levels:
     sample       : 3 coords written (12) + 8 voxel reads (32) + target written (4) = 48
     encode       : coords (12) + L levels x 8 corners x F x table element (2 B fp16, 4 B fp32)
                    + L x F features written (2 B bf16, 4 B fp32)
-    scatter_priv : the bin-privatized levels [0, lp): coords (12) + lp x F dX reads (4 B)
-                   + lp x 8 corners x F fp32 gradient adds (4 B)
-    scatter      : the same for the remaining levels [lp, L) (direct atomics)
+    scatter_priv : coords (12) + lp x F dL/dy reads (4 B) + lp x 8 corners x F fp32 gradient adds (4 B)
+    scatter      : the same for the nd direct levels
+    part_bucket  : coords (12) + np x F dL/dy reads (4 B) + np x 8 records of (1 + F) x 4 B written,
+                   np = L - lf partitioned levels
+    part_accum   : np x 8 records read, plus per launch one read and one write of
+                   every partitioned table entry (F x 4 B each way)
     """
     te = 2 if precision == "mixed" else 4
+    batch = res["batch"]
+    lp, lf = res["priv_levels"], res["part_levels"]
+    npart = L_LEVELS - lf
     if phase == "sample":
-        return 48
+        return 48 * batch
     if phase == "encode":
-        return 12 + L_LEVELS * 8 * F_FEAT * te + L_LEVELS * F_FEAT * te
-    nl = n_levels_priv if phase == "scatter_priv" else L_LEVELS - n_levels_priv
+        return (12 + L_LEVELS * 8 * F_FEAT * te + L_LEVELS * F_FEAT * te) * batch
     if phase in ("scatter_priv", "scatter"):
-        return (12 + nl * F_FEAT * 4 + nl * 8 * F_FEAT * 4) if nl > 0 else 0
+        nl = lp if phase == "scatter_priv" else lf - lp
+        return (12 + nl * F_FEAT * 4 + nl * 8 * F_FEAT * 4) * batch if nl > 0 else 0
+    if phase == "part_bucket":
+        return (12 + npart * F_FEAT * 4 + npart * 8 * (1 + F_FEAT) * 4) * batch if npart > 0 else 0
+    if phase == "part_accum":
+        if npart <= 0:
+            return 0
+        entries = sum(res["level_entries"][lf:]) * res["n_blocks"]
+        return npart * 8 * (1 + F_FEAT) * 4 * batch + entries * F_FEAT * 4 * 2
     return None
 
 
@@ -129,6 +144,7 @@ def run_precision(torch, DVNR, cfg, blocks, vols, precision, steps, warmup, seed
         stream.synchronize()
         t1 = time.perf_counter()
         bins, priv = model.plan_info()
+        part = model.partitioned_levels()
         outs = [torch.empty((d[2], d[1], d[0]), dtype=torch.float32, device="cuda") for d, _ in blocks]
         for b in range(len(blocks)):  # warm
             model.decode(b, out=outs[b], stream=stream)
@@ -175,9 +191,10 @@ def run_precision(torch, DVNR, cfg, blocks, vols, precision, steps, warmup, seed
                decode_voxels_per_s=cnt / (dec_ms * 1e-3), psnr=float(10 * np.log10(cnt / sse)),
                loss_first=float(lossv[0]), loss_last=float(lossv[-1]),
                phase_ms={k: v / max(nsteps, 1) for k, v in phases.items()}, n_params=model.sizes.n_params,
-               bins_per_axis=bins, priv_levels=priv, batch=batch, render=render)
+               bins_per_axis=bins, priv_levels=priv, part_levels=part, batch=batch, render=render,
+               level_entries=model.level_info()[3], n_blocks=len(blocks))
     log(f"[bench] {precision}: {ms:.3f} ms/step, {res['samples_per_s'] / 1e6:.1f} M samples/s, "
-        f"psnr {res['psnr']:.2f} dB, decode {dec_ms:.2f} ms, bins {bins}^3, privatized levels {priv}, phases " +
+        f"psnr {res['psnr']:.2f} dB, decode {dec_ms:.2f} ms, bins {bins}^3, privatized levels {priv}, partitioned from level {part}, phases " +
         ", ".join(f"{k} {v:.3f}" for k, v in res["phase_ms"].items()))
     del model
     return res
@@ -226,11 +243,15 @@ def run_timeseries(torch, DVNR, cfg, precision, n_timesteps, steps_per_t, seed=3
 
 
 PHASE_KERNEL = {"scatter_priv": "k_scatter_priv", "scatter": "k_scatter", "adam": "k_adam", "encode": "k_encode",
-                "mlp": "k_mlp_train", "sample": "k_sort_place", "reduce": "k_reduce_slots"}
+                "mlp": "k_mlp_train", "sample": "k_sort_place", "reduce": "k_reduce_slots",
+                "part_bucket": "k_part_bucket", "part_accum": "k_part_accum"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "train_step_256cube_hbm_counters.md")
 
 
-KERNEL_SOURCES = {"k_scatter_priv": ["k_sort.hip", "dvnr_device.h", "dvnr_internal.h"]}
+KERNEL_SOURCES = {"k_scatter_priv": ["k_sort.hip", "dvnr_device.h", "dvnr_internal.h"],
+                  "k_part_bucket": ["k_scatter_part.hip", "dvnr_device.h", "dvnr_internal.h"],
+                  "k_part_accum": ["k_scatter_part.hip", "dvnr_device.h", "dvnr_internal.h"],
+                  "k_adam": ["k_core.hip", "dvnr_device.h", "dvnr_internal.h"]}
 
 
 def sources_digest(kernel):
@@ -254,7 +275,8 @@ def measured_traffic(phase):
             for line in f:
                 if line.startswith("traffic-record:"):
                     rec = json.loads(line.split(":", 1)[1])
-                    if rec["kernel"] == PHASE_KERNEL.get(phase) and rec["sources_sha256"] == sources_digest(rec["kernel"]):
+                    if (rec["kernel"] == PHASE_KERNEL.get(phase) and rec["kernel"] in KERNEL_SOURCES
+                            and rec["sources_sha256"] == sources_digest(rec["kernel"])):
                         return rec["read_bytes"] + rec["write_bytes"]
     except (OSError, ValueError, KeyError):
         return None
@@ -267,18 +289,25 @@ def roofline_for(precision, res):
     batch = res["batch"]
     if dom == "adam":
         per_launch = ADAM_BYTES_PER_PARAM[precision] * res["n_params"]
-    elif phase_bytes(precision, dom, res["priv_levels"]) is not None:
-        per_launch = phase_bytes(precision, dom, res["priv_levels"]) * batch
+    elif phase_bytes(precision, dom, res) is not None:
+        per_launch = phase_bytes(precision, dom, res)
     else:  # mlp: MFMA-bound reading, 37,248 flop per sample
         flops = 37248.0 * batch
         tf = flops / (ph[dom] * 1e-3) / 1e12
         peak = 2500.0 if precision == "mixed" else 157.3
-        return {"kernel": dom, "bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
-                "frac": tf / peak, "traffic": None}
+        return {"kernel": PHASE_KERNEL.get(dom, dom), "phase": dom, "bound": "mfma", "achieved": tf, "peak": peak,
+                "unit": "TFLOP/s", "frac": tf / peak, "traffic": None}
     gbs = per_launch / (ph[dom] * 1e-3) / 1e9
-    return {"kernel": dom, "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": gbs / PEAK_HBM_GBS, "traffic": measured_traffic(dom) if precision == "mixed" else None,
-            "algorithmic_bytes_per_launch": per_launch, "avg_launch_ms": ph[dom]}
+    # the other byte-bound phases against the same peak
+    others = {}
+    for k, v in ph.items():
+        b = ADAM_BYTES_PER_PARAM[precision] * res["n_params"] if k == "adam" else phase_bytes(precision, k, res)
+        if k != dom and b and v > 0:
+            others[k] = round(b / (v * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+    return {"kernel": PHASE_KERNEL.get(dom, dom), "phase": dom, "bound": "hbm", "achieved": gbs,
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+            "traffic": measured_traffic(dom) if precision == "mixed" else None,
+            "algorithmic_bytes_per_launch": per_launch, "avg_launch_ms": ph[dom], "other_phases_frac": others}
 
 
 def cpu_baseline(cfg, vol, dims, n_samples):

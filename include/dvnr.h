@@ -317,12 +317,15 @@ dvnr_status dvnr_debug_indices(dvnr_t* h, int32_t level, int64_t n, const float*
 /* Per-phase device time in milliseconds, summed over the training steps run
  * with the "profile_phases" option since the previous call (those steps run
  * eagerly, with HIP events on the training stream between the phases):
- * ms7[0] sampler, [1] encoding forward, [2] MLP forward/loss/backward,
+ * ms[0] sampler, [1] encoding forward, [2] MLP forward/loss/backward,
  * [3] encoding backward of the bin-privatized levels, [4] encoding backward
- * of the remaining levels (direct atomics), [5] weight-gradient reduction,
- * [6] Adam.  *n_steps (may be NULL) receives the number of steps covered.
- * Waits for those steps to finish; resets the sums. */
-dvnr_status dvnr_phase_times(dvnr_t* h, double* ms7, int64_t* n_steps);
+ * by direct atomics, [5] and [6] the two passes of the destination-partitioned
+ * encoding backward (bucketing, slice sums), [7] weight-gradient reduction,
+ * [8] Adam; `ms` holds DVNR_N_PHASES doubles.  *n_steps (may be NULL)
+ * receives the number of steps covered.  Waits for those steps to finish;
+ * resets the sums. */
+#define DVNR_N_PHASES 9
+dvnr_status dvnr_phase_times(dvnr_t* h, double* ms, int64_t* n_steps);
 
 /* Autotuner: time the candidate step configurations (unordered or spatially
  * ordered sampling, the number of bin-privatized coarse levels, the number of
@@ -341,6 +344,11 @@ dvnr_status dvnr_autotune(dvnr_t* h, int64_t samples_per_step, int32_t n_trial_s
  * number of coarse levels whose encoding backward is bin-privatized (levels
  * [0, *priv_levels)); 0 when ordered sampling is off.  Any pointer may be NULL. */
 dvnr_status dvnr_plan_info(const dvnr_t* h, int32_t* bins_per_axis, int32_t* priv_levels);
+
+/* First level of the current training plan whose encoding backward is
+ * destination-partitioned (levels [*first_level, n_levels)); n_levels when
+ * none is.  See the "scatter_part" option. */
+dvnr_status dvnr_plan_partition(const dvnr_t* h, int32_t* first_level);
 
 /* Wait for `stream`; reports HIP errors and a non-finite loss seen since the
  * last dvnr_sync (DVNR_E_NONFINITE). */
@@ -397,6 +405,24 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *                          kernel, in waves per SIMD (default 1)
  *  "mlp_grid"        n   : workgroups of the persistent MLP training kernel
  *                          (1 .. 512, default 256; also set by dvnr_autotune)
+ *  "scatter_part"    n   : destination-partitioned encoding backward of the
+ *                          levels [n, n_levels) (-1, the default: for mixed
+ *                          precision, the hashed levels when they get at
+ *                          least one contribution per table entry per step;
+ *                          none for fp32; >= n_levels: none).  Each step sorts the levels'
+ *                          (sample, corner) contributions into per-slice
+ *                          buckets (slices of "part_slice" / F entries) and sums
+ *                          each bucket in LDS, instead of one global atomic per
+ *                          contribution.  Levels with more than 256 slices stay
+ *                          on the atomic paths, and so do levels with fewer
+ *                          than 2^16 entries (the workspace holds buckets
+ *                          for the others: about 40 (1 + F) bytes per
+ *                          sample of max_batch and level).
+ *  "part_slice"      n   : fp32 accumulators per slice: 4096, 8192 (default)
+ *                          or 16384
+ *  "part_capacity"   n   : cap every bucket at n records (0, the default: 1.25x
+ *                          the mean load plus 32); records beyond a bucket's
+ *                          capacity are added by direct atomics (tests)
  * Returns DVNR_E_INVALID for an unknown name. */
 dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value);
 

@@ -107,6 +107,7 @@ SIGNATURES = {
     "dvnr_train_until": [P, C.POINTER(StopPolicy), I64, C.POINTER(C.c_int64), C.POINTER(C.c_double), VP],
     "dvnr_phase_times": [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
     "dvnr_plan_info": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+    "dvnr_plan_partition": [P, C.POINTER(C.c_int32)],
     "dvnr_autotune": [P, I64, I32, C.POINTER(C.c_double), VP],
 }
 

@@ -96,8 +96,9 @@ struct dvnr {
   int profile = 0;
   std::vector<hipEvent_t> prof_ev;
   int64_t prof_recorded = 0, prof_accumulated = 0;
-  static constexpr int kPhases = 7;  // sample, encode, mlp, scatter (privatized), scatter (direct), reduce, adam
-  double prof_ms[kPhases] = {0, 0, 0, 0, 0, 0, 0};
+  // sample, encode, mlp, scatter (privatized), scatter (direct), partition pass 1, pass 2, reduce, adam
+  static constexpr int kPhases = DVNR_N_PHASES;
+  double prof_ms[kPhases] = {};
   hipGraphExec_t graph = nullptr;
   hipStream_t graph_stream = nullptr;
   int64_t graph_total = -1;
@@ -132,6 +133,19 @@ struct dvnr {
   int scatter_concurrent = 0;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // destination-partitioned backward of the fine levels [part_l0, L): bucket
+  // layout, cursors and records in one library-owned allocation (grown on demand)
+  int scatter_part = -1;  // option: first partitioned level (-1: chosen per plan; >= L: none)
+  int part_cap = 0;       // option: bucket capacity override in records (0: automatic)
+  int part_slice_floats = 8192;  // option: fp32 accumulators per slice
+  int part_min = 0;       // first level that may be partitioned (workspace sized for [part_min, L))
+  int part_l0 = 0;
+  PartDesc pdesc{};
+  int64_t o_pblk = 0, o_pcur = 0, o_precs = 0, o_ptmax = 0;
+  PartBlock* d_pblk() const { return (PartBlock*)(ws() + o_pblk); }
+  float* d_ptmax() const { return (float*)(ws() + o_ptmax); }  // [levels][tiles] largest contribution
+  int32_t* d_pcur() const { return (int32_t*)(ws() + o_pcur); }
+  uint32_t* d_precs() const { return (uint32_t*)(ws() + o_precs); }
   ~dvnr() {
     if (graph) (void)hipGraphExecDestroy(graph);
     for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
@@ -194,6 +208,24 @@ static bool build_levels(const dvnr_encoding& e, LevelDesc& ld, int64_t& n_entri
     return false;
   }
   return true;
+}
+
+// Table entries of level l.
+static int64_t level_entries(const dvnr_t* h, int l) {
+  const int64_t R = h->ld.R[l];
+  return h->ld.dense[l] ? R * R * R : ((int64_t)1 << h->enc.log2_table_size);
+}
+
+// Sub-bucket capacity: 1.25x the mean load of a block's (slice, sub-bucket)
+// plus 8 records.  Sub-buckets per bucket: about one per 512 records of the
+// lightest bucket, a power of two in [1, kPartSub]; then a level's ns * nsub
+// <= max(ns, 8 n / 512) for every block, so its records are at most
+// 10 n + 9 (kPartMaxSlices + n / 64) per block (the workspace bound).
+static int64_t part_bucket_cap(int64_t n, int ns, int nsub) {
+  return n > 0 ? (10 * n + (int64_t)ns * nsub - 1) / ((int64_t)ns * nsub) + 8 : 0;
+}
+static int64_t part_level_records(int64_t max_batch, int n_blocks) {
+  return 10 * max_batch + 9 * (max_batch / 64 + 1) + (int64_t)9 * kPartMaxSlices * n_blocks;
 }
 
 extern "C" {
@@ -301,6 +333,23 @@ dvnr_status dvnr_create(const dvnr_encoding* enc, const dvnr_mlp* mlp, const dvn
     h->o_counts = take(sizeof(uint32_t) * kMaxBins * h->max_groups);
     h->o_binstart = take(sizeof(int32_t) * (kMaxBins + 1) * n_blocks);
     h->o_totals = take(sizeof(uint32_t) * kMaxBins * n_blocks);
+    // destination-partitioned backward: the suffix of levels whose tables have
+    // at least kPartMinEntries entries and fit kPartMaxSlices of the largest slices
+    {
+      int pm = e.n_levels;
+      while (pm > 0) {
+        const int64_t E = level_entries(h, pm - 1);
+        if (E < kPartMinEntries || E > (int64_t)kPartMaxSlices * (kPartSliceMax / e.n_features)) break;
+        --pm;
+      }
+      h->part_min = pm;
+      h->part_l0 = e.n_levels;
+      const int64_t nl = e.n_levels - pm;
+      h->o_pblk = take(sizeof(PartBlock) * n_blocks);
+      h->o_ptmax = take(sizeof(float) * nl * h->max_tiles);
+      h->o_pcur = take(sizeof(int32_t) * kPartSub * kPartMaxSlices * nl * n_blocks);
+      h->o_precs = take(sizeof(uint32_t) * (1 + e.n_features) * nl * part_level_records(max_batch, n_blocks));
+    }
     h->spatial_sort = (h->prec == Prec::MIXED) ? 1 : 0;
     h->ws_bytes = o;
     *out = h;
@@ -474,6 +523,79 @@ static std::vector<int64_t> apportion(const dvnr_t* h, int64_t total) {
 // Boundary samples among n: boundary_frac * n rounded half up.
 static int64_t boundary_count(int64_t n, double frac) { return (int64_t)std::floor(frac * (double)n + 0.5); }
 
+// Levels of the destination-partitioned backward and their bucket layout.
+// Auto choice (mixed precision): the hashed levels, when they receive at
+// least one contribution per table entry per step on average over the
+// sampled blocks (there a bin's vertex box no longer merges contributions,
+// while the dense levels' boxes still do).  Only levels from part_min (sized
+// into the workspace) with at most kPartMaxSlices slices qualify.
+static dvnr_status plan_partition(dvnr_t* h, const std::vector<int64_t>& n, hipStream_t s) {
+  const int L = h->enc.n_levels, F = h->enc.n_features;
+  const int sf = h->part_slice_floats;
+  int sh = 0;
+  while (((int64_t)2 << sh) * F <= sf) ++sh;
+  const int64_t S = (int64_t)1 << sh;
+  int64_t sum = 0, act = 0;
+  for (auto v : n)
+    if (v > 0) sum += v, ++act;
+  const double avg = act ? (double)sum / (double)act : 0.0;
+  int lf = L;
+  if (h->scatter_part >= 0) {
+    lf = std::min(h->scatter_part, L);
+  } else if (h->prec == Prec::MIXED) {
+    while (lf > 0 && !h->ld.dense[lf - 1] && 8.0 * avg >= (double)level_entries(h, lf - 1)) --lf;
+  }
+  lf = std::max(lf, h->part_min);
+  for (int l = lf; l < L; ++l)
+    if (level_entries(h, l) > kPartMaxSlices * S) lf = l + 1;
+  if (act == 0) lf = L;
+  h->part_l0 = lf;
+  PartDesc& pd = h->pdesc;
+  pd = PartDesc{};
+  pd.l0 = lf;
+  pd.nl = L - lf;
+  pd.slice_floats = sf;
+  int nq = 0;
+  for (int l = lf; l < L; ++l) {
+    pd.E[l] = (int32_t)level_entries(h, l);
+    pd.sh[l] = sh;
+    pd.ns[l] = (int32_t)((pd.E[l] + S - 1) / S);
+    pd.qbase[l] = nq;
+    nq += pd.ns[l];
+  }
+  pd.nq = nq;
+  if (lf >= L) return DVNR_OK;
+  {
+    int64_t n_min = INT64_MAX;
+    int ns_max = 1;
+    for (auto v : n)
+      if (v > 0) n_min = std::min(n_min, v);
+    for (int l = lf; l < L; ++l) ns_max = std::max(ns_max, (int)pd.ns[l]);
+    int g = 1;
+    while (2 * g <= kPartSub && 8 * n_min >= (int64_t)2 * g * 512 * ns_max) g *= 2;
+    pd.nsub = g;
+  }
+  std::vector<PartBlock> pbv(h->nb, PartBlock{});
+  int64_t rec = 0;
+  for (int b = 0; b < h->nb; ++b) {
+    for (int l = lf; l < L; ++l) {
+      int64_t cap = part_bucket_cap(n[b], pd.ns[l], pd.nsub);
+      if (h->part_cap > 0) cap = std::min<int64_t>(cap, h->part_cap);
+      pbv[b].off[l] = rec;
+      pbv[b].cap[l] = (int32_t)cap;
+      rec += cap * pd.ns[l] * pd.nsub;
+    }
+  }
+  for (int t = h->n_tiles - 1; t >= 0; --t) pbv[h->htiles[t].block].tile0 = t;
+  for (int t = 0; t < h->n_tiles; ++t) pbv[h->htiles[t].block].ntiles += 1;
+  if (rec > (int64_t)(L - h->part_min) * part_level_records(h->max_batch, h->nb) ||
+      (int64_t)nq * h->nb > (int64_t)(L - h->part_min) * kPartMaxSlices * h->nb || h->n_tiles > h->max_tiles)
+    return fail(DVNR_E_INVALID, "partitioned backward exceeds its workspace");
+  HIPCHK(hipMemcpyAsync(h->d_pblk(), pbv.data(), sizeof(PartBlock) * h->nb, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(h->d_pcur(), 0, sizeof(int32_t) * kPartSub * h->nb * nq, s));
+  return DVNR_OK;
+}
+
 static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_t s) {
   int64_t total = 0;
   for (auto v : n) total += v;
@@ -573,6 +695,10 @@ static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_
     h->priv_direct = c;
   }
   h->priv_L = h->priv_levels >= 0 ? std::min(h->priv_levels, h->enc.n_levels) : pl;
+  {
+    dvnr_status st = plan_partition(h, n, s);
+    if (st) return st;
+  }
   HIPCHK(hipMemcpyAsync(h->d_plan(), h->hplan.data(), sizeof(BlockPlan) * h->nb, hipMemcpyHostToDevice, s));
   if (h->n_tiles)
     HIPCHK(hipMemcpyAsync(h->d_tiles(), h->htiles.data(), sizeof(Tile) * h->n_tiles, hipMemcpyHostToDevice, s));
@@ -660,7 +786,8 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
                           h->d_target(), wsrc, h->d_dfeat(), h->max_batch, h->d_slots(), h->slot_stride, h->mlp_grid,
                           h->loss_l1, h->mlp_waves, s));
   PROF(3);
-  const int lp = sorted ? h->priv_L : 0;
+  const int lf = h->part_l0;  // levels [lf, L): destination-partitioned
+  const int lp = std::min(sorted ? h->priv_L : 0, lf);
   // privatized levels [0, lp) in up to three launches by LDS class: small boxes
   // (coarse levels, high occupancy), large boxes, and levels whose boxes never
   // fit (direct atomics over each bin's samples, no LDS).  Plain workgroup
@@ -695,15 +822,24 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
     if (conc && c < lp) HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
   }
   PROF(4);
-  HIPCHK(launch_scatter(Prec::F32, h->ld, lp, h->enc.n_levels, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
+  HIPCHK(launch_scatter(Prec::F32, h->ld, lp, lf, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
                         h->d_coords(), h->d_dfeat(), F, h->max_batch * F, h->buf.grads, h->scatter_grouped,
                         h->xcd_map, sorted ? h->scatter_strided : 0, s));
   PROF(5);
+  if (lf < h->enc.n_levels)
+    HIPCHK(launch_part_bucket(h->ld, h->pdesc, h->d_meta(), h->d_tiles(), h->n_tiles, h->d_plan(), h->d_pblk(),
+                              h->d_coords(), h->d_dfeat(), h->max_batch * F, h->d_pcur(), h->d_precs(),
+                              h->d_ptmax(), (float*)h->buf.grads, s));
+  PROF(6);
+  if (lf < h->enc.n_levels)
+    HIPCHK(launch_part_accum(h->ld, h->pdesc, h->d_meta(), h->nb, h->n_tiles, h->d_plan(), h->d_pblk(),
+                             h->d_pcur(), h->d_precs(), h->d_ptmax(), (float*)h->buf.grads, s));
+  PROF(7);
   HIPCHK(launch_reduce_slots(h->d_slots(), h->slot_stride, h->d_ranges(), h->nb, h->n_mlp, h->n_table, h->stride,
                              Prec::F32, h->buf.grads, h->d_ring(), h->d_ctr(), 1, s));
-  PROF(6);
+  PROF(8);
   if (!h->apply_update) {
-    PROF(7);
+    PROF(9);
     return DVNR_OK;
   }
   HIPCHK(launch_adam(h->prec, h->buf.params, h->buf.grads, h->buf.adam_m, h->buf.adam_v,
@@ -711,7 +847,7 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
                      h->d_plan(), h->d_ctr(), h->opt.lr, h->opt.beta1, h->opt.beta2, h->opt.eps,
                      h->opt.weight_decay, h->opt.lr_decay_interval > 0 ? h->opt.lr_decay_base : 1.0,
                      h->opt.lr_decay_start, h->opt.lr_decay_interval > 0 ? h->opt.lr_decay_interval : 0, s));
-  PROF(7);
+  PROF(9);
   return DVNR_OK;
 }
 
@@ -1359,19 +1495,25 @@ dvnr_status dvnr_plan_info(const dvnr_t* h, int32_t* bins_per_axis, int32_t* pri
   if (!h) return fail(DVNR_E_INVALID, "null handle");
   const bool on = h->spatial_sort && h->n_groups > 0;
   if (bins_per_axis) *bins_per_axis = on ? h->sort_B : 0;
-  if (priv_levels) *priv_levels = on ? h->priv_L : 0;
+  if (priv_levels) *priv_levels = on ? std::min(h->priv_L, h->part_l0) : 0;
   return DVNR_OK;
 }
 
-dvnr_status dvnr_phase_times(dvnr_t* h, double* ms7, int64_t* n_steps) {
-  if (!h || !ms7) return fail(DVNR_E_INVALID, "null argument");
+dvnr_status dvnr_plan_partition(const dvnr_t* h, int32_t* first_level) {
+  if (!h || !first_level) return fail(DVNR_E_INVALID, "null argument");
+  *first_level = h->part_l0;
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_phase_times(dvnr_t* h, double* ms, int64_t* n_steps) {
+  if (!h || !ms) return fail(DVNR_E_INVALID, "null argument");
   while (h->prof_accumulated < h->prof_recorded) {
     dvnr_status st = prof_accumulate_one(h, h->prof_accumulated);
     if (st) return st;
     h->prof_accumulated += 1;
   }
   for (int p = 0; p < dvnr::kPhases; ++p) {
-    ms7[p] = h->prof_ms[p];
+    ms[p] = h->prof_ms[p];
     h->prof_ms[p] = 0.0;
   }
   if (n_steps) *n_steps = h->prof_recorded;
@@ -1390,6 +1532,16 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
     h->mlp_waves = value >= 2 ? 2 : 1;
   } else if (n == "mlp_grid") {
     h->mlp_cap = (int)std::max<int64_t>(1, std::min<int64_t>(value, 2 * kMlpGrid));
+    h->plan_total = -1;
+  } else if (n == "scatter_part") {
+    h->scatter_part = (int)std::max<int64_t>(-1, std::min<int64_t>(value, kMaxLevels));
+    h->plan_total = -1;  // the partitioned levels and buckets live in the plan
+  } else if (n == "part_slice") {
+    if (value != 4096 && value != 8192 && value != 16384) return fail(DVNR_E_INVALID, "part_slice: 4096, 8192 or 16384");
+    h->part_slice_floats = (int)value;
+    h->plan_total = -1;
+  } else if (n == "part_capacity") {
+    h->part_cap = (int)std::max<int64_t>(0, std::min<int64_t>(value, 1 << 30));
     h->plan_total = -1;
   } else if (n == "scatter_concurrent") {
     h->scatter_concurrent = value ? 1 : 0;

@@ -122,6 +122,50 @@ hipError_t launch_scatter(Prec gp, const LevelDesc& ld, int l0, int l1, const Bl
                           int n_tiles, int direct_block, const BlockPlan* plan, const float* coords, const void* dfeat,
                           int64_t ss, int64_t ls, void* grad, int grouped, int xcd_map, int strided, hipStream_t s);
 
+// Destination-partitioned encoding backward of the levels [l0, l0 + nl): the
+// gradient table of such a level is cut into slices of 2^sh[l] entries (at
+// most kPartSliceMax fp32 accumulators); slice s of level l of a block owns
+// bucket q = qbase[l] + s of that block (nq buckets per block).
+constexpr int kPartSliceMax = 16384;  // accumulators of one slice (64 KB of LDS)
+constexpr int kPartMaxSlices = 256;   // slices of one level
+constexpr int kPartMinEntries = 1 << 16;  // smallest table that may be partitioned
+constexpr int kPartSub = 16;          // sub-buckets per bucket (tile t appends to sub-bucket t % kPartSub)
+struct PartDesc {
+  int32_t l0, nl;
+  int32_t nq;                    // buckets per block
+  int32_t slice_floats;          // accumulators per slice (2^sh[l] * F)
+  int32_t nsub;                  // sub-buckets per bucket in use (1 .. kPartSub)
+  int32_t sh[kMaxLevels];        // log2 of entries per slice
+  int32_t ns[kMaxLevels];        // slices of level l (ceil(entries / 2^sh), <= kPartMaxSlices)
+  int32_t qbase[kMaxLevels];     // first bucket of level l
+  int32_t E[kMaxLevels];         // entries of level l
+};
+// Per-block bucket layout: sub-bucket g of bucket (level l, slice s) starts at
+// record off[l] + (s * nsub + g) * cap[l] of the record buffer and holds at
+// most cap[l] records; its cursor is cursor[(b * nq + q) * kPartSub + g].  The
+// block's tiles are [tile0, tile0 + ntiles).
+struct PartBlock {
+  int64_t off[kMaxLevels];
+  int32_t cap[kMaxLevels];
+  int32_t tile0, ntiles;
+};
+// Pass 1 over the tiles: every (sample, corner) contribution of the levels is
+// appended, as one record of 1 + F words (slice << 16 | entry within the
+// slice, then F floats), to its slice's bucket (sub-bucket tile % nsub);
+// a full sub-bucket's overflow is added to `grad` directly; tmax[(l - l0) *
+// n_tiles + tile] receives the tile's largest |contribution|.  Pass 2: one
+// workgroup per (block, level, slice) sums its bucket in LDS (64-bit fixed
+// point scaled by the block's largest contribution), adds the slice into
+// `grad` and clears the bucket's cursors (cursors start at zero and are left
+// at zero).
+hipError_t launch_part_bucket(const LevelDesc& ld, const PartDesc& pd, const BlockMeta* meta, const Tile* tiles,
+                              int n_tiles, const BlockPlan* plan, const PartBlock* pb, const float* coords,
+                              const float* dfeat, int64_t ls, int32_t* cursor, uint32_t* recs, float* tmax,
+                              float* grad, hipStream_t s);
+hipError_t launch_part_accum(const LevelDesc& ld, const PartDesc& pd, const BlockMeta* meta, int n_blocks,
+                             int n_tiles, const BlockPlan* plan, const PartBlock* pb, int32_t* cursor,
+                             const uint32_t* recs, const float* tmax, float* grad, hipStream_t s);
+
 // Spatially ordered sampler: Philox draws of every group (<= kSortGroup
 // samples of one block) stored grouped by B^3 spatial bins; bin_start
 // [n_blocks][kMaxBins + 1] receives each bin's first sample (within the block).

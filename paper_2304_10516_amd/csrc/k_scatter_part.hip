@@ -1,0 +1,313 @@
+// Destination-partitioned encoding backward (gfx950) for levels with large
+// tables.
+//
+// On a fine level nearly every (sample, corner) contribution of a step lands
+// on its own table entry, spread over the whole table by the spatial hash, so
+// neither a bin's LDS box nor wave aggregation merges them: one global atomic
+// per contribution is paid at the L2 atomic units' request rate.  Here the
+// contributions are instead routed to their destination.  The table of such a
+// level is cut into slices of up to kPartSliceMax fp32 accumulators (LDS):
+//   pass 1 (k_part_bucket), one workgroup per (tile of samples, level): the 8
+//     corner entries and contributions w * dL/dy of each sample become
+//     records, counting-sorted by slice in LDS; one global atomic per
+//     (workgroup, nonempty slice) reserves room in that slice's bucket, and
+//     each slice's run of records is written contiguously;
+//   pass 2 (k_part_accum), one workgroup per (block, level, slice): sums its
+//     bucket's records into LDS and adds the slice to the gradient table in
+//     coalesced rows, so every entry of the slice is written once per step.
+// The LDS sums are 64-bit fixed point: LDS float atomics run at a small
+// fraction of the rate of integer ones on this chip.  Pass 1 records the
+// largest |contribution| of each tile; a bucket of n records whose block's
+// largest contribution is M is summed in units of 2^-K with n M 2^K <= 2^62,
+// so no sum can overflow, each contribution is rounded by at most 2^-(K+1)
+// <= n M 2^-63 (far below fp32 rounding of the sums), and the sums do not
+// depend on record order.
+// Appends to one bucket are spread over up to kPartSub sub-buckets (by tile),
+// so that the atomics reserving room in a bucket do not queue on one address.
+// A sub-bucket that fills up (possible only for very uneven slice loads)
+// sends its excess records to the gradient table as direct float atomics.
+#include "dvnr_device.h"
+
+namespace dvnrk {
+
+// Exclusive prefix sum over the 256 lanes of a workgroup; `total` receives the sum.
+__device__ __forceinline__ int wg_exclusive_scan(int v, int* wsum, int& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int s = wsum[i];
+    pre += i < w ? s : 0;
+    tot += s;
+  }
+  total = tot;
+  return pre + x - v;
+}
+
+template <int F>
+__global__ __launch_bounds__(256) void k_part_bucket(LevelDesc ld, PartDesc pd, const BlockMeta* __restrict__ meta,
+                                                     const Tile* __restrict__ tiles, int n_tiles,
+                                                     const BlockPlan* __restrict__ plan,
+                                                     const PartBlock* __restrict__ pb,
+                                                     const float* __restrict__ coords,
+                                                     const float* __restrict__ dfeat, int64_t ls,
+                                                     int32_t* __restrict__ cursor, uint32_t* __restrict__ recs,
+                                                     float* __restrict__ tmax, float* __restrict__ grad) {
+  constexpr int RW = 1 + F;  // words per record
+  __shared__ uint32_t stage[8 * kTile * RW];
+  __shared__ int hist[kPartMaxSlices], lbase[kPartMaxSlices], gbase[kPartMaxSlices], wsum[4];
+  __shared__ float wmax[4];
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x / pd.nl;
+  const int l = pd.l0 + (int)(blockIdx.x % pd.nl);
+  if (tile >= n_tiles) return;
+  const Tile t = tiles[tile];
+  const int b = t.block;
+  const int sh = pd.sh[l];
+  const int sub = tile % pd.nsub;
+  const uint32_t smask = (1u << sh) - 1u;
+  hist[tid] = 0;
+  __syncthreads();
+  const bool valid = tid < t.count;
+  uint32_t e[8];
+  float w[8], d[F];
+  int rk[8];
+  float m = 0.0f;  // largest |w * dL/dy| of the lane
+  if (valid) {
+    const int64_t gi = plan[b].sample_off + t.start + tid;
+    const int R = ld.R[l];
+    const float sc = ld.scale[l];
+    int ix, iy, iz;
+    float tx, ty, tz;
+    grid_pos(coords[3 * gi + 0], sc, R, ix, tx);
+    grid_pos(coords[3 * gi + 1], sc, R, iy, ty);
+    grid_pos(coords[3 * gi + 2], sc, R, iz, tz);
+    float dm = 0.0f;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      d[f] = dfeat[(int64_t)l * ls + gi * F + f];
+      dm = fmaxf(dm, fabsf(d[f]));
+    }
+    const int dense = ld.dense[l];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t cx = k & 1, cy = (k >> 1) & 1, cz = k >> 2;
+      e[k] = corner_index(dense, R, ld.T_mask, ix + cx, iy + cy, iz + cz);
+      w[k] = (cx ? tx : 1.0f - tx) * (cy ? ty : 1.0f - ty) * (cz ? tz : 1.0f - tz);
+      m = fmaxf(m, w[k] * dm);  // bounds |w * d[f]| for every f (rounding is monotone)
+      rk[k] = atomicAdd(&hist[e[k] >> sh], 1);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((tid & 63) == 0) wmax[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0)
+    tmax[(int64_t)(l - pd.l0) * n_tiles + tile] = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+  // slice runs in LDS, and room for them in the slices' sub-buckets
+  const int c = hist[tid];
+  int total;
+  lbase[tid] = wg_exclusive_scan(c, wsum, total);
+  if (c > 0)
+    gbase[tid] = atomicAdd(&cursor[((int64_t)b * pd.nq + pd.qbase[l] + tid) * kPartSub + sub], c);
+  __syncthreads();
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t q = e[k] >> sh;
+      const int p = (lbase[q] + rk[k]) * RW;
+      stage[p] = (q << 16) | (e[k] & smask);
+#pragma unroll
+      for (int f = 0; f < F; ++f) stage[p + 1 + f] = __float_as_uint(w[k] * d[f]);
+    }
+  }
+  __syncthreads();
+  const int64_t off = pb[b].off[l];
+  const int cap = pb[b].cap[l];
+  for (int i = tid; i < total; i += 256) {
+    const uint32_t w0 = stage[i * RW];
+    const int q = (int)(w0 >> 16);
+    const int j = gbase[q] + i - lbase[q];
+    if (j < cap) {
+      uint32_t* r = recs + (off + ((int64_t)q * pd.nsub + sub) * cap + j) * RW;
+#pragma unroll
+      for (int k = 0; k < RW; ++k) r[k] = stage[i * RW + k];
+    } else {
+      float* g = grad + meta[b].param_off + ((int64_t)ld.off[l] + ((int64_t)q << sh) + (w0 & smask)) * F;
+#pragma unroll
+      for (int f = 0; f < F; ++f) unsafeAtomicAdd(&g[f], __uint_as_float(stage[i * RW + 1 + f]));
+    }
+  }
+}
+
+template <int F, int SF>
+__global__ __launch_bounds__(256) void k_part_accum(LevelDesc ld, PartDesc pd, const BlockMeta* __restrict__ meta,
+                                                    int n_tiles, const BlockPlan* __restrict__ plan,
+                                                    const PartBlock* __restrict__ pb, int32_t* __restrict__ cursor,
+                                                    const uint32_t* __restrict__ recs,
+                                                    const float* __restrict__ tmax, float* __restrict__ grad) {
+  constexpr int RW = 1 + F;
+  constexpr int U = 16;  // records in flight per lane
+  __shared__ unsigned long long acc[SF];
+  __shared__ int sstart[kPartSub + 1];
+  __shared__ float wmax[4];
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x / pd.nq, q = blockIdx.x % pd.nq;
+  if (plan[b].n == 0) return;  // no sample, no record: the bucket's cursors are still zero
+  int l = pd.l0;
+  while (l + 1 < pd.l0 + pd.nl && q >= pd.qbase[l + 1]) ++l;
+  const int s = q - pd.qbase[l];
+  const int sh = pd.sh[l];
+  const uint32_t smask = (1u << sh) - 1u;
+  const int cap = pb[b].cap[l];
+  // sub-bucket record counts (cursors cleared for the next step's pass 1)
+  if (tid < kPartSub) {
+    int cnt = 0;
+    if (tid < pd.nsub) {
+      int32_t* cur = cursor + ((int64_t)b * pd.nq + q) * kPartSub + tid;
+      cnt = min(*cur, cap);
+      *cur = 0;
+    }
+    sstart[tid + 1] = cnt;
+  }
+  // largest contribution over the block's tiles on this level
+  {
+    const float* tm = tmax + (int64_t)(l - pd.l0) * n_tiles + pb[b].tile0;
+    float m = 0.0f;
+    for (int i = tid; i < pb[b].ntiles; i += 256) m = fmaxf(m, tm[i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((tid & 63) == 0) wmax[tid >> 6] = m;
+  }
+  for (int i = tid; i < SF; i += 256) acc[i] = 0ull;
+  __syncthreads();
+  if (tid == 0) {
+    sstart[0] = 0;
+    for (int g = 0; g < kPartSub; ++g) sstart[g + 1] += sstart[g];
+  }
+  __syncthreads();
+  const int n = sstart[kPartSub];
+  const float M = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+  // fixed-point unit 2^-K: n M 2^K <= 2^62 with n M < 2^E
+  int E = 0;
+  (void)frexpf((float)n * M, &E);
+  const int K = max(-120, min(120, 62 - E));
+  const float scale = ldexpf(1.0f, K);
+  const uint32_t* r = recs + (pb[b].off[l] + (int64_t)s * pd.nsub * cap) * RW;
+  for (int j0 = 0; j0 < n; j0 += 256 * U) {
+    // unconditional loads (lanes past the end re-read the last record and skip
+    // it below), so that all U loads are in flight together; record j of the
+    // bucket is record j - sstart[g] of sub-bucket g
+    uint32_t v[U][RW];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = min(j0 + u * 256 + tid, n - 1);
+      int g = 0;
+#pragma unroll
+      for (int k = 1; k < kPartSub; ++k) g += j >= sstart[k] ? 1 : 0;
+      const uint32_t* rr = r + ((int64_t)g * cap + (j - sstart[g])) * RW;
+#pragma unroll
+      for (int k = 0; k < RW; ++k) v[u][k] = rr[k];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (j0 + u * 256 + tid < n) {
+        const uint32_t ent = v[u][0] & smask;
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+          atomicAdd(&acc[ent * F + f], (unsigned long long)__float2ll_rn(__uint_as_float(v[u][1 + f]) * scale));
+      }
+    }
+  }
+  __syncthreads();
+  const double unit = 1.0 / (double)scale;
+  const int64_t e0 = (int64_t)s << sh;
+  const int nf = (int)min((int64_t)1 << sh, (int64_t)pd.E[l] - e0) * F;
+  float* g = grad + meta[b].param_off + ((int64_t)ld.off[l] + e0) * F;
+  // read-add-write of the slice: batches of unconditional loads (clamped to
+  // the slice) so that a lane's loads overlap instead of waiting one by one
+  constexpr int PT = SF / 256, KB = PT < 8 ? PT : 8;
+  for (int k0 = 0; k0 < PT; k0 += KB) {
+    float gv[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) gv[k] = g[min(tid + 256 * (k0 + k), nf - 1)];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int i = tid + 256 * (k0 + k);
+      if (i < nf) {
+        const long long a = (long long)acc[i];
+        if (a != 0) g[i] = gv[k] + (float)((double)a * unit);
+      }
+    }
+  }
+}
+
+hipError_t launch_part_bucket(const LevelDesc& ld, const PartDesc& pd, const BlockMeta* meta, const Tile* tiles,
+                              int n_tiles, const BlockPlan* plan, const PartBlock* pb, const float* coords,
+                              const float* dfeat, int64_t ls, int32_t* cursor, uint32_t* recs, float* tmax,
+                              float* grad, hipStream_t s) {
+  if (pd.nl <= 0 || n_tiles <= 0) return hipSuccess;
+  const int64_t grid = (int64_t)n_tiles * pd.nl;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  // bucket ids fit the LDS histogram and the record's upper 16 bits
+  if (pd.nsub < 1 || pd.nsub > kPartSub) return hipErrorInvalidValue;
+  for (int l = pd.l0; l < pd.l0 + pd.nl; ++l)
+    if (pd.ns[l] > kPartMaxSlices || pd.sh[l] > 16 || ((int64_t)pd.ns[l] << pd.sh[l]) < pd.E[l])
+      return hipErrorInvalidValue;
+  switch (ld.F) {
+#define DVNR_PART_B(FF)                                                                                          \
+  case FF:                                                                                                       \
+    hipLaunchKernelGGL(k_part_bucket<FF>, dim3((unsigned)grid), dim3(256), 0, s, ld, pd, meta, tiles, n_tiles,   \
+                       plan, pb, coords, dfeat, ls, cursor, recs, tmax, grad);                                         \
+    break;
+    DVNR_PART_B(1)
+    DVNR_PART_B(2)
+    DVNR_PART_B(4)
+    DVNR_PART_B(8)
+#undef DVNR_PART_B
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_part_accum(const LevelDesc& ld, const PartDesc& pd, const BlockMeta* meta, int n_blocks,
+                             int n_tiles, const BlockPlan* plan, const PartBlock* pb, int32_t* cursor,
+                             const uint32_t* recs, const float* tmax, float* grad, hipStream_t s) {
+  if (pd.nl <= 0 || n_blocks <= 0 || pd.nq <= 0) return hipSuccess;
+  const int64_t grid = (int64_t)n_blocks * pd.nq;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  // every level's slice (2^sh entries x F) fits the launch's accumulators
+  if (pd.nsub < 1 || pd.nsub > kPartSub) return hipErrorInvalidValue;
+  for (int l = pd.l0; l < pd.l0 + pd.nl; ++l)
+    if (((int64_t)ld.F << pd.sh[l]) > pd.slice_floats || pd.ns[l] > kPartMaxSlices) return hipErrorInvalidValue;
+#define DVNR_PART_A(FF, SS)                                                                                      \
+  hipLaunchKernelGGL((k_part_accum<FF, SS>), dim3((unsigned)grid), dim3(256), 0, s, ld, pd, meta,             \
+                     n_tiles, plan, pb, cursor, recs, tmax, grad)
+#define DVNR_PART_SF(FF)                                                                                         \
+  case FF:                                                                                                       \
+    if (pd.slice_floats == 4096) DVNR_PART_A(FF, 4096);                                                          \
+    else if (pd.slice_floats == 8192) DVNR_PART_A(FF, 8192);                                                     \
+    else if (pd.slice_floats == 16384) DVNR_PART_A(FF, 16384);                                                   \
+    else return hipErrorInvalidValue;                                                                            \
+    break;
+  switch (ld.F) {
+    DVNR_PART_SF(1)
+    DVNR_PART_SF(2)
+    DVNR_PART_SF(4)
+    DVNR_PART_SF(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef DVNR_PART_SF
+#undef DVNR_PART_A
+  return hipGetLastError();
+}
+
+}  // namespace dvnrk

@@ -218,11 +218,11 @@ class DVNR:
                                                     _stream_ptr(stream)))
         return coords, target
 
-    PHASES = ("sample", "encode", "mlp", "scatter_priv", "scatter", "reduce", "adam")
+    PHASES = ("sample", "encode", "mlp", "scatter_priv", "scatter", "part_bucket", "part_accum", "reduce", "adam")
 
     def phase_times(self):
         """{phase: total ms} and the step count since the previous call (needs option profile_phases=1)."""
-        ms = (C.c_double * 7)()
+        ms = (C.c_double * len(self.PHASES))()
         n = C.c_int64()
         L.check(self.lib.dvnr_phase_times(self.h, ms, C.byref(n)))
         return dict(zip(self.PHASES, list(ms))), n.value
@@ -239,6 +239,12 @@ class DVNR:
         bpa, pl = C.c_int32(), C.c_int32()
         L.check(self.lib.dvnr_plan_info(self.h, C.byref(bpa), C.byref(pl)))
         return bpa.value, pl.value
+
+    def partitioned_levels(self):
+        """First level whose encoding backward is destination-partitioned in the current plan (n_levels: none)."""
+        lf = C.c_int32()
+        L.check(self.lib.dvnr_plan_partition(self.h, C.byref(lf)))
+        return lf.value
 
     def sync(self, stream=None):
         L.check(self.lib.dvnr_sync(self.h, _stream_ptr(stream)))

@@ -169,3 +169,22 @@ def test_model_cache_host_logic():
     nb = C.c_int64()
     assert lib.dvnr_cache_snapshot_bytes(h, C.byref(nb)) == 2
     lib.dvnr_destroy(h)
+
+
+def test_partitioned_backward_options():
+    """Option validation of the destination-partitioned backward; no level is
+    partitioned before a training plan exists."""
+    lib, code, h = _make(o.Encoding(16, 2, 19, 16, 0.0, 256), o.MLP(2, 64), precision="mixed")
+    assert code == 0
+    try:
+        lib.dvnr_plan_partition.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
+        lf = C.c_int32(-7)
+        assert lib.dvnr_plan_partition(h, C.byref(lf)) == 0 and lf.value == 16
+        assert lib.dvnr_plan_partition(h, None) == 1
+        for v, ok in ((4096, 0), (8192, 0), (16384, 0), (1000, 1), (32768, 1), (0, 1)):
+            assert lib.dvnr_set_option(h, b"part_slice", v) == ok, v
+        assert lib.dvnr_set_option(h, b"scatter_part", 9) == 0
+        assert lib.dvnr_set_option(h, b"scatter_part", -1) == 0
+        assert lib.dvnr_set_option(h, b"part_capacity", 8) == 0
+    finally:
+        lib.dvnr_destroy(h)

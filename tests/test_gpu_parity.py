@@ -215,37 +215,66 @@ def test_sorted_sampling_gradient_parity(precision, priv, classes, binned):
     assert normwise(gg[nt:], g[nt:]) <= tol, "weight gradient"
 
 
-@pytest.mark.parametrize("precision,classes,waves,conc", [("fp32", 0, 1, 0), ("fp32", 1, 1, 0), ("fp32", 0, 1, 1),
-                                                          ("mixed", 0, 1, 0), ("mixed", 0, 2, 0), ("mixed", 1, 1, 1)])
-def test_sorted_sampling_gradient_parity_fine_levels(precision, classes, waves, conc):
+# (precision, LDS classes, MLP waves, concurrent, ordered, scatter_part, bucket cap, slice floats,
+#  first partitioned level expected: the first with 2^16 entries is level 6)
+FINE_CASES = [("fp32", 0, 1, 0, 1, -1, 0, 8192, 16), ("fp32", 1, 1, 0, 1, -1, 0, 8192, 16),
+              ("fp32", 0, 1, 1, 1, -1, 0, 8192, 16), ("mixed", 0, 1, 0, 1, -1, 0, 8192, 16),
+              ("mixed", 0, 2, 0, 1, -1, 0, 8192, 16), ("mixed", 1, 1, 1, 1, -1, 0, 8192, 16),
+              # destination-partitioned levels: fine only, every eligible one (ordered and not),
+              # tiny buckets (most records overflow into direct atomics), other slice sizes
+              ("fp32", 0, 1, 0, 1, 9, 0, 8192, 9), ("fp32", 0, 1, 0, 1, 0, 0, 8192, 6),
+              ("fp32", 0, 1, 0, 0, 6, 0, 16384, 6), ("fp32", 0, 1, 0, 1, 9, 8, 8192, 9),
+              ("fp32", 0, 1, 0, 0, 12, 0, 4096, 12), ("mixed", 0, 1, 0, 1, 9, 0, 8192, 9),
+              # 16384 samples, 64 slices per level: 4 sub-buckets per bucket
+              ("fp32", 0, 1, 0, 1, 9, 0, 16384, 9, 16384)]
+FINE_CASES = [c if len(c) == 10 else c + (8192,) for c in FINE_CASES]
+
+
+@pytest.mark.parametrize("precision,classes,waves,conc,sort,part,cap,slice_,lf,n", FINE_CASES)
+def test_sorted_sampling_gradient_parity_fine_levels(precision, classes, waves, conc, sort, part, cap, slice_, lf, n):
     """16 levels up to R = 256 with 8192 samples (2^3 bins of ~1024): coarse
     levels accumulate in LDS, levels whose bin box exceeds the LDS budget take
-    the in-kernel direct-atomic path; bins above 1024 samples take two chunks."""
-    say(f"ordered sampling, all levels privatized, c2 levels {precision}, LDS classes {classes}")
+    the in-kernel direct-atomic path; bins above 1024 samples take two chunks.
+    With lf < 16 the levels [lf, 16) take the destination-partitioned
+    backward instead (slice buckets summed in LDS); cap > 0 shrinks its
+    buckets to cap records so that most records take the overflow atomics."""
+    say(f"c2 levels {precision}: ordered {sort}, LDS classes {classes}, partitioned from level {part}, "
+        f"bucket cap {cap}")
     vol = gaussian_sum_field(64, seed=3)
     lay = o.layout(*C2)
     p = init_param_draws(lay.n_table_params, lay.mlp_shapes, seed=2).astype(np.float64)
     p[:lay.n_table_params] *= 1e3
+    if n > 8192:
+        # all parameters positive, so every ReLU unit is active: with random signs and
+        # this many samples, some sample's hidden pre-activation lies within fp32
+        # rounding of zero, its unit switches between fp32 and fp64 and all its
+        # corner entries move by a macroscopic amount
+        p = np.abs(p)
     model = make(C2, [((64, 64, 64), 0)], precision=precision, max_batch=1 << 14, seed=91)
     model.bind_volumes([dev(vol)])
     model.load_params([p])
-    model.set_option("spatial_sort", 1)
+    model.set_option("spatial_sort", sort)
     model.set_option("priv_levels", -1)
     model.set_option("priv_classes", classes)
     model.set_option("mlp_waves", waves)
     model.set_option("scatter_concurrent", conc)
+    model.set_option("scatter_part", part)
+    model.set_option("part_capacity", cap)
+    model.set_option("part_slice", slice_)
     model.set_option("apply_update", 0)
     model.set_option("use_graph", 0)
-    loss = model.train(1, 8192, want_loss=True)
+    loss = model.train(1, n, want_loss=True)
     torch.cuda.synchronize()
-    assert model.plan_info() == (2, 16)
+    bins = max(B for B in range(1, 9) if B ** 3 * 512 <= n)  # about 512 samples per bin
+    assert model.plan_info() == ((bins, lf) if sort else (0, 0))
+    assert model.partitioned_levels() == lf
     if precision == "fp32":
         pref = model.block_params(0).cpu().numpy().astype(np.float64)
     else:  # the mixed path computes with the fp16 table / bf16 weight working copy
         nt = lay.n_table_params
         w = torch.tensor(p[nt:]).to(torch.bfloat16).to(torch.float64).numpy()
         pref = np.concatenate([p[:nt].astype(np.float16).astype(np.float64), w])
-    x = o.training_coords(91, 0, 0, 8192)
+    x = o.training_coords(91, 0, 0, n)
     tgt = o.normalized_targets(vol, (64, 64, 64), 0, x)
     L, g, _ = o.loss_and_grad(lay, pref, x, tgt)
     gg = model.block_grads(0).cpu().numpy()
@@ -451,18 +480,25 @@ def test_autotune_leaves_state_and_results_unchanged():
     assert normwise(model.block_grads(0).cpu().numpy(), g) <= 3e-2
 
 
-@pytest.mark.parametrize("precision,conc", [("fp32", 0), ("mixed", 1)])
-def test_graph_replay_matches_eager_steps(precision, conc):
+@pytest.mark.parametrize("precision,conc,part", [("fp32", 0, -1), ("mixed", 1, -1), ("mixed", 0, 9)])
+def test_graph_replay_matches_eager_steps(precision, conc, part):
     """Steps replayed from the captured hipGraph (with eager work and host syncs
     between replays) follow the same trajectory as eagerly launched steps; with
-    conc, the captured step forks part of the backward onto a second stream."""
-    say(f"graph replay vs eager steps {precision} concurrent={conc}")
+    conc, the captured step forks part of the backward onto a second stream;
+    with part >= 0 (c2 levels), levels [part, 16) take the partitioned
+    backward, whose bucket cursors each step leaves at zero for the next."""
+    say(f"graph replay vs eager steps {precision} concurrent={conc} partitioned from level {part}")
     vol, lay, p0, _ = _setup_c1_block("fp32")
+    cfg = C1
+    if part >= 0:
+        cfg = C2
+        p0 = init_param_draws(o.layout(*C2).n_table_params, o.layout(*C2).mlp_shapes, seed=4)
     losses = {}
     for use_graph in (0, 1):
-        model = make(C1, [((64, 64, 64), 0)], precision=precision, max_batch=1 << 14, seed=77)
+        model = make(cfg, [((64, 64, 64), 0)], precision=precision, max_batch=1 << 14, seed=77)
         model.bind_volumes([dev(vol)])
         model.load_params([p0.astype(np.float64)])
+        model.set_option("scatter_part", part)
         model.set_option("use_graph", use_graph)
         model.set_option("scatter_concurrent", conc)
         s = torch.cuda.Stream()
@@ -474,6 +510,8 @@ def test_graph_replay_matches_eager_steps(precision, conc):
                 s.synchronize()
         losses[use_graph] = torch.cat(out).cpu().numpy()
         model.sync(stream=s)
+        if part >= 0:
+            assert model.partitioned_levels() == part
     np.testing.assert_allclose(losses[1], losses[0], rtol=2e-4 if precision == "fp32" else 1e-3, atol=0)
 
 
