@@ -178,8 +178,11 @@ __device__ __forceinline__ bool level_major_item(int wg, int l0, int L, int n_ti
     level = l0 + lvl;
     return tile < n_tiles;
   }
-  level = l0 + wg % L;
+  // plain: consecutive workgroups take the levels of one tile, rotated by the
+  // tile index so that no XCD (workgroup w % 8) is left with a single level
+  // when L is a multiple of 8
   tile = wg / L;
+  level = l0 + (wg % L + tile) % L;
   return tile < n_tiles;
 }
 

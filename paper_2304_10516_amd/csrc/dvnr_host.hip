@@ -524,11 +524,11 @@ static std::vector<int64_t> apportion(const dvnr_t* h, int64_t total) {
 static int64_t boundary_count(int64_t n, double frac) { return (int64_t)std::floor(frac * (double)n + 0.5); }
 
 // Levels of the destination-partitioned backward and their bucket layout.
-// Auto choice (mixed precision): the hashed levels, when they receive at
-// least one contribution per table entry per step on average over the
-// sampled blocks (there a bin's vertex box no longer merges contributions,
-// while the dense levels' boxes still do).  Only levels from part_min (sized
-// into the workspace) with at most kPartMaxSlices slices qualify.
+// Auto choice (mixed precision): the longest suffix of the levels from
+// part_min (tables of at least kPartMinEntries entries, sized into the
+// workspace) whose tables receive at least one contribution per entry per
+// step on average over the sampled blocks.  Only levels with at most
+// kPartMaxSlices slices qualify.
 static dvnr_status plan_partition(dvnr_t* h, const std::vector<int64_t>& n, hipStream_t s) {
   const int L = h->enc.n_levels, F = h->enc.n_features;
   const int sf = h->part_slice_floats;
@@ -543,7 +543,7 @@ static dvnr_status plan_partition(dvnr_t* h, const std::vector<int64_t>& n, hipS
   if (h->scatter_part >= 0) {
     lf = std::min(h->scatter_part, L);
   } else if (h->prec == Prec::MIXED) {
-    while (lf > 0 && !h->ld.dense[lf - 1] && 8.0 * avg >= (double)level_entries(h, lf - 1)) --lf;
+    while (lf > h->part_min && 8.0 * avg >= (double)level_entries(h, lf - 1)) --lf;
   }
   lf = std::max(lf, h->part_min);
   for (int l = lf; l < L; ++l)
@@ -556,10 +556,22 @@ static dvnr_status plan_partition(dvnr_t* h, const std::vector<int64_t>& n, hipS
   pd.nl = L - lf;
   pd.slice_floats = sf;
   int nq = 0;
+  // slice size per level: at most the "part_slice" accumulators, halved while
+  // a slice's bucket still averages kPartSliceRecords records (the dense
+  // levels' small tables get many contributions per entry) and the level
+  // keeps at most kPartMaxSlices slices
   for (int l = lf; l < L; ++l) {
-    pd.E[l] = (int32_t)level_entries(h, l);
-    pd.sh[l] = sh;
-    pd.ns[l] = (int32_t)((pd.E[l] + S - 1) / S);
+    const int64_t E = level_entries(h, l);
+    int shl = sh;
+    while (shl > 0) {
+      const int64_t half = (int64_t)1 << (shl - 1);
+      if (8.0 * avg * (double)half / (double)E < (double)kPartSliceRecords || (E + half - 1) / half > kPartMaxSlices)
+        break;
+      --shl;
+    }
+    pd.E[l] = (int32_t)E;
+    pd.sh[l] = shl;
+    pd.ns[l] = (int32_t)((E + ((int64_t)1 << shl) - 1) >> shl);
     pd.qbase[l] = nq;
     nq += pd.ns[l];
   }

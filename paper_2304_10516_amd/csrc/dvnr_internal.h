@@ -130,6 +130,7 @@ constexpr int kPartSliceMax = 16384;  // accumulators of one slice (64 KB of LDS
 constexpr int kPartMaxSlices = 256;   // slices of one level
 constexpr int kPartMinEntries = 1 << 16;  // smallest table that may be partitioned
 constexpr int kPartSub = 16;          // sub-buckets per bucket (tile t appends to sub-bucket t % kPartSub)
+constexpr int kPartSliceRecords = 16384;  // records per slice the slice sizes aim at
 struct PartDesc {
   int32_t l0, nl;
   int32_t nq;                    // buckets per block

@@ -66,9 +66,8 @@ __global__ __launch_bounds__(256) void k_part_bucket(LevelDesc ld, PartDesc pd, 
   __shared__ int hist[kPartMaxSlices], lbase[kPartMaxSlices], gbase[kPartMaxSlices], wsum[4];
   __shared__ float wmax[4];
   const int tid = threadIdx.x;
-  const int tile = blockIdx.x / pd.nl;
-  const int l = pd.l0 + (int)(blockIdx.x % pd.nl);
-  if (tile >= n_tiles) return;
+  int tile, l;
+  if (!level_major_item(blockIdx.x, pd.l0, pd.nl, n_tiles, 0, tile, l)) return;
   const Tile t = tiles[tile];
   const int b = t.block;
   const int sh = pd.sh[l];
@@ -187,7 +186,7 @@ __global__ __launch_bounds__(256) void k_part_accum(LevelDesc ld, PartDesc pd, c
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     if ((tid & 63) == 0) wmax[tid >> 6] = m;
   }
-  for (int i = tid; i < SF; i += 256) acc[i] = 0ull;
+  for (int i = tid; i < (F << sh); i += 256) acc[i] = 0ull;
   __syncthreads();
   if (tid == 0) {
     sstart[0] = 0;

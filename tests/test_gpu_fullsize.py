@@ -13,8 +13,9 @@ samples per step.  The float64 oracle computes the whole step at this size
   scale of zero, a few of them switch their unit between fp32 and fp64, and a
   switched sample moves all its 128 corner entries by a macroscopic amount
   (the small-size tests cover inactive units);
-* mixed precision with its default options (those of the benchmark): the bars
-  of the bf16 MLP (per-level 2-norm 1e-1 with cosine >= 0.995, weights 3e-2).
+* mixed precision with its default options (those of the benchmark: levels
+  6..15 partitioned): the bars of the bf16 MLP (per-level 2-norm 1e-1 with
+  cosine >= 0.995, weights 3e-2).
 """
 import sys
 
@@ -69,7 +70,7 @@ def test_full_size_step_gradient(field, precision):
     torch.cuda.synchronize()
     lf = model.partitioned_levels()
     say(f"partitioned levels from {lf}; plan {model.plan_info()}")
-    assert lf == 9
+    assert lf == (9 if precision == "fp32" else 6)  # mixed default: every level with 2^16 entries or more
     if precision == "fp32":
         pref = model.block_params(0).cpu().numpy().astype(np.float64)
     else:
