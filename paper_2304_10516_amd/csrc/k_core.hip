@@ -359,7 +359,8 @@ hipError_t launch_scatter(Prec gp, const LevelDesc& ld, int l0, int l1, const Bl
 // [slot_ranges[2b], slot_ranges[2b+1]).  Writes the MLP gradient (overwrite)
 // and the block's mean loss into the loss ring.  A workgroup covers 32
 // consecutive elements; its 8 rows of 32 lanes split the slot range
-// (coalesced 128-byte rows), then reduce through LDS in a fixed order.
+// (coalesced 128-byte rows, eight slots in flight per lane), then reduce
+// through LDS in a fixed order.
 // ===========================================================================
 template <typename GT>
 __global__ __launch_bounds__(256) void k_reduce_slots(const float* __restrict__ slots, int64_t slot_stride,
@@ -372,9 +373,25 @@ __global__ __launch_bounds__(256) void k_reduce_slots(const float* __restrict__ 
   const int c = threadIdx.x % 32, r = threadIdx.x / 32;
   const int64_t e = (int64_t)blockIdx.x * 32 + c;
   const int s0 = ranges[2 * b], s1 = ranges[2 * b + 1];
+  // a row walks slots s0 + r, s0 + r + 8, ...: eight independent partial sums
+  // keep eight loads in flight per lane (the summation order stays fixed)
+  float a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (e <= n_mlp) {
+    int sl = s0 + r;
+    for (; sl + 56 < s1; sl += 64) {
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = slots[(int64_t)(sl + 8 * k) * slot_stride + e];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a8[k] += v[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+      if (sl + 8 * k < s1) a8[k] += slots[(int64_t)(sl + 8 * k) * slot_stride + e];
+  }
   float acc = 0.0f;
-  if (e <= n_mlp)
-    for (int sl = s0 + r; sl < s1; sl += 8) acc += slots[(int64_t)sl * slot_stride + e];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc += a8[k];
   part[r][c] = acc;
   __syncthreads();
   if (r != 0 || e > n_mlp) return;
