@@ -30,6 +30,11 @@
 
 namespace dvnrk {
 
+#ifndef DVNR_PART_ACCUM_THREADS
+#define DVNR_PART_ACCUM_THREADS 512
+#endif
+constexpr int kPartAccumThreads = DVNR_PART_ACCUM_THREADS;  // threads of a slice-pass workgroup
+
 // Exclusive prefix sum over the 256 lanes of a workgroup; `total` receives the sum.
 __device__ __forceinline__ int wg_exclusive_scan(int v, int* wsum, int& total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -147,8 +152,8 @@ __global__ __launch_bounds__(256) void k_part_bucket(LevelDesc ld, PartDesc pd, 
   }
 }
 
-template <int F, int SF>
-__global__ __launch_bounds__(256) void k_part_accum(LevelDesc ld, PartDesc pd, const BlockMeta* __restrict__ meta,
+template <int F, int SF, int NT>
+__global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, const BlockMeta* __restrict__ meta,
                                                     int n_tiles, const BlockPlan* __restrict__ plan,
                                                     const PartBlock* __restrict__ pb, int32_t* __restrict__ cursor,
                                                     const uint32_t* __restrict__ recs,
@@ -157,7 +162,7 @@ __global__ __launch_bounds__(256) void k_part_accum(LevelDesc ld, PartDesc pd, c
   constexpr int U = 16;  // records in flight per lane
   __shared__ unsigned long long acc[SF];
   __shared__ int sstart[kPartSub + 1];
-  __shared__ float wmax[4];
+  __shared__ float wmax[NT / 64];
   const int tid = threadIdx.x;
   const int b = blockIdx.x / pd.nq, q = blockIdx.x % pd.nq;
   if (plan[b].n == 0) return;  // no sample, no record: the bucket's cursors are still zero
@@ -181,12 +186,12 @@ __global__ __launch_bounds__(256) void k_part_accum(LevelDesc ld, PartDesc pd, c
   {
     const float* tm = tmax + (int64_t)(l - pd.l0) * n_tiles + pb[b].tile0;
     float m = 0.0f;
-    for (int i = tid; i < pb[b].ntiles; i += 256) m = fmaxf(m, tm[i]);
+    for (int i = tid; i < pb[b].ntiles; i += NT) m = fmaxf(m, tm[i]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     if ((tid & 63) == 0) wmax[tid >> 6] = m;
   }
-  for (int i = tid; i < (F << sh); i += 256) acc[i] = 0ull;
+  for (int i = tid; i < (F << sh); i += NT) acc[i] = 0ull;
   __syncthreads();
   if (tid == 0) {
     sstart[0] = 0;
@@ -194,21 +199,23 @@ __global__ __launch_bounds__(256) void k_part_accum(LevelDesc ld, PartDesc pd, c
   }
   __syncthreads();
   const int n = sstart[kPartSub];
-  const float M = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+  float M = 0.0f;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) M = fmaxf(M, wmax[i]);
   // fixed-point unit 2^-K: n M 2^K <= 2^62 with n M < 2^E
   int E = 0;
   (void)frexpf((float)n * M, &E);
   const int K = max(-120, min(120, 62 - E));
   const float scale = ldexpf(1.0f, K);
   const uint32_t* r = recs + (pb[b].off[l] + (int64_t)s * pd.nsub * cap) * RW;
-  for (int j0 = 0; j0 < n; j0 += 256 * U) {
+  for (int j0 = 0; j0 < n; j0 += NT * U) {
     // unconditional loads (lanes past the end re-read the last record and skip
     // it below), so that all U loads are in flight together; record j of the
     // bucket is record j - sstart[g] of sub-bucket g
     uint32_t v[U][RW];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int j = min(j0 + u * 256 + tid, n - 1);
+      const int j = min(j0 + u * NT + tid, n - 1);
       int g = 0;
 #pragma unroll
       for (int k = 1; k < kPartSub; ++k) g += j >= sstart[k] ? 1 : 0;
@@ -218,7 +225,7 @@ __global__ __launch_bounds__(256) void k_part_accum(LevelDesc ld, PartDesc pd, c
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (j0 + u * 256 + tid < n) {
+      if (j0 + u * NT + tid < n) {
         const uint32_t ent = v[u][0] & smask;
 #pragma unroll
         for (int f = 0; f < F; ++f)
@@ -233,14 +240,14 @@ __global__ __launch_bounds__(256) void k_part_accum(LevelDesc ld, PartDesc pd, c
   float* g = grad + meta[b].param_off + ((int64_t)ld.off[l] + e0) * F;
   // read-add-write of the slice: batches of unconditional loads (clamped to
   // the slice) so that a lane's loads overlap instead of waiting one by one
-  constexpr int PT = SF / 256, KB = PT < 8 ? PT : 8;
+  constexpr int PT = SF / NT, KB = PT < 8 ? PT : 8;
   for (int k0 = 0; k0 < PT; k0 += KB) {
     float gv[KB];
 #pragma unroll
-    for (int k = 0; k < KB; ++k) gv[k] = g[min(tid + 256 * (k0 + k), nf - 1)];
+    for (int k = 0; k < KB; ++k) gv[k] = g[min(tid + NT * (k0 + k), nf - 1)];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
-      const int i = tid + 256 * (k0 + k);
+      const int i = tid + NT * (k0 + k);
       if (i < nf) {
         const long long a = (long long)acc[i];
         if (a != 0) g[i] = gv[k] + (float)((double)a * unit);
@@ -288,8 +295,8 @@ hipError_t launch_part_accum(const LevelDesc& ld, const PartDesc& pd, const Bloc
   for (int l = pd.l0; l < pd.l0 + pd.nl; ++l)
     if (((int64_t)ld.F << pd.sh[l]) > pd.slice_floats || pd.ns[l] > kPartMaxSlices) return hipErrorInvalidValue;
 #define DVNR_PART_A(FF, SS)                                                                                      \
-  hipLaunchKernelGGL((k_part_accum<FF, SS>), dim3((unsigned)grid), dim3(256), 0, s, ld, pd, meta,             \
-                     n_tiles, plan, pb, cursor, recs, tmax, grad)
+  hipLaunchKernelGGL((k_part_accum<FF, SS, kPartAccumThreads>), dim3((unsigned)grid), dim3(kPartAccumThreads), 0, s, \
+                     ld, pd, meta, n_tiles, plan, pb, cursor, recs, tmax, grad)
 #define DVNR_PART_SF(FF)                                                                                         \
   case FF:                                                                                                       \
     if (pd.slice_floats == 4096) DVNR_PART_A(FF, 4096);                                                          \
