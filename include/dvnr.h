@@ -421,6 +421,10 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *                          sample of max_batch and level).
  *  "part_slice"      n   : fp32 accumulators per slice: 4096, 8192 (default)
  *                          or 16384
+ *  "part_concurrent" 0/1 : run the two partitioned passes on a second stream
+ *                          (default priority), forked and joined with events
+ *                          inside the step, concurrently with the bin-privatized
+ *                          levels (default 1)
  *  "part_capacity"   n   : cap every bucket at n records (0, the default: 1.25x
  *                          the mean load plus 32); records beyond a bucket's
  *                          capacity are added by direct atomics (tests)

@@ -131,8 +131,9 @@ struct dvnr {
   // privatized backward run on it concurrently with the LDS-class levels,
   // forked and joined with events inside the step (also under graph capture)
   int scatter_concurrent = 0;
+  int part_concurrent = 1;  // option: partitioned passes on the second stream, concurrent with the privatized levels
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_fork2 = nullptr, ev_join2 = nullptr;
   // destination-partitioned backward of the fine levels [part_l0, L): bucket
   // layout, cursors and records in one library-owned allocation (grown on demand)
   int scatter_part = -1;  // option: first partitioned level (-1: chosen per plan; >= L: none)
@@ -149,8 +150,8 @@ struct dvnr {
   ~dvnr() {
     if (graph) (void)hipGraphExecDestroy(graph);
     for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_join) (void)hipEventDestroy(ev_join);
+    for (hipEvent_t e : {ev_fork, ev_join, ev_fork2, ev_join2})
+      if (e) (void)hipEventDestroy(e);
     if (side) (void)hipStreamDestroy(side);
   }
 };
@@ -765,6 +766,15 @@ static dvnr_status prof_mark(dvnr_t* h, int p, hipStream_t s) {
     if (st_) return st_;                 \
   } while (0)
 
+// The second stream (default priority) and its fork/join events, created on first use.
+static hipError_t ensure_side(dvnr_t* h) {
+  if (h->side) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+  for (hipEvent_t* ev : {&h->ev_fork, &h->ev_join, &h->ev_fork2, &h->ev_join2})
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  return e;
+}
+
 // One training step on the current plan (coordinates generated when gen != 0).
 static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   const bool mixed = h->prec == Prec::MIXED;
@@ -800,6 +810,20 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   PROF(3);
   const int lf = h->part_l0;  // levels [lf, L): destination-partitioned
   const int lp = std::min(sorted ? h->priv_L : 0, lf);
+  // part_concurrent: the partitioned passes (HBM streams) run on the second
+  // stream while the privatized levels (LDS and latency bound) run on `s`
+  const bool pconc = h->part_concurrent && lf < h->enc.n_levels && lp > 0;
+  if (pconc) {
+    HIPCHK(ensure_side(h));
+    HIPCHK(hipEventRecord(h->ev_fork2, s));
+    HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork2, 0));
+    HIPCHK(launch_part_bucket(h->ld, h->pdesc, h->d_meta(), h->d_tiles(), h->n_tiles, h->d_plan(), h->d_pblk(),
+                              h->d_coords(), h->d_dfeat(), h->max_batch * F, h->d_pcur(), h->d_precs(),
+                              h->d_ptmax(), (float*)h->buf.grads, h->side));
+    HIPCHK(launch_part_accum(h->ld, h->pdesc, h->d_meta(), h->nb, h->n_tiles, h->d_plan(), h->d_pblk(),
+                             h->d_pcur(), h->d_precs(), h->d_ptmax(), (float*)h->buf.grads, h->side));
+    HIPCHK(hipEventRecord(h->ev_join2, h->side));
+  }
   // privatized levels [0, lp) in up to three launches by LDS class: small boxes
   // (coarse levels, high occupancy), large boxes, and levels whose boxes never
   // fit (direct atomics over each bin's samples, no LDS).  Plain workgroup
@@ -813,11 +837,7 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
     const int a = h->priv_classes ? std::min(h->priv_small, lp) : 0;
     const int c = h->priv_classes || conc ? std::min(std::max(h->priv_direct, a), lp) : lp;
     if (conc && c < lp) {
-      if (!h->side) {
-        HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-        HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
-      }
+      HIPCHK(ensure_side(h));
       HIPCHK(hipEventRecord(h->ev_fork, s));
       HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
       HIPCHK(launch_scatter_priv(h->ld, c, lp, h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(),
@@ -838,14 +858,15 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
                         h->d_coords(), h->d_dfeat(), F, h->max_batch * F, h->buf.grads, h->scatter_grouped,
                         h->xcd_map, sorted ? h->scatter_strided : 0, s));
   PROF(5);
-  if (lf < h->enc.n_levels)
+  if (lf < h->enc.n_levels && !pconc)
     HIPCHK(launch_part_bucket(h->ld, h->pdesc, h->d_meta(), h->d_tiles(), h->n_tiles, h->d_plan(), h->d_pblk(),
                               h->d_coords(), h->d_dfeat(), h->max_batch * F, h->d_pcur(), h->d_precs(),
                               h->d_ptmax(), (float*)h->buf.grads, s));
   PROF(6);
-  if (lf < h->enc.n_levels)
+  if (lf < h->enc.n_levels && !pconc)
     HIPCHK(launch_part_accum(h->ld, h->pdesc, h->d_meta(), h->nb, h->n_tiles, h->d_plan(), h->d_pblk(),
                              h->d_pcur(), h->d_precs(), h->d_ptmax(), (float*)h->buf.grads, s));
+  if (pconc) HIPCHK(hipStreamWaitEvent(s, h->ev_join2, 0));
   PROF(7);
   HIPCHK(launch_reduce_slots(h->d_slots(), h->slot_stride, h->d_ranges(), h->nb, h->n_mlp, h->n_table, h->stride,
                              Prec::F32, h->buf.grads, h->d_ring(), h->d_ctr(), 1, s));
@@ -1555,6 +1576,8 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
   } else if (n == "part_capacity") {
     h->part_cap = (int)std::max<int64_t>(0, std::min<int64_t>(value, 1 << 30));
     h->plan_total = -1;
+  } else if (n == "part_concurrent") {
+    h->part_concurrent = value ? 1 : 0;
   } else if (n == "scatter_concurrent") {
     h->scatter_concurrent = value ? 1 : 0;
   } else if (n == "encode_binned") {
