@@ -421,6 +421,9 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *                          sample of max_batch and level).
  *  "part_slice"      n   : fp32 accumulators per slice: 4096, 8192 (default)
  *                          or 16384
+ *  "encode_concurrent" 0/1 : run the binned encoding of the coarse levels on
+ *                          a second stream concurrently with the tile encoding
+ *                          of the others (default 1)
  *  "part_concurrent" 0/1 : run the two partitioned passes on a second stream
  *                          (default priority), forked and joined with events
  *                          inside the step, concurrently with the bin-privatized

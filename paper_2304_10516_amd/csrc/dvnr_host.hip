@@ -132,8 +132,10 @@ struct dvnr {
   // forked and joined with events inside the step (also under graph capture)
   int scatter_concurrent = 0;
   int part_concurrent = 1;  // option: partitioned passes on the second stream, concurrent with the privatized levels
+  int encode_concurrent = 1;  // option: binned encoding on the second stream, concurrent with the tile encoding
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_fork2 = nullptr, ev_join2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_fork2 = nullptr, ev_join2 = nullptr, ev_fork3 = nullptr,
+             ev_join3 = nullptr;
   // destination-partitioned backward of the fine levels [part_l0, L): bucket
   // layout, cursors and records in one library-owned allocation (grown on demand)
   int scatter_part = -1;  // option: first partitioned level (-1: chosen per plan; >= L: none)
@@ -150,7 +152,7 @@ struct dvnr {
   ~dvnr() {
     if (graph) (void)hipGraphExecDestroy(graph);
     for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {ev_fork, ev_join, ev_fork2, ev_join2})
+    for (hipEvent_t e : {ev_fork, ev_join, ev_fork2, ev_join2, ev_fork3, ev_join3})
       if (e) (void)hipEventDestroy(e);
     if (side) (void)hipStreamDestroy(side);
   }
@@ -770,7 +772,7 @@ static dvnr_status prof_mark(dvnr_t* h, int p, hipStream_t s) {
 static hipError_t ensure_side(dvnr_t* h) {
   if (h->side) return hipSuccess;
   hipError_t e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
-  for (hipEvent_t* ev : {&h->ev_fork, &h->ev_join, &h->ev_fork2, &h->ev_join2})
+  for (hipEvent_t* ev : {&h->ev_fork, &h->ev_join, &h->ev_fork2, &h->ev_join2, &h->ev_fork3, &h->ev_join3})
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   return e;
 }
@@ -795,12 +797,23 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   const void* table = mixed ? h->buf.work16 : h->buf.params;
   // ordered samples: levels [0, enc_binned) interpolate from LDS-staged bin boxes
   const int le = sorted && h->encode_binned ? h->enc_binned : 0;
+  // encode_concurrent: the binned (LDS-bound) levels on the second stream while
+  // the tile encoding gathers the others
+  const bool econc = h->encode_concurrent && le > 0 && le < h->enc.n_levels;
+  if (econc) {
+    HIPCHK(ensure_side(h));
+    HIPCHK(hipEventRecord(h->ev_fork3, s));
+    HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork3, 0));
+  }
   if (le > 0)
     HIPCHK(launch_encode_binned(h->prec, mixed ? 1 : 0, h->ld, 0, le, h->sort_B, h->nb, h->d_meta(), h->d_plan(),
-                                h->d_binstart(), h->d_coords(), table, h->d_feat(), F, h->max_batch * F, s));
+                                h->d_binstart(), h->d_coords(), table, h->d_feat(), F, h->max_batch * F,
+                                econc ? h->side : s));
+  if (econc) HIPCHK(hipEventRecord(h->ev_join3, h->side));
   HIPCHK(launch_encode(h->prec, mixed ? 1 : 0, h->ld, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
                        h->d_coords(), table, h->d_feat(), F, h->max_batch * F, h->xcd_map, s, le,
                        h->enc.n_levels));
+  if (econc) HIPCHK(hipStreamWaitEvent(s, h->ev_join3, 0));
   PROF(2);
   const void* wsrc = mixed ? (const void*)((const uint16_t*)h->buf.work16 + h->n_table)
                            : (const void*)((const float*)h->buf.params + h->n_table);
@@ -866,10 +879,12 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   if (lf < h->enc.n_levels && !pconc)
     HIPCHK(launch_part_accum(h->ld, h->pdesc, h->d_meta(), h->nb, h->n_tiles, h->d_plan(), h->d_pblk(),
                              h->d_pcur(), h->d_precs(), h->d_ptmax(), (float*)h->buf.grads, s));
-  if (pconc) HIPCHK(hipStreamWaitEvent(s, h->ev_join2, 0));
   PROF(7);
+  // the weight-gradient reduction needs only the MLP's slots and writes the
+  // weights' gradient: with the concurrent passes it runs before the join
   HIPCHK(launch_reduce_slots(h->d_slots(), h->slot_stride, h->d_ranges(), h->nb, h->n_mlp, h->n_table, h->stride,
                              Prec::F32, h->buf.grads, h->d_ring(), h->d_ctr(), 1, s));
+  if (pconc) HIPCHK(hipStreamWaitEvent(s, h->ev_join2, 0));
   PROF(8);
   if (!h->apply_update) {
     PROF(9);
@@ -1576,6 +1591,8 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
   } else if (n == "part_capacity") {
     h->part_cap = (int)std::max<int64_t>(0, std::min<int64_t>(value, 1 << 30));
     h->plan_total = -1;
+  } else if (n == "encode_concurrent") {
+    h->encode_concurrent = value ? 1 : 0;
   } else if (n == "part_concurrent") {
     h->part_concurrent = value ? 1 : 0;
   } else if (n == "scatter_concurrent") {
