@@ -57,6 +57,43 @@ __device__ __forceinline__ int wg_exclusive_scan(int v, int* wsum, int& total) {
   return pre + x - v;
 }
 
+// Records.  Generic F: 1 + F words, (slice << 16 | entry within the slice)
+// then the F fp32 contributions.  F == 2: one 64-bit word — entry within the
+// slice (bits 0..12), exponent e + 127 of the larger |contribution| (bits
+// 13..20; 0 for a zero record), and the two contributions as 21-bit two's-
+// complement mantissas m_i (bits 21..41, 42..62), contribution i = m_i 2^(e-20)
+// with |m_i| < 2^20: each contribution keeps 2^-20 of the pair's larger
+// magnitude (the slice is implied by the bucket).
+template <int F> struct PartRec {
+  static constexpr int RW = F == 2 ? 2 : 1 + F;  // 32-bit words per record
+};
+
+__device__ __forceinline__ uint64_t pack_rec2(uint32_t ent, float c0, float c1) {
+  const float a = fmaxf(fabsf(c0), fabsf(c1));
+  int e = 0;
+  (void)frexpf(a, &e);  // a < 2^e
+  if (!(a > 0.0f) || e < -126) return (uint64_t)ent;
+  const float sc = ldexpf(1.0f, 20 - e);
+  const int m0 = max(-(1 << 20) + 1, min((1 << 20) - 1, (int)rintf(c0 * sc)));
+  const int m1 = max(-(1 << 20) + 1, min((1 << 20) - 1, (int)rintf(c1 * sc)));
+  return (uint64_t)ent | ((uint64_t)(e + 127) << 13) | ((uint64_t)((uint32_t)m0 & 0x1FFFFFu) << 21) |
+         ((uint64_t)((uint32_t)m1 & 0x1FFFFFu) << 42);
+}
+
+// Fields of a packed record: exponent field (0: zero record) and the two mantissas.
+__device__ __forceinline__ void unpack_rec2(uint64_t r, int& ex, int& m0, int& m1) {
+  ex = (int)((r >> 13) & 0xFFu);
+  m0 = ((int)((uint32_t)(r >> 21) << 11)) >> 11;  // sign-extend 21 bits
+  m1 = ((int)((uint32_t)(r >> 42) << 11)) >> 11;
+}
+
+// m 2^s as a 64-bit integer, rounding to nearest when s < 0.
+__device__ __forceinline__ long long shift_fixed(int m, int s) {
+  if (s >= 0) return (long long)m << min(s, 42);  // |m 2^s| <= M 2^K <= 2^62 keeps s <= 42
+  if (s < -40) return 0;
+  return ((long long)m + (1ll << (-s - 1))) >> (-s);
+}
+
 template <int F>
 __global__ __launch_bounds__(256) void k_part_bucket(LevelDesc ld, PartDesc pd, const BlockMeta* __restrict__ meta,
                                                      const Tile* __restrict__ tiles, int n_tiles,
@@ -66,8 +103,10 @@ __global__ __launch_bounds__(256) void k_part_bucket(LevelDesc ld, PartDesc pd, 
                                                      const float* __restrict__ dfeat, int64_t ls,
                                                      int32_t* __restrict__ cursor, uint32_t* __restrict__ recs,
                                                      float* __restrict__ tmax, float* __restrict__ grad) {
-  constexpr int RW = 1 + F;  // words per record
-  __shared__ uint32_t stage[8 * kTile * RW];
+  constexpr int RW = PartRec<F>::RW;
+  constexpr bool PACK = F == 2;
+  __shared__ __align__(16) uint32_t stage[8 * kTile * RW];  // records in slice order
+  __shared__ uint8_t stq[PACK ? 8 * kTile : 1];  // slice of each packed record
   __shared__ int hist[kPartMaxSlices], lbase[kPartMaxSlices], gbase[kPartMaxSlices], wsum[4];
   __shared__ float wmax[4];
   const int tid = threadIdx.x;
@@ -127,10 +166,15 @@ __global__ __launch_bounds__(256) void k_part_bucket(LevelDesc ld, PartDesc pd, 
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const uint32_t q = e[k] >> sh;
-      const int p = (lbase[q] + rk[k]) * RW;
-      stage[p] = (q << 16) | (e[k] & smask);
+      const int i = lbase[q] + rk[k];
+      if constexpr (PACK) {
+        reinterpret_cast<uint64_t*>(stage)[i] = pack_rec2(e[k] & smask, w[k] * d[0], w[k] * d[1]);
+        stq[i] = (uint8_t)q;
+      } else {
+        stage[i * RW] = (q << 16) | (e[k] & smask);
 #pragma unroll
-      for (int f = 0; f < F; ++f) stage[p + 1 + f] = __float_as_uint(w[k] * d[f]);
+        for (int f = 0; f < F; ++f) stage[i * RW + 1 + f] = __float_as_uint(w[k] * d[f]);
+      }
     }
   }
   __syncthreads();
@@ -138,16 +182,29 @@ __global__ __launch_bounds__(256) void k_part_bucket(LevelDesc ld, PartDesc pd, 
   const int cap = pb[b].cap[l];
   for (int i = tid; i < total; i += 256) {
     const uint32_t w0 = stage[i * RW];
-    const int q = (int)(w0 >> 16);
+    const int q = PACK ? (int)stq[i] : (int)(w0 >> 16);
     const int j = gbase[q] + i - lbase[q];
+    const int64_t rec = off + ((int64_t)q * pd.nsub + sub) * cap + j;
     if (j < cap) {
-      uint32_t* r = recs + (off + ((int64_t)q * pd.nsub + sub) * cap + j) * RW;
+      if constexpr (PACK) {
+        reinterpret_cast<uint64_t*>(recs)[rec] = reinterpret_cast<const uint64_t*>(stage)[i];
+      } else {
 #pragma unroll
-      for (int k = 0; k < RW; ++k) r[k] = stage[i * RW + k];
+        for (int k = 0; k < RW; ++k) recs[rec * RW + k] = stage[i * RW + k];
+      }
     } else {
       float* g = grad + meta[b].param_off + ((int64_t)ld.off[l] + ((int64_t)q << sh) + (w0 & smask)) * F;
+      if constexpr (PACK) {
+        int ex, m0, m1;
+        unpack_rec2(reinterpret_cast<const uint64_t*>(stage)[i], ex, m0, m1);
+        if (ex) {
+          unsafeAtomicAdd(&g[0], ldexpf((float)m0, ex - 147));
+          unsafeAtomicAdd(&g[1], ldexpf((float)m1, ex - 147));
+        }
+      } else {
 #pragma unroll
-      for (int f = 0; f < F; ++f) unsafeAtomicAdd(&g[f], __uint_as_float(stage[i * RW + 1 + f]));
+        for (int f = 0; f < F; ++f) unsafeAtomicAdd(&g[f], __uint_as_float(stage[i * RW + 1 + f]));
+      }
     }
   }
 }
@@ -158,7 +215,8 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
                                                     const PartBlock* __restrict__ pb, int32_t* __restrict__ cursor,
                                                     const uint32_t* __restrict__ recs,
                                                     const float* __restrict__ tmax, float* __restrict__ grad) {
-  constexpr int RW = 1 + F;
+  constexpr int RW = PartRec<F>::RW;
+  constexpr bool PACK = F == 2;
   constexpr int U = 16;  // records in flight per lane
   __shared__ unsigned long long acc[SF];
   __shared__ int sstart[kPartSub + 1];
@@ -207,6 +265,7 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
   (void)frexpf((float)n * M, &E);
   const int K = max(-120, min(120, 62 - E));
   const float scale = ldexpf(1.0f, K);
+  const int kshift = K - 147;  // packed record: contribution i in units 2^-K is m_i 2^(ex - 147 + K)
   const uint32_t* r = recs + (pb[b].off[l] + (int64_t)s * pd.nsub * cap) * RW;
   for (int j0 = 0; j0 < n; j0 += NT * U) {
     // unconditional loads (lanes past the end re-read the last record and skip
@@ -220,16 +279,32 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
 #pragma unroll
       for (int k = 1; k < kPartSub; ++k) g += j >= sstart[k] ? 1 : 0;
       const uint32_t* rr = r + ((int64_t)g * cap + (j - sstart[g])) * RW;
+      if constexpr (PACK) {
+        const uint2 t2 = *reinterpret_cast<const uint2*>(rr);
+        v[u][0] = t2.x;
+        v[u][1] = t2.y;
+      } else {
 #pragma unroll
-      for (int k = 0; k < RW; ++k) v[u][k] = rr[k];
+        for (int k = 0; k < RW; ++k) v[u][k] = rr[k];
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (j0 + u * NT + tid < n) {
         const uint32_t ent = v[u][0] & smask;
+        if constexpr (PACK) {
+          const uint64_t r64 = (uint64_t)v[u][0] | ((uint64_t)v[u][1] << 32);
+          int ex, m0, m1;
+          unpack_rec2(r64, ex, m0, m1);
+          if (ex) {
+            atomicAdd(&acc[ent * 2], (unsigned long long)shift_fixed(m0, ex + kshift));
+            atomicAdd(&acc[ent * 2 + 1], (unsigned long long)shift_fixed(m1, ex + kshift));
+          }
+        } else {
 #pragma unroll
-        for (int f = 0; f < F; ++f)
-          atomicAdd(&acc[ent * F + f], (unsigned long long)__float2ll_rn(__uint_as_float(v[u][1 + f]) * scale));
+          for (int f = 0; f < F; ++f)
+            atomicAdd(&acc[ent * F + f], (unsigned long long)__float2ll_rn(__uint_as_float(v[u][1 + f]) * scale));
+        }
       }
     }
   }
