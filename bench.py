@@ -52,11 +52,12 @@ def phase_bytes(precision, phase, res):
                    + L x F features written (2 B bf16, 4 B fp32)
     scatter_priv : coords (12) + lp x F dL/dy reads (4 B) + lp x 8 corners x F fp32 gradient adds (4 B)
     scatter      : the same for the nd direct levels
-    part_bucket  : coords (12) + np x F dL/dy reads (4 B) + np x 8 records of (1 + F) x 4 B written,
-                   np = L - lf partitioned levels
+    part_bucket  : coords (12) + np x F dL/dy reads (4 B) + np x 8 records written, np = L - lf
+                   partitioned levels; a record is 8 B for F = 2 (packed), (1 + F) x 4 B otherwise
     part_accum   : np x 8 records read, plus per launch one read and one write of
                    every partitioned table entry (F x 4 B each way)
     """
+    rec = 8 if F_FEAT == 2 else (1 + F_FEAT) * 4
     te = 2 if precision == "mixed" else 4
     batch = res["batch"]
     lp, lf = res["priv_levels"], res["part_levels"]
@@ -69,12 +70,12 @@ def phase_bytes(precision, phase, res):
         nl = lp if phase == "scatter_priv" else lf - lp
         return (12 + nl * F_FEAT * 4 + nl * 8 * F_FEAT * 4) * batch if nl > 0 else 0
     if phase == "part_bucket":
-        return (12 + npart * F_FEAT * 4 + npart * 8 * (1 + F_FEAT) * 4) * batch if npart > 0 else 0
+        return (12 + npart * F_FEAT * 4 + npart * 8 * rec) * batch if npart > 0 else 0
     if phase == "part_accum":
         if npart <= 0:
             return 0
         entries = sum(res["level_entries"][lf:]) * res["n_blocks"]
-        return npart * 8 * (1 + F_FEAT) * 4 * batch + entries * F_FEAT * 4 * 2
+        return npart * 8 * rec * batch + entries * F_FEAT * 4 * 2
     return None
 
 
@@ -162,12 +163,18 @@ def run_precision(torch, DVNR, cfg, blocks, vols, precision, steps, warmup, seed
             cnt += c
         # per-phase device times: a further short run with HIP events between the
         # phases (eager launches), after the quality of the timed run was measured
+        # (the concurrent branches of the step run one after the other here, so
+        # that each phase is one kernel's time)
         model.set_option("profile_phases", 1)
+        model.set_option("part_concurrent", 0)
+        model.set_option("encode_concurrent", 0)
         model.phase_times()
         model.train(min(steps, 200), batch, stream=stream)
         stream.synchronize()
         phases, nsteps = model.phase_times()
         model.set_option("profile_phases", 0)
+        model.set_option("part_concurrent", 1)
+        model.set_option("encode_concurrent", 1)
         render = None
         if len(blocks) == 1:
             # sample-streaming direct volume rendering of the trained block, 1024^2 rays
