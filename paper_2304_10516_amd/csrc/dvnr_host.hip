@@ -144,7 +144,9 @@ struct dvnr {
   int part_min = 0;       // first level that may be partitioned (workspace sized for [part_min, L))
   int part_l0 = 0;
   PartDesc pdesc{};
-  int64_t o_pblk = 0, o_pcur = 0, o_precs = 0, o_ptmax = 0;
+  int64_t o_pblk = 0, o_pcur = 0, o_precs = 0, o_ptmax = 0, o_povf = 0;
+  uint8_t* d_povf() const { return (uint8_t*)(ws() + o_povf); }  // [nb][nq] overflow flags
+  int part_adam = 1;  // option: the slice pass applies Adam to the partitioned levels
   PartBlock* d_pblk() const { return (PartBlock*)(ws() + o_pblk); }
   float* d_ptmax() const { return (float*)(ws() + o_ptmax); }  // [levels][tiles] largest contribution
   int32_t* d_pcur() const { return (int32_t*)(ws() + o_pcur); }
@@ -350,6 +352,7 @@ dvnr_status dvnr_create(const dvnr_encoding* enc, const dvnr_mlp* mlp, const dvn
       const int64_t nl = e.n_levels - pm;
       h->o_pblk = take(sizeof(PartBlock) * n_blocks);
       h->o_ptmax = take(sizeof(float) * nl * h->max_tiles);
+      h->o_povf = take(sizeof(uint8_t) * kPartMaxSlices * nl * n_blocks);
       h->o_pcur = take(sizeof(int32_t) * kPartSub * kPartMaxSlices * nl * n_blocks);
       h->o_precs = take(sizeof(uint32_t) * (1 + e.n_features) * nl * part_level_records(max_batch, n_blocks));
     }
@@ -608,6 +611,7 @@ static dvnr_status plan_partition(dvnr_t* h, const std::vector<int64_t>& n, hipS
     return fail(DVNR_E_INVALID, "partitioned backward exceeds its workspace");
   HIPCHK(hipMemcpyAsync(h->d_pblk(), pbv.data(), sizeof(PartBlock) * h->nb, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(h->d_pcur(), 0, sizeof(int32_t) * kPartSub * h->nb * nq, s));
+  HIPCHK(hipMemsetAsync(h->d_povf(), 0, sizeof(uint8_t) * h->nb * nq, s));
   return DVNR_OK;
 }
 
@@ -826,15 +830,42 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   // part_concurrent: the partitioned passes (HBM streams) run on the second
   // stream while the privatized levels (LDS and latency bound) run on `s`
   const bool pconc = h->part_concurrent && lf < h->enc.n_levels && lp > 0;
+  // part_adam: the slice pass applies Adam to the partitioned levels itself
+  // (their gradient never goes through memory); it reads the step counter
+  // before the slot reduction advances it
+  const bool padam = h->part_adam && h->apply_update && lf < h->enc.n_levels;
+  PartAdam pa{};
+  if (padam) {
+    pa.params = (float*)h->buf.params;
+    pa.m = (float*)h->buf.adam_m;
+    pa.v = (float*)h->buf.adam_v;
+    pa.work16 = mixed ? (uint16_t*)h->buf.work16 : nullptr;
+    pa.ctr = h->d_ctr();
+    pa.lr0 = (float)h->opt.lr;
+    pa.b1 = (float)h->opt.beta1;
+    pa.b2 = (float)h->opt.beta2;
+    pa.eps = (float)h->opt.eps;
+    pa.wd = (float)h->opt.weight_decay;
+    pa.decay_base = h->opt.lr_decay_interval > 0 ? h->opt.lr_decay_base : 1.0;
+    pa.decay_start = h->opt.lr_decay_start;
+    pa.decay_interval = h->opt.lr_decay_interval > 0 ? h->opt.lr_decay_interval : 0;
+  }
+  auto part_bucket = [&](hipStream_t st) {
+    return launch_part_bucket(h->ld, h->pdesc, h->d_meta(), h->d_tiles(), h->n_tiles, h->d_plan(), h->d_pblk(),
+                              h->d_coords(), h->d_dfeat(), h->max_batch * F, h->d_pcur(), h->d_precs(),
+                              h->d_ptmax(), h->d_povf(), (float*)h->buf.grads, st);
+  };
+  auto part_accum = [&](hipStream_t st) {
+    return launch_part_accum(h->ld, h->pdesc, h->d_meta(), h->nb, h->n_tiles, h->d_plan(), h->d_pblk(),
+                             h->d_pcur(), h->d_precs(), h->d_ptmax(), (float*)h->buf.grads, padam ? &pa : nullptr,
+                             h->d_povf(), st);
+  };
   if (pconc) {
     HIPCHK(ensure_side(h));
     HIPCHK(hipEventRecord(h->ev_fork2, s));
     HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork2, 0));
-    HIPCHK(launch_part_bucket(h->ld, h->pdesc, h->d_meta(), h->d_tiles(), h->n_tiles, h->d_plan(), h->d_pblk(),
-                              h->d_coords(), h->d_dfeat(), h->max_batch * F, h->d_pcur(), h->d_precs(),
-                              h->d_ptmax(), (float*)h->buf.grads, h->side));
-    HIPCHK(launch_part_accum(h->ld, h->pdesc, h->d_meta(), h->nb, h->n_tiles, h->d_plan(), h->d_pblk(),
-                             h->d_pcur(), h->d_precs(), h->d_ptmax(), (float*)h->buf.grads, h->side));
+    HIPCHK(part_bucket(h->side));
+    HIPCHK(part_accum(h->side));
     HIPCHK(hipEventRecord(h->ev_join2, h->side));
   }
   // privatized levels [0, lp) in up to three launches by LDS class: small boxes
@@ -871,30 +902,31 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
                         h->d_coords(), h->d_dfeat(), F, h->max_batch * F, h->buf.grads, h->scatter_grouped,
                         h->xcd_map, sorted ? h->scatter_strided : 0, s));
   PROF(5);
-  if (lf < h->enc.n_levels && !pconc)
-    HIPCHK(launch_part_bucket(h->ld, h->pdesc, h->d_meta(), h->d_tiles(), h->n_tiles, h->d_plan(), h->d_pblk(),
-                              h->d_coords(), h->d_dfeat(), h->max_batch * F, h->d_pcur(), h->d_precs(),
-                              h->d_ptmax(), (float*)h->buf.grads, s));
+  if (lf < h->enc.n_levels && !pconc) HIPCHK(part_bucket(s));
   PROF(6);
-  if (lf < h->enc.n_levels && !pconc)
-    HIPCHK(launch_part_accum(h->ld, h->pdesc, h->d_meta(), h->nb, h->n_tiles, h->d_plan(), h->d_pblk(),
-                             h->d_pcur(), h->d_precs(), h->d_ptmax(), (float*)h->buf.grads, s));
+  if (lf < h->enc.n_levels && !pconc) HIPCHK(part_accum(s));
   PROF(7);
   // the weight-gradient reduction needs only the MLP's slots and writes the
-  // weights' gradient: with the concurrent passes it runs before the join
+  // weights' gradient: with the concurrent passes it runs before the join,
+  // unless the slice pass still has to read the step counter it advances
+  if (pconc && padam) HIPCHK(hipStreamWaitEvent(s, h->ev_join2, 0));
   HIPCHK(launch_reduce_slots(h->d_slots(), h->slot_stride, h->d_ranges(), h->nb, h->n_mlp, h->n_table, h->stride,
                              Prec::F32, h->buf.grads, h->d_ring(), h->d_ctr(), 1, s));
-  if (pconc) HIPCHK(hipStreamWaitEvent(s, h->ev_join2, 0));
+  if (pconc && !padam) HIPCHK(hipStreamWaitEvent(s, h->ev_join2, 0));
   PROF(8);
   if (!h->apply_update) {
     PROF(9);
     return DVNR_OK;
   }
+  // Adam over the parameters the slice pass did not update: the partitioned
+  // levels' tables are the block-relative elements [off_lf F, n_table)
+  const int64_t skip0 = padam ? (int64_t)h->ld.off[lf] * F : 0, skip1 = padam ? h->n_table : 0;
   HIPCHK(launch_adam(h->prec, h->buf.params, h->buf.grads, h->buf.adam_m, h->buf.adam_v,
                      mixed ? (uint16_t*)h->buf.work16 : nullptr, h->nb, h->stride, h->n_table, h->n_table + h->n_mlp,
                      h->d_plan(), h->d_ctr(), h->opt.lr, h->opt.beta1, h->opt.beta2, h->opt.eps,
                      h->opt.weight_decay, h->opt.lr_decay_interval > 0 ? h->opt.lr_decay_base : 1.0,
-                     h->opt.lr_decay_start, h->opt.lr_decay_interval > 0 ? h->opt.lr_decay_interval : 0, s));
+                     h->opt.lr_decay_start, h->opt.lr_decay_interval > 0 ? h->opt.lr_decay_interval : 0, s, skip0,
+                     skip1));
   PROF(9);
   return DVNR_OK;
 }
@@ -1591,6 +1623,8 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
   } else if (n == "part_capacity") {
     h->part_cap = (int)std::max<int64_t>(0, std::min<int64_t>(value, 1 << 30));
     h->plan_total = -1;
+  } else if (n == "part_adam") {
+    h->part_adam = value ? 1 : 0;
   } else if (n == "encode_concurrent") {
     h->encode_concurrent = value ? 1 : 0;
   } else if (n == "part_concurrent") {

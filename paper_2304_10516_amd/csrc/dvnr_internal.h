@@ -159,13 +159,32 @@ struct PartBlock {
 // point scaled by the block's largest contribution), adds the slice into
 // `grad` and clears the bucket's cursors (cursors start at zero and are left
 // at zero).
+// ovf[b * nq + q] is set to 1 when a record of bucket q of block b took the
+// overflow atomics (the slice pass then also reads the gradient, and clears
+// the flag).
 hipError_t launch_part_bucket(const LevelDesc& ld, const PartDesc& pd, const BlockMeta* meta, const Tile* tiles,
                               int n_tiles, const BlockPlan* plan, const PartBlock* pb, const float* coords,
                               const float* dfeat, int64_t ls, int32_t* cursor, uint32_t* recs, float* tmax,
-                              float* grad, hipStream_t s);
+                              uint8_t* ovf, float* grad, hipStream_t s);
+// Adam applied by the slice pass to its slice (fp32 parameters, fp16 working
+// copy of the table when work16 != nullptr); the step counter is read before
+// the slot reduction advances it, so the update's index is ctr->step + 1.
+struct PartAdam {
+  float* params;
+  float* m;
+  float* v;
+  uint16_t* work16;
+  const Counters* ctr;
+  float lr0, b1, b2, eps, wd;
+  double decay_base;
+  int64_t decay_start, decay_interval;
+};
+// adam == nullptr: the slice pass adds its sums into `grad`; otherwise it
+// updates the slice's parameters and leaves their gradient at zero.
 hipError_t launch_part_accum(const LevelDesc& ld, const PartDesc& pd, const BlockMeta* meta, int n_blocks,
                              int n_tiles, const BlockPlan* plan, const PartBlock* pb, int32_t* cursor,
-                             const uint32_t* recs, const float* tmax, float* grad, hipStream_t s);
+                             const uint32_t* recs, const float* tmax, float* grad, const PartAdam* adam,
+                             uint8_t* ovf, hipStream_t s);
 
 // Spatially ordered sampler: Philox draws of every group (<= kSortGroup
 // samples of one block) stored grouped by B^3 spatial bins; bin_start
@@ -199,10 +218,13 @@ hipError_t launch_reduce_slots(const float* slots, int64_t slot_stride, const in
                                int64_t n_mlp, int64_t mlp_rel_off, int64_t block_stride, Prec gp, void* grad,
                                float* loss_ring, Counters* ctr, int bump, hipStream_t s);
 
+// skip0 <= skip1: block-relative elements [skip0, skip1) are left alone (the
+// slice pass updated them).
 hipError_t launch_adam(Prec p, void* params, void* grad, void* m, void* v, uint16_t* work16, int n_blocks,
                        int64_t block_stride, int64_t n_table_params, int64_t n_used, const BlockPlan* plan,
                        const Counters* ctr, double lr, double b1, double b2, double eps, double wd,
-                       double decay_base, int64_t decay_start, int64_t decay_interval, hipStream_t s);
+                       double decay_base, int64_t decay_start, int64_t decay_interval, hipStream_t s,
+                       int64_t skip0 = 0, int64_t skip1 = 0);
 
 // Reference-style building blocks (thread per sample) for the autograd pieces.
 hipError_t launch_mlp_simple_fwd(Prec p, const MlpDesc& md, int64_t n, const void* feats, const void* w,

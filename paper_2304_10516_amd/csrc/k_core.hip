@@ -445,7 +445,7 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
                                               int64_t block_stride, int64_t n_table, int64_t n_used,
                                               const BlockPlan* __restrict__ plan, const Counters* __restrict__ ctr,
                                               P lr0, P b1, P b2, P eps, P wd, double decay_base, int64_t decay_start,
-                                              int64_t decay_interval) {
+                                              int64_t decay_interval, int64_t skip0, int64_t skip1) {
   // grid (element groups of the block, blocks): no division per element, one
   // uniform skip for a block that drew no sample this step
   const int b = blockIdx.y;
@@ -463,8 +463,20 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
   }
   __syncthreads();
   const P bc1 = bc[0], bc2 = bc[1], lr = bc[2];
-  const int64_t j0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  // with a skipped range, the first pre = ceil(skip0 / 1024) workgroup columns
+  // cover [0, 1024 pre) and the others [max(1024 pre, skip1 rounded down to
+  // 1024), n_used): every element outside the range exactly once
+  int64_t gx = blockIdx.x, base = 0;
+  if (skip1 > skip0) {
+    const int64_t pre = (skip0 + 1023) / 1024;
+    if (gx >= pre) {
+      base = max(pre * 1024, skip1 / 1024 * 1024);
+      gx -= pre;
+    }
+  }
+  const int64_t j0 = base + 4 * (gx * blockDim.x + threadIdx.x);
   if (j0 >= n_used) return;
+  if (j0 >= skip0 && j0 + 4 <= skip1) return;  // updated by the slice pass
   const int64_t i0 = (int64_t)b * block_stride + j0;
   P th[4], g[4], m[4], v[4];
   if constexpr (sizeof(P) == 4) {
@@ -491,12 +503,16 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
       v[k] = vel[i0 + k];
     }
   }
+  bool keep[4];  // elements of a group straddling the skipped range keep their values
+#pragma unroll
+  for (int k = 0; k < 4; ++k) keep[k] = j0 + k >= skip0 && j0 + k < skip1;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (j0 + k >= n_used) {
       g[k] = 0;
       continue;
     }
+    if (keep[k]) continue;
     const P gg = g[k] + wd * th[k];
     m[k] = b1 * m[k] + (P(1) - b1) * gg;
     v[k] = b2 * v[k] + (P(1) - b2) * gg * gg;
@@ -522,6 +538,7 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
   if (work16) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
+      if (keep[k]) continue;
       const float f = (float)th[k];
       uint16_t bits;
       if (j0 + k < n_table) {
@@ -539,18 +556,24 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
 hipError_t launch_adam(Prec p, void* params, void* grad, void* m, void* v, uint16_t* work16, int n_blocks,
                        int64_t block_stride, int64_t n_table_params, int64_t n_used, const BlockPlan* plan,
                        const Counters* ctr, double lr, double b1, double b2, double eps, double wd,
-                       double decay_base, int64_t decay_start, int64_t decay_interval, hipStream_t s) {
+                       double decay_base, int64_t decay_start, int64_t decay_interval, hipStream_t s,
+                       int64_t skip0, int64_t skip1) {
   if (n_blocks <= 0 || n_used <= 0) return hipSuccess;
   if (n_blocks > 65535) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((n_used + 1023) / 1024), (unsigned)n_blocks);
+  int64_t gx = (n_used + 1023) / 1024;
+  if (skip1 > skip0) {
+    const int64_t pre = (skip0 + 1023) / 1024, base = std::max(pre * 1024, skip1 / 1024 * 1024);
+    gx = pre + std::max<int64_t>(0, (n_used - base + 1023) / 1024);
+  }
+  const dim3 grid((unsigned)gx, (unsigned)n_blocks);
   if (p == Prec::F64)
     hipLaunchKernelGGL(k_adam<double>, grid, dim3(256), 0, s, (double*)params, (double*)grad, (double*)m, (double*)v,
                        nullptr, block_stride, n_table_params, n_used, plan, ctr, lr, b1, b2, eps, wd, decay_base,
-                       decay_start, decay_interval);
+                       decay_start, decay_interval, skip0, skip1);
   else
     hipLaunchKernelGGL(k_adam<float>, grid, dim3(256), 0, s, (float*)params, (float*)grad, (float*)m, (float*)v,
                        work16, block_stride, n_table_params, n_used, plan, ctr, (float)lr, (float)b1, (float)b2,
-                       (float)eps, (float)wd, decay_base, decay_start, decay_interval);
+                       (float)eps, (float)wd, decay_base, decay_start, decay_interval, skip0, skip1);
   return hipGetLastError();
 }
 

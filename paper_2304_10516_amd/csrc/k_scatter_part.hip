@@ -102,7 +102,8 @@ __global__ __launch_bounds__(256) void k_part_bucket(LevelDesc ld, PartDesc pd, 
                                                      const float* __restrict__ coords,
                                                      const float* __restrict__ dfeat, int64_t ls,
                                                      int32_t* __restrict__ cursor, uint32_t* __restrict__ recs,
-                                                     float* __restrict__ tmax, float* __restrict__ grad) {
+                                                     float* __restrict__ tmax, uint8_t* __restrict__ ovf,
+                                                     float* __restrict__ grad) {
   constexpr int RW = PartRec<F>::RW;
   constexpr bool PACK = F == 2;
   __shared__ __align__(16) uint32_t stage[8 * kTile * RW];  // records in slice order
@@ -193,6 +194,7 @@ __global__ __launch_bounds__(256) void k_part_bucket(LevelDesc ld, PartDesc pd, 
         for (int k = 0; k < RW; ++k) recs[rec * RW + k] = stage[i * RW + k];
       }
     } else {
+      ovf[(int64_t)b * pd.nq + pd.qbase[l] + q] = 1;
       float* g = grad + meta[b].param_off + ((int64_t)ld.off[l] + ((int64_t)q << sh) + (w0 & smask)) * F;
       if constexpr (PACK) {
         int ex, m0, m1;
@@ -214,7 +216,8 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
                                                     int n_tiles, const BlockPlan* __restrict__ plan,
                                                     const PartBlock* __restrict__ pb, int32_t* __restrict__ cursor,
                                                     const uint32_t* __restrict__ recs,
-                                                    const float* __restrict__ tmax, float* __restrict__ grad) {
+                                                    const float* __restrict__ tmax, float* __restrict__ grad,
+                                                    PartAdam adam, int do_adam, uint8_t* __restrict__ ovf) {
   constexpr int RW = PartRec<F>::RW;
   constexpr bool PACK = F == 2;
   constexpr int U = 16;  // records in flight per lane
@@ -312,21 +315,73 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
   const double unit = 1.0 / (double)scale;
   const int64_t e0 = (int64_t)s << sh;
   const int nf = (int)min((int64_t)1 << sh, (int64_t)pd.E[l] - e0) * F;
-  float* g = grad + meta[b].param_off + ((int64_t)ld.off[l] + e0) * F;
-  // read-add-write of the slice: batches of unconditional loads (clamped to
-  // the slice) so that a lane's loads overlap instead of waiting one by one
+  const int64_t el0 = meta[b].param_off + ((int64_t)ld.off[l] + e0) * F;  // first element of the slice
+  float* g = grad + el0;
+  // overflow records of this bucket went to the gradient by atomics
+  __shared__ int has_ovf;
+  __shared__ float hbc[3];
+  if (tid == 0) {
+    uint8_t* fl = ovf + (int64_t)b * pd.nq + q;
+    has_ovf = *fl;
+    *fl = 0;
+    if (do_adam) {
+      // this update's index t = step + 1 (the slot reduction advances the counter later)
+      const int64_t ti = adam.ctr->step + 1;
+      const double t = (double)ti;
+      hbc[0] = (float)(1.0 / (1.0 - pow((double)adam.b1, t)));
+      hbc[1] = (float)(1.0 / (1.0 - pow((double)adam.b2, t)));
+      double lr = (double)adam.lr0;
+      if (adam.decay_interval > 0 && ti > adam.decay_start)
+        lr *= pow(adam.decay_base, (double)(ti - adam.decay_start) / (double)adam.decay_interval);
+      hbc[2] = (float)lr;
+    }
+  }
+  __syncthreads();
+  const bool rd_g = !do_adam || has_ovf;
+  // read-add-write of the slice (or its Adam update): batches of unconditional
+  // loads (clamped to the slice) so that a lane's loads overlap
   constexpr int PT = SF / NT, KB = PT < 8 ? PT : 8;
   for (int k0 = 0; k0 < PT; k0 += KB) {
     float gv[KB];
 #pragma unroll
-    for (int k = 0; k < KB; ++k) gv[k] = g[min(tid + NT * (k0 + k), nf - 1)];
+    for (int k = 0; k < KB; ++k) gv[k] = rd_g ? g[min(tid + NT * (k0 + k), nf - 1)] : 0.0f;
+    if (!do_adam) {
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        const int i = tid + NT * (k0 + k);
+        if (i < nf) {
+          const long long a = (long long)acc[i];
+          if (a != 0) g[i] = gv[k] + (float)((double)a * unit);
+        }
+      }
+      continue;
+    }
+    float th[KB], mm[KB], vv[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int64_t e = el0 + min(tid + NT * (k0 + k), nf - 1);
+      th[k] = adam.params[e];
+      mm[k] = adam.m[e];
+      vv[k] = adam.v[e];
+    }
+    const float bc1 = hbc[0], bc2 = hbc[1], lr = hbc[2];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       const int i = tid + NT * (k0 + k);
-      if (i < nf) {
-        const long long a = (long long)acc[i];
-        if (a != 0) g[i] = gv[k] + (float)((double)a * unit);
+      if (i >= nf) continue;
+      const float gg = gv[k] + (float)((double)(long long)acc[i] * unit) + adam.wd * th[k];
+      const float m1 = adam.b1 * mm[k] + (1.0f - adam.b1) * gg;
+      const float v1 = adam.b2 * vv[k] + (1.0f - adam.b2) * gg * gg;
+      const float t1 = th[k] - lr * (m1 * bc1) / (sqrtf(v1 * bc2) + adam.eps);
+      const int64_t e = el0 + i;
+      adam.params[e] = t1;
+      adam.m[e] = m1;
+      adam.v[e] = v1;
+      if (adam.work16) {
+        const __half hv = __float2half_rn(t1);
+        adam.work16[e] = *reinterpret_cast<const uint16_t*>(&hv);
       }
+      if (has_ovf) g[i] = 0.0f;
     }
   }
 }
@@ -334,7 +389,7 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
 hipError_t launch_part_bucket(const LevelDesc& ld, const PartDesc& pd, const BlockMeta* meta, const Tile* tiles,
                               int n_tiles, const BlockPlan* plan, const PartBlock* pb, const float* coords,
                               const float* dfeat, int64_t ls, int32_t* cursor, uint32_t* recs, float* tmax,
-                              float* grad, hipStream_t s) {
+                              uint8_t* ovf, float* grad, hipStream_t s) {
   if (pd.nl <= 0 || n_tiles <= 0) return hipSuccess;
   const int64_t grid = (int64_t)n_tiles * pd.nl;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
@@ -347,7 +402,7 @@ hipError_t launch_part_bucket(const LevelDesc& ld, const PartDesc& pd, const Blo
 #define DVNR_PART_B(FF)                                                                                          \
   case FF:                                                                                                       \
     hipLaunchKernelGGL(k_part_bucket<FF>, dim3((unsigned)grid), dim3(256), 0, s, ld, pd, meta, tiles, n_tiles,   \
-                       plan, pb, coords, dfeat, ls, cursor, recs, tmax, grad);                                         \
+                       plan, pb, coords, dfeat, ls, cursor, recs, tmax, ovf, grad);                                         \
     break;
     DVNR_PART_B(1)
     DVNR_PART_B(2)
@@ -361,7 +416,10 @@ hipError_t launch_part_bucket(const LevelDesc& ld, const PartDesc& pd, const Blo
 
 hipError_t launch_part_accum(const LevelDesc& ld, const PartDesc& pd, const BlockMeta* meta, int n_blocks,
                              int n_tiles, const BlockPlan* plan, const PartBlock* pb, int32_t* cursor,
-                             const uint32_t* recs, const float* tmax, float* grad, hipStream_t s) {
+                             const uint32_t* recs, const float* tmax, float* grad, const PartAdam* adam,
+                             uint8_t* ovf, hipStream_t s) {
+  const PartAdam ad = adam ? *adam : PartAdam{};
+  const int do_adam = adam ? 1 : 0;
   if (pd.nl <= 0 || n_blocks <= 0 || pd.nq <= 0) return hipSuccess;
   const int64_t grid = (int64_t)n_blocks * pd.nq;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
@@ -371,7 +429,7 @@ hipError_t launch_part_accum(const LevelDesc& ld, const PartDesc& pd, const Bloc
     if (((int64_t)ld.F << pd.sh[l]) > pd.slice_floats || pd.ns[l] > kPartMaxSlices) return hipErrorInvalidValue;
 #define DVNR_PART_A(FF, SS)                                                                                      \
   hipLaunchKernelGGL((k_part_accum<FF, SS, kPartAccumThreads>), dim3((unsigned)grid), dim3(kPartAccumThreads), 0, s, \
-                     ld, pd, meta, n_tiles, plan, pb, cursor, recs, tmax, grad)
+                     ld, pd, meta, n_tiles, plan, pb, cursor, recs, tmax, grad, ad, do_adam, ovf)
 #define DVNR_PART_SF(FF)                                                                                         \
   case FF:                                                                                                       \
     if (pd.slice_floats == 4096) DVNR_PART_A(FF, 4096);                                                          \

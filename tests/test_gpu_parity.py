@@ -339,6 +339,55 @@ def test_adam_update_parity_c1(decay):
     assert np.mean(d[small] <= 3 * opt.lr * 1.01) == 1.0
 
 
+@pytest.mark.parametrize("decay", [False, True])
+def test_adam_fused_in_slice_pass_c2(decay):
+    """Levels 9..15 destination-partitioned with the Adam update applied by the
+    slice pass (part_adam): three fp32 steps on explicit coordinates against the
+    oracle's Adam (same bars as the plain update test), and on the partitioned
+    levels after the first step against the separate Adam kernel (the same
+    arithmetic on the same fixed-point sums: within 1e-7)."""
+    say(f"adam fused into the slice pass, c2 levels fp32, learning-rate decay {decay}")
+    from paper_2304_10516_amd.dvnr import DVNR, EncodingCfg, MlpCfg, OptimCfg
+    vol = gaussian_sum_field(64, seed=3)
+    lay = o.layout(*C2)
+    p = init_param_draws(lay.n_table_params, lay.mlp_shapes, seed=2).astype(np.float64)
+    p[:lay.n_table_params] *= 1e3
+    kw = dict(lr=1e-2, lr_decay_base=0.5, lr_decay_start=1, lr_decay_interval=1) if decay else dict(lr=1e-2)
+    enc, mlp = C2
+    out, first = {}, {}
+    for fused in (1, 0):
+        model = DVNR(EncodingCfg(enc.n_levels, enc.n_features, enc.log2_table_size, enc.base_resolution,
+                                 enc.per_level_scale, enc.finest_resolution), MlpCfg(mlp.n_hidden_layers, mlp.width),
+                     [((64, 64, 64), 0)], OptimCfg(**kw), precision="fp32", max_batch=1 << 14, seed=91)
+        model.bind_volumes([dev(vol)])
+        model.load_params([p])
+        model.set_option("scatter_part", 9)
+        model.set_option("part_adam", fused)
+        pr = model.block_params(0).cpu().numpy().astype(np.float64)
+        st, opt = o.adam_init(lay.n_params), o.Optim(**kw)
+        small = np.zeros(lay.n_params, bool)
+        for step in range(3):
+            x = o.training_coords(91, 0, step, 8192)
+            model.train_step_coords(dev(x), [8192])
+            assert model.partitioned_levels() == 9
+            if step == 0:
+                first[fused] = model.block_params(0).cpu().numpy().astype(np.float64)
+            L, g, _ = o.loss_and_grad(lay, pr, x, o.normalized_targets(vol, (64, 64, 64), 0, x))
+            small |= np.abs(g) < 1e-5 * np.abs(g).max()
+            pr = o.adam(pr, g, st, opt)
+        torch.cuda.synchronize()
+        out[fused] = model.block_params(0).cpu().numpy().astype(np.float64)
+        d = np.abs(out[fused] - pr)
+        assert np.max(d[~small]) <= 1e-4 * opt.lr * 3 + 1e-7
+        assert np.mean(d[small] <= 3 * opt.lr * 1.01) == 1.0
+        assert float(model.grads.abs().max()) == 0.0  # every gradient is left at zero for the next step
+    # after the first step: the partitioned levels' sums are fixed point (order
+    # independent), so both ways apply Adam to the same gradient there (later
+    # steps differ through the other levels' float atomics, taken in any order)
+    a0 = lay.levels[9].off * 2
+    assert np.max(np.abs(first[1][a0:lay.n_table_params] - first[0][a0:lay.n_table_params])) <= 1e-7
+
+
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("mixed", 1e-2)])
 @pytest.mark.parametrize("fused,dims,cfg_name", [(1, (24, 20, 16), "c2"), (0, (24, 20, 16), "c2"),
                                                  (1, (37, 9, 21), "c1")])
