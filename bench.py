@@ -42,6 +42,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def part_params(res):
+    """Table parameters of the destination-partitioned levels (updated by the slice pass)."""
+    lf = res["part_levels"]
+    return sum(res["level_entries"][lf:]) * F_FEAT * res["n_blocks"] if lf < L_LEVELS else 0
+
+
 def phase_bytes(precision, phase, res):
     """Algorithmic bytes of one launch of a phase's kernel (None: not a byte-bound phase).
 
@@ -54,8 +60,10 @@ def phase_bytes(precision, phase, res):
     scatter      : the same for the nd direct levels
     part_bucket  : coords (12) + np x F dL/dy reads (4 B) + np x 8 records written, np = L - lf
                    partitioned levels; a record is 8 B for F = 2 (packed), (1 + F) x 4 B otherwise
-    part_accum   : np x 8 records read, plus per launch one read and one write of
-                   every partitioned table entry (F x 4 B each way)
+    part_accum   : np x 8 records read, plus per launch the Adam update of every partitioned
+                   table parameter, which the slice pass applies itself: theta, m, v read and
+                   written (24 B) and the fp16 working copy written (2 B, mixed precision)
+    adam         : the remaining parameters (34 B each mixed, 32 B fp32)
     """
     rec = 8 if F_FEAT == 2 else (1 + F_FEAT) * 4
     te = 2 if precision == "mixed" else 4
@@ -74,8 +82,9 @@ def phase_bytes(precision, phase, res):
     if phase == "part_accum":
         if npart <= 0:
             return 0
-        entries = sum(res["level_entries"][lf:]) * res["n_blocks"]
-        return npart * 8 * rec * batch + entries * F_FEAT * 4 * 2
+        return npart * 8 * rec * batch + part_params(res) * (26 if precision == "mixed" else 24)
+    if phase == "adam":
+        return ADAM_BYTES_PER_PARAM[precision] * (res["n_params"] - part_params(res))
     return None
 
 
@@ -294,9 +303,7 @@ def roofline_for(precision, res):
     ph = res["phase_ms"]
     dom = max(ph, key=lambda k: ph[k])
     batch = res["batch"]
-    if dom == "adam":
-        per_launch = ADAM_BYTES_PER_PARAM[precision] * res["n_params"]
-    elif phase_bytes(precision, dom, res) is not None:
+    if phase_bytes(precision, dom, res) is not None:
         per_launch = phase_bytes(precision, dom, res)
     else:  # mlp: MFMA-bound reading, 37,248 flop per sample
         flops = 37248.0 * batch
@@ -308,7 +315,7 @@ def roofline_for(precision, res):
     # the other byte-bound phases against the same peak
     others = {}
     for k, v in ph.items():
-        b = ADAM_BYTES_PER_PARAM[precision] * res["n_params"] if k == "adam" else phase_bytes(precision, k, res)
+        b = phase_bytes(precision, k, res)
         if k != dom and b and v > 0:
             others[k] = round(b / (v * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
     return {"kernel": PHASE_KERNEL.get(dom, dom), "phase": dom, "bound": "hbm", "achieved": gbs,
