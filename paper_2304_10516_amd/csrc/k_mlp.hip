@@ -133,12 +133,6 @@ __device__ void load_weights(const WSRC* __restrict__ wsrc, const MlpDesc& md, t
 
 template <typename T> __device__ __forceinline__ float ldf(const T* p) { return (float)*p; }
 
-// Level-major feature planes [L][plane][F]; feature f of sample gi.
-template <typename FT>
-__device__ __forceinline__ float load_feat(const FT* __restrict__ feat, int64_t plane, int F, int64_t gi, int f) {
-  const int l = f / F, ff = f % F;
-  return (float)feat[((int64_t)l * plane + gi) * F + ff];
-}
 
 // ---------------------------------------------------------------------------
 // Training kernel.  Persistent: workgroup w processes tiles
@@ -248,6 +242,22 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
 
   int cur_block = -1;
   reset();
+  // element offsets (without the sample term gi * F) of the features this lane
+  // reads (8 g + i) and of the feature gradients it writes (16 mm + 4 g + i);
+  // -1 past the input width.  The launcher keeps L * plane * F below 2^31.
+  int fo[8], dxo[2][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int f = 8 * g + i;
+    fo[i] = f < md.in_dim ? (f / F) * (int)plane * F + f % F : -1;
+  }
+#pragma unroll
+  for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int f = 16 * mm + 4 * g + i;
+      dxo[mm][i] = f < md.in_dim ? (f / F) * (int)plane * F + f % F : -1;
+    }
   for (int t = t0; t < t1; ++t) {
     const Tile tl = tiles[t];
     if (tl.block != cur_block) {
@@ -278,11 +288,9 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
       const int sl = wave * 64 + k * 16 + c;
       const bool ok = sl < tl.count;
       const int64_t gi = base + sl;
+      const int gF = (int)gi * F;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int f = 8 * g + i;
-        x[i] = (ok && f < md.in_dim) ? load_feat(feat, plane, F, gi, f) : 0.0f;
-      }
+      for (int i = 0; i < 8; ++i) x[i] = (ok && fo[i] >= 0) ? (float)feat[fo[i] + gF] : 0.0f;
       y = ok ? target[gi] : 0.0f;
     };
     load_group(0, xr, yr);
@@ -396,10 +404,8 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
               acc = TR::mma(A[(S::N_A0 + 2 * S::N_AH + mm * S::KS_H + s) * 64 + lane], db[s], acc);
             if (valid) {
 #pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const int f = 16 * mm + 4 * g + i;
-                if (f < md.in_dim) dfeat[((int64_t)(f / F) * plane + gi) * F + (f % F)] = acc[i];
-              }
+              for (int i = 0; i < 4; ++i)
+                if (dxo[mm][i] >= 0) dfeat[dxo[mm][i] + (int)gi * F] = acc[i];
             }
           }
         }
@@ -464,6 +470,14 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpDesc md, int F, const Bloc
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int g = lane / 16, c = lane % 16;
   const BlockRange br = range[tl.block];
+  int fo[S::KS_IN * TR::VPL];  // element offsets of this lane's features (-1 past the input width)
+#pragma unroll
+  for (int s = 0; s < S::KS_IN; ++s)
+#pragma unroll
+    for (int j = 0; j < TR::VPL; ++j) {
+      const int f = 8 * g + s * TR::VPL + j;
+      fo[s * TR::VPL + j] = f < md.in_dim ? (f / F) * (int)plane * F + f % F : -1;
+    }
   for (int q = 0; q < 4; ++q) {
     const int sl = wave * 64 + q * 16 + c;
     const bool valid = sl < tl.count;
@@ -473,8 +487,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpDesc md, int F, const Bloc
     for (int s = 0; s < S::KS_IN; ++s)
 #pragma unroll
       for (int j = 0; j < TR::VPL; ++j) {
-        const int f = 8 * g + s * TR::VPL + j;
-        TR::put(xb[s], j, (valid && f < md.in_dim) ? load_feat(feat, plane, F, gi, f) : 0.0f);
+        const int o = fo[s * TR::VPL + j];
+        TR::put(xb[s], j, (valid && o >= 0) ? (float)feat[o + (int)gi * F] : 0.0f);
       }
     f32x4 h[S::MT];
 #pragma unroll
@@ -562,7 +576,8 @@ hipError_t launch_mlp_train(Prec p, const MlpDesc& md, const LevelDesc& ld, cons
                             const float* target, const void* weights_src, float* dfeat, int64_t plane,
                             float* slots, int64_t slot_stride, int grid, int loss_l1, int min_waves, hipStream_t s) {
   // weights_src points at the MLP weights of block 0 (element n_table_params);
-  // the kernel adds each block's parameter offset.
+  // the kernel adds each block's parameter offset.  Feature offsets are 32-bit.
+  if ((int64_t)md.in_dim * plane >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
 #define X(WW, NN)                                                                                                   \
   if (md.width == WW && md.n_hidden == NN) {                                                                        \
     if (p == Prec::MIXED && min_waves >= 2)                                                                         \
@@ -585,6 +600,7 @@ hipError_t launch_mlp_infer(Prec p, const MlpDesc& md, const LevelDesc& ld, cons
                             const BlockRange* range, const BlockPlan* plan, const Tile* tiles, int n_tiles,
                             int direct_block, const void* feat, const void* weights_src, int64_t plane, float* out,
                             hipStream_t s) {
+  if ((int64_t)md.in_dim * plane >= ((int64_t)1 << 31)) return hipErrorInvalidValue;  // 32-bit feature offsets
 #define X(WW, NN)                                                                                                 \
   if (md.width == WW && md.n_hidden == NN) {                                                                      \
     if (p == Prec::MIXED)                                                                                         \
