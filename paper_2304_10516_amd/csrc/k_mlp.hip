@@ -283,24 +283,27 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
     // this wave's 64 samples of the tile: 4 groups of 16, passes of DWS samples;
     // the features and target of group k+1 are loaded while group k computes
     constexpr int NG = 4;
-    float xr[8], yr;
-    auto load_group = [&](int k, float (&x)[8], float& y) {
+    // raw features and target of a group, prefetched one group ahead (at the
+    // last group the first one is reloaded, unused); loads are unconditional (element 0
+    // stands in for a missing sample or feature) and values are converted and
+    // masked only where they are used, so that no wait follows the loads
+    FT xr[8];
+    float yr;
+    auto load_group = [&](int k, FT (&x)[8], float& y) {
       const int sl = wave * 64 + k * 16 + c;
       const bool ok = sl < tl.count;
-      const int64_t gi = base + sl;
-      const int gF = (int)gi * F;
+      const int gF = ok ? (int)(base + sl) * F : 0;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) x[i] = (ok && fo[i] >= 0) ? (float)feat[fo[i] + gF] : 0.0f;
-      y = ok ? target[gi] : 0.0f;
+      for (int i = 0; i < 8; ++i) x[i] = feat[fo[i] >= 0 ? fo[i] + gF : 0];
+      y = target[ok ? base + sl : 0];
     };
     load_group(0, xr, yr);
 #pragma unroll 1
     for (int kg = 0; kg < NG; ++kg) {
       const int q = kg % S::GP;
-      float xn[8], yn = 0.0f;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) xn[i] = 0.0f;
-      if (kg + 1 < NG) load_group(kg + 1, xn, yn);
+      FT xn[8];
+      float yn;
+      load_group(kg + 1 < NG ? kg + 1 : 0, xn, yn);
       {
         const int sl = wave * 64 + kg * 16 + c;  // sample within the tile
         const bool valid = sl < tl.count;
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
 #pragma unroll
           for (int j = 0; j < TR::VPL; ++j) {
             const int f = 8 * g + s * TR::VPL + j;
-            const float x = xr[s * TR::VPL + j];
+            const float x = (valid && fo[s * TR::VPL + j] >= 0) ? (float)xr[s * TR::VPL + j] : 0.0f;
             TR::put(xb[s], j, x);
             mySI[0][f * S::RS + scol] = (st_t)x;
           }
@@ -349,7 +352,7 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
         op += __shfl_xor(op, 16, 64);
         op += __shfl_xor(op, 32, 64);
         // ---- loss: L2, dL/do = 2 (o - y) / n_b; L1, dL/do = sign(o - y) / n_b
-        const float y = yr;
+        const float y = valid ? yr : 0.0f;
         const float r = op - y;
         const float sg = r > 0.0f ? inv_n : (r < 0.0f ? -inv_n : 0.0f);
         const float dO = valid ? (l1 ? sg : 2.0f * r * inv_n) : 0.0f;
@@ -488,7 +491,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpDesc md, int F, const Bloc
 #pragma unroll
       for (int j = 0; j < TR::VPL; ++j) {
         const int o = fo[s * TR::VPL + j];
-        TR::put(xb[s], j, (valid && o >= 0) ? (float)feat[o + (int)gi * F] : 0.0f);
+        const float v = (float)feat[(valid && o >= 0) ? o + (int)gi * F : 0];  // unconditional load
+        TR::put(xb[s], j, (valid && o >= 0) ? v : 0.0f);
       }
     f32x4 h[S::MT];
 #pragma unroll
