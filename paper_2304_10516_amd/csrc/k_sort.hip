@@ -59,18 +59,42 @@ __global__ __launch_bounds__(1024) void k_sort_scan(const int32_t* __restrict__ 
   const int g0 = group_range[2 * b], g1 = group_range[2 * b + 1];
   const int per = (g1 - g0 + 15) / 16;
   const int ra = g0 + r * per, rb = min(g1, ra + per);
+  // a row of up to PR groups keeps its counts in registers, loaded together
+  // (clamped indices, masked values) instead of one dependent load at a time
+  constexpr int PR = 16;
+  const bool regs = per <= PR && g1 > g0;  // uniform over the workgroup
+  uint32_t cv[PR];
   uint32_t sum = 0;
-  if (k < nbins)
+  if (regs) {
+    const int kk = min(k, nbins - 1);
+#pragma unroll
+    for (int i = 0; i < PR; ++i) {
+      const int gg = min(ra + i, g1 - 1);
+      const uint32_t v = counts[(int64_t)gg * nbins + kk];
+      cv[i] = (k < nbins && ra + i < rb) ? v : 0u;
+      sum += cv[i];
+    }
+  } else if (k < nbins) {
     for (int g = ra; g < rb; ++g) sum += counts[(int64_t)g * nbins + k];
+  }
   part[r][threadIdx.x % 64] = sum;
   __syncthreads();
   uint32_t base = 0;
   for (int q = 0; q < r; ++q) base += part[q][threadIdx.x % 64];
   if (k < nbins) {
-    for (int g = ra; g < rb; ++g) {
-      const uint32_t c = counts[(int64_t)g * nbins + k];
-      counts[(int64_t)g * nbins + k] = base;
-      base += c;
+    if (regs) {
+#pragma unroll
+      for (int i = 0; i < PR; ++i)
+        if (ra + i < rb) {
+          counts[(int64_t)(ra + i) * nbins + k] = base;
+          base += cv[i];
+        }
+    } else {
+      for (int g = ra; g < rb; ++g) {
+        const uint32_t c = counts[(int64_t)g * nbins + k];
+        counts[(int64_t)g * nbins + k] = base;
+        base += c;
+      }
     }
     if (r == 15) totals[b * kMaxBins + k] = base;  // the last row ends with the bin total
   }
@@ -141,25 +165,31 @@ __global__ __launch_bounds__(kSortGroup) void k_sort_place(const Tile* __restric
   const int n_uni = plan[gr.block].n_uni;
   const int g = bm.ghost;
   const int NX = bm.dims[0] + 2 * g, NY = bm.dims[1] + 2 * g, NZ = bm.dims[2] + 2 * g;
+  // the volume is global memory: the address-space cast lets the compiler use
+  // global (not flat) loads, which do not wait on the LDS counter
+  typedef const __attribute__((address_space(1))) float gfloat;
   for (int j = threadIdx.x; j < gr.count; j += blockDim.x) {
     float x, y, z;
     train_coord((uint32_t)(gr.start + j), step, (uint32_t)gr.block, n_uni, dist.sigma_sqrt2, seed, x, y, z);
-    const uint32_t dst = atomicAdd(&cursor[bin_of(x, y, z, B)], 1u);
-    const int64_t gi = base + dst;
-    coords[3 * gi + 0] = x;
-    coords[3 * gi + 1] = y;
-    coords[3 * gi + 2] = z;
+    // voxel loads first, so that they are in flight during the LDS atomic below
     int ix, iy, iz;
     float tx, ty, tz;
     cell_pos_s(x, bm.dims[0], g, NX, ix, tx);
     cell_pos_s(y, bm.dims[1], g, NY, iy, ty);
     cell_pos_s(z, bm.dims[2], g, NZ, iz, tz);
-    const float* v = bm.vol + ((int64_t)iz * NY + iy) * NX + ix;
+    gfloat* v = (gfloat*)(bm.vol + ((int64_t)iz * NY + iy) * NX + ix);
     const int64_t sy = NX, sz = (int64_t)NX * NY;
-    const float c00 = v[0] + tx * (v[1] - v[0]);
-    const float c10 = v[sy] + tx * (v[sy + 1] - v[sy]);
-    const float c01 = v[sz] + tx * (v[sz + 1] - v[sz]);
-    const float c11 = v[sz + sy] + tx * (v[sz + sy + 1] - v[sz + sy]);
+    const float v000 = v[0], v100 = v[1], v010 = v[sy], v110 = v[sy + 1];
+    const float v001 = v[sz], v101 = v[sz + 1], v011 = v[sz + sy], v111 = v[sz + sy + 1];
+    const uint32_t dst = atomicAdd(&cursor[bin_of(x, y, z, B)], 1u);
+    const int64_t gi = base + dst;
+    coords[3 * gi + 0] = x;
+    coords[3 * gi + 1] = y;
+    coords[3 * gi + 2] = z;
+    const float c00 = v000 + tx * (v100 - v000);
+    const float c10 = v010 + tx * (v110 - v010);
+    const float c01 = v001 + tx * (v101 - v001);
+    const float c11 = v011 + tx * (v111 - v011);
     const float c0 = c00 + ty * (c10 - c00);
     const float c1 = c01 + ty * (c11 - c01);
     target[gi] = (c0 + tz * (c1 - c0) - br.vmin) * br.inv_range;
