@@ -69,17 +69,34 @@ __device__ __forceinline__ void train_coord(uint32_t i, uint32_t step, uint32_t 
 }
 
 // ---------------------------------------------------------------------------
+// Round-to-nearest fp32 operations that the compiler may not contract into an
+// FMA with a neighbouring operation (each result is rounded on its own).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float fmul_nc(float a, float b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+__device__ __forceinline__ float fadd_nc(float a, float b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
+__device__ __forceinline__ float fsub_nc(float a, float b) {
+#pragma clang fp contract(off)
+  return a - b;
+}
+
+// ---------------------------------------------------------------------------
 // Grid position on a level of R vertices per axis.  x is clamped to [0,1];
 // p = x*(R-1) is a single round-to-nearest float multiply (never contracted
 // into an FMA), i0 = min(floor(p), R-2), t = p - i0 (exact).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void grid_pos(float x, float scale, int R, int& i0, float& t) {
   x = fminf(fmaxf(x, 0.0f), 1.0f);
-  const float p = __fmul_rn(x, scale);
+  const float p = fmul_nc(x, scale);
   int i = (int)floorf(p);
   i = min(i, R - 2);
   i0 = i;
-  t = __fsub_rn(p, (float)i);
+  t = fsub_nc(p, (float)i);
 }
 
 // Spatial hash of the multiresolution hash encoding: XOR of coordinate

@@ -20,7 +20,7 @@
 namespace dvnrk {
 
 __device__ __forceinline__ float dot3_rn(float ax, float ay, float az, float bx, float by, float bz) {
-  return __fadd_rn(__fadd_rn(__fmul_rn(ax, bx), __fmul_rn(ay, by)), __fmul_rn(az, bz));
+  return fadd_nc(fadd_nc(fmul_nc(ax, bx), fmul_nc(ay, by)), fmul_nc(az, bz));
 }
 
 __device__ __forceinline__ void normalize_rn(float* v) {
@@ -30,9 +30,9 @@ __device__ __forceinline__ void normalize_rn(float* v) {
 }
 
 __device__ __forceinline__ void cross_rn(const float* a, const float* b, float* c) {
-  c[0] = __fsub_rn(__fmul_rn(a[1], b[2]), __fmul_rn(a[2], b[1]));
-  c[1] = __fsub_rn(__fmul_rn(a[2], b[0]), __fmul_rn(a[0], b[2]));
-  c[2] = __fsub_rn(__fmul_rn(a[0], b[1]), __fmul_rn(a[1], b[0]));
+  c[0] = fsub_nc(fmul_nc(a[1], b[2]), fmul_nc(a[2], b[1]));
+  c[1] = fsub_nc(fmul_nc(a[2], b[0]), fmul_nc(a[0], b[2]));
+  c[2] = fsub_nc(fmul_nc(a[0], b[1]), fmul_nc(a[1], b[0]));
 }
 
 __global__ __launch_bounds__(256) void k_ray_init(RayCamera cam, int width, int height, float* __restrict__ dirs,
@@ -43,22 +43,22 @@ __global__ __launch_bounds__(256) void k_ray_init(RayCamera cam, int width, int 
   // camera frame: f = normalize(center - eye), r = normalize(f x up), u = r x f
   float fw[3], rt[3], uu[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) fw[a] = __fsub_rn(cam.center[a], cam.eye[a]);
+  for (int a = 0; a < 3; ++a) fw[a] = fsub_nc(cam.center[a], cam.eye[a]);
   normalize_rn(fw);
   cross_rn(fw, cam.up, rt);
   normalize_rn(rt);
   cross_rn(rt, fw, uu);
   const float aspect = __fdiv_rn((float)width, (float)height);
   const int i = p % width, j = p / width;
-  const float px = __fmul_rn(__fmul_rn(__fsub_rn(__fdiv_rn(__fmul_rn(2.0f, __fadd_rn((float)i, 0.5f)), (float)width),
+  const float px = fmul_nc(fmul_nc(fsub_nc(__fdiv_rn(fmul_nc(2.0f, fadd_nc((float)i, 0.5f)), (float)width),
                                                  1.0f),
                                        cam.tan_h),
                              aspect);
   const float py =
-      __fmul_rn(__fsub_rn(1.0f, __fdiv_rn(__fmul_rn(2.0f, __fadd_rn((float)j, 0.5f)), (float)height)), cam.tan_h);
+      fmul_nc(fsub_nc(1.0f, __fdiv_rn(fmul_nc(2.0f, fadd_nc((float)j, 0.5f)), (float)height)), cam.tan_h);
   float d[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) d[a] = __fadd_rn(__fadd_rn(fw[a], __fmul_rn(px, rt[a])), __fmul_rn(py, uu[a]));
+  for (int a = 0; a < 3; ++a) d[a] = fadd_nc(fadd_nc(fw[a], fmul_nc(px, rt[a])), fmul_nc(py, uu[a]));
   const float n = __fsqrt_rn(dot3_rn(d[0], d[1], d[2], d[0], d[1], d[2]));
 #pragma unroll
   for (int a = 0; a < 3; ++a) d[a] = __fdiv_rn(d[a], n);
@@ -67,8 +67,8 @@ __global__ __launch_bounds__(256) void k_ray_init(RayCamera cam, int width, int 
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float inv = __fdiv_rn(1.0f, d[a]);
-    const float ta = __fmul_rn(__fsub_rn(0.0f, cam.eye[a]), inv);
-    const float tb = __fmul_rn(__fsub_rn(1.0f, cam.eye[a]), inv);
+    const float ta = fmul_nc(fsub_nc(0.0f, cam.eye[a]), inv);
+    const float tb = fmul_nc(fsub_nc(1.0f, cam.eye[a]), inv);
     t0 = fmaxf(t0, fminf(ta, tb));
     t1 = fminf(t1, fmaxf(ta, tb));
   }
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_ray_init(RayCamera cam, int width, int 
 
 // Sample position t_k = t0 + (k + 1/2) dt; the sample exists iff t_k < t1.
 __device__ __forceinline__ float sample_t(float t0, int k, float dt) {
-  return __fadd_rn(t0, __fmul_rn(__fadd_rn((float)k, 0.5f), dt));
+  return fadd_nc(t0, fmul_nc(fadd_nc((float)k, 0.5f), dt));
 }
 
 __global__ __launch_bounds__(256) void k_ray_gen(RayCamera cam, const int32_t* __restrict__ active, int n_rays,
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void k_ray_gen(RayCamera cam, const int32_t* _
   const bool ok = tk < t01[2 * p + 1];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
-    coords[3 * q + a] = ok ? __fadd_rn(cam.eye[a], __fmul_rn(tk, dirs[3 * p + a])) : 0.5f;
+    coords[3 * q + a] = ok ? fadd_nc(cam.eye[a], fmul_nc(tk, dirs[3 * p + a])) : 0.5f;
 }
 
 // One lane per ray; values[jj * n_rays + r] is the de-normalized INR output of
