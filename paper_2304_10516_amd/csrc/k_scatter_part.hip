@@ -220,7 +220,7 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
                                                     PartAdam adam, int do_adam, uint8_t* __restrict__ ovf) {
   constexpr int RW = PartRec<F>::RW;
   constexpr bool PACK = F == 2;
-  constexpr int U = 16;  // records in flight per lane
+  constexpr int U = 8;  // records per lane and batch (two batches in flight)
   __shared__ unsigned long long acc[SF];
   __shared__ int sstart[kPartSub + 1];
   __shared__ float wmax[NT / 64];
@@ -270,14 +270,14 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
   const float scale = ldexpf(1.0f, K);
   const int kshift = K - 147;  // packed record: contribution i in units 2^-K is m_i 2^(ex - 147 + K)
   const uint32_t* r = recs + (pb[b].off[l] + (int64_t)s * pd.nsub * cap) * RW;
-  for (int j0 = 0; j0 < n; j0 += NT * U) {
-    // unconditional loads (lanes past the end re-read the last record and skip
-    // it below), so that all U loads are in flight together; record j of the
-    // bucket is record j - sstart[g] of sub-bucket g
-    uint32_t v[U][RW];
+  // a batch of U records per lane from j0 on: unconditional loads (lanes past
+  // the end re-read the last record and skip it when summing), so that all of
+  // them are in flight together; record j of the bucket is record
+  // j - sstart[g] of sub-bucket g
+  auto load_batch = [&](int j0, uint32_t(&v)[U][RW]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int j = min(j0 + u * NT + tid, n - 1);
+      const int j = max(0, min(j0 + u * NT + tid, n - 1));
       int g = 0;
 #pragma unroll
       for (int k = 1; k < kPartSub; ++k) g += j >= sstart[k] ? 1 : 0;
@@ -291,6 +291,38 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
         for (int k = 0; k < RW; ++k) v[u][k] = rr[k];
       }
     }
+  };
+  uint32_t vn[U][RW];
+  if (n > 0) load_batch(0, vn);
+  // while the first batch is in flight: this bucket's overflow flag and the
+  // Adam factors of this update (published by the barrier after the sums)
+  __shared__ int has_ovf;
+  __shared__ float hbc[3];
+  if (tid == 0) {
+    uint8_t* fl = ovf + (int64_t)b * pd.nq + q;
+    has_ovf = *fl;
+    *fl = 0;
+    if (do_adam) {
+      // this update's index t = step + 1 (the slot reduction advances the counter later)
+      const int64_t ti = adam.ctr->step + 1;
+      const double t = (double)ti;
+      hbc[0] = (float)(1.0 / (1.0 - pow((double)adam.b1, t)));
+      hbc[1] = (float)(1.0 / (1.0 - pow((double)adam.b2, t)));
+      double lr = (double)adam.lr0;
+      if (adam.decay_interval > 0 && ti > adam.decay_start)
+        lr *= pow(adam.decay_base, (double)(ti - adam.decay_start) / (double)adam.decay_interval);
+      hbc[2] = (float)lr;
+    }
+  }
+  // software pipeline: the next batch's loads are issued before this batch's
+  // LDS sums
+  for (int j0 = 0; j0 < n; j0 += NT * U) {
+    uint32_t v[U][RW];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < RW; ++k) v[u][k] = vn[u][k];
+    if (j0 + NT * U < n) load_batch(j0 + NT * U, vn);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (j0 + u * NT + tid < n) {
@@ -318,25 +350,6 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
   const int64_t el0 = meta[b].param_off + ((int64_t)ld.off[l] + e0) * F;  // first element of the slice
   float* g = grad + el0;
   // overflow records of this bucket went to the gradient by atomics
-  __shared__ int has_ovf;
-  __shared__ float hbc[3];
-  if (tid == 0) {
-    uint8_t* fl = ovf + (int64_t)b * pd.nq + q;
-    has_ovf = *fl;
-    *fl = 0;
-    if (do_adam) {
-      // this update's index t = step + 1 (the slot reduction advances the counter later)
-      const int64_t ti = adam.ctr->step + 1;
-      const double t = (double)ti;
-      hbc[0] = (float)(1.0 / (1.0 - pow((double)adam.b1, t)));
-      hbc[1] = (float)(1.0 / (1.0 - pow((double)adam.b2, t)));
-      double lr = (double)adam.lr0;
-      if (adam.decay_interval > 0 && ti > adam.decay_start)
-        lr *= pow(adam.decay_base, (double)(ti - adam.decay_start) / (double)adam.decay_interval);
-      hbc[2] = (float)lr;
-    }
-  }
-  __syncthreads();
   const bool rd_g = !do_adam || has_ovf;
   // read-add-write of the slice (or its Adam update): batches of unconditional
   // loads (clamped to the slice) so that a lane's loads overlap
