@@ -282,16 +282,18 @@ def sources_digest(kernel):
     return d.hexdigest()
 
 
-def measured_traffic(phase):
+def measured_traffic(phase, workload):
     """HBM bytes per launch of the phase's kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, or None when the summary does not cover it
-    or the kernel sources changed since the counters were taken."""
+    FETCH_SIZE / WRITE_SIZE summary, or None when the summary does not cover it,
+    was taken on another workload, or the kernel sources changed since the
+    counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             for line in f:
                 if line.startswith("traffic-record:"):
                     rec = json.loads(line.split(":", 1)[1])
                     if (rec["kernel"] == PHASE_KERNEL.get(phase) and rec["kernel"] in KERNEL_SOURCES
+                            and rec.get("workload") == workload
                             and rec["sources_sha256"] == sources_digest(rec["kernel"])):
                         return rec["read_bytes"] + rec["write_bytes"]
     except (OSError, ValueError, KeyError):
@@ -299,7 +301,7 @@ def measured_traffic(phase):
     return None
 
 
-def roofline_for(precision, res):
+def roofline_for(precision, res, workload):
     ph = res["phase_ms"]
     dom = max(ph, key=lambda k: ph[k])
     batch = res["batch"]
@@ -320,7 +322,7 @@ def roofline_for(precision, res):
             others[k] = round(b / (v * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
     return {"kernel": PHASE_KERNEL.get(dom, dom), "phase": dom, "bound": "hbm", "achieved": gbs,
             "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-            "traffic": measured_traffic(dom) if precision == "mixed" else None,
+            "traffic": measured_traffic(dom, workload) if precision == "mixed" else None,
             "algorithmic_bytes_per_launch": per_launch, "avg_launch_ms": ph[dom], "other_phases_frac": others}
 
 
@@ -425,7 +427,7 @@ def main():
         "decode_voxels_per_s": head["decode_voxels_per_s"],
         "psnr_db": head["psnr"],
         "phase_ms": head["phase_ms"],
-        "roofline": roofline_for(head_prec, head),
+        "roofline": roofline_for(head_prec, head, args.workload),
     }
     if head.get("render"):
         out["render"] = head["render"]
