@@ -1,0 +1,59 @@
+"""Host logic of bench.py: the algorithmic byte model of the slice pass, the
+roofline fraction, the workload- and source-scoped HBM traffic records, and
+the single-GPU guard.  No GPU is used."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def _res(batch=1 << 18):
+    # the 256^3 workload's plan: levels 0-5 privatized, 6-15 partitioned
+    ent = [min(int(16 * (16.0 ** (1 / 15)) ** l + 1e-6) ** 3, 1 << 19) for l in range(16)]
+    return {"batch": batch, "priv_levels": 6, "part_levels": 6, "level_entries": ent, "n_blocks": 1,
+            "n_params": sum(ent) * 2 + 6208, "phase_ms": {"part_accum": 0.1, "part_bucket": 0.05, "mlp": 0.06}}
+
+
+def test_slice_pass_bytes_and_fraction():
+    """10 partitioned levels x 8 records of 8 B per sample, plus 26 B of Adam
+    traffic per partitioned table parameter; achieved = bytes / launch time."""
+    res = _res()
+    npar = sum(res["level_entries"][6:]) * 2
+    assert bench.part_params(res) == npar
+    want = 10 * 8 * 8 * (1 << 18) + 26 * npar
+    assert bench.phase_bytes("mixed", "part_accum", res) == want
+    r = bench.roofline_for("mixed", res, "c9")
+    assert r["kernel"] == "k_part_accum" and r["bound"] == "hbm" and r["traffic"] is None
+    assert r["achieved"] == pytest.approx(want / 1e-4 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
+
+
+def test_traffic_record_scoped_to_workload_and_sources(tmp_path, monkeypatch):
+    dig = bench.sources_digest("k_part_accum")
+    rec = {"kernel": "k_part_accum", "workload": "c2", "read_bytes": 3, "write_bytes": 4, "sources_sha256": dig}
+    stale = dict(rec, kernel="k_part_bucket", sources_sha256="0" * 64)
+    f = tmp_path / "counters.md"
+    f.write_text("# counters\n\ntraffic-record: " + json.dumps(rec) + "\ntraffic-record: " + json.dumps(stale) + "\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic("part_accum", "c2") == 7
+    assert bench.measured_traffic("part_accum", "c3") is None  # taken on another workload
+    assert bench.measured_traffic("part_bucket", "c2") is None  # sources changed since
+    assert bench.measured_traffic("mlp", "c2") is None  # no record
+
+
+def test_committed_traffic_records_name_their_workload():
+    with open(bench.TRAFFIC_FILE) as fh:
+        recs = [json.loads(l.split(":", 1)[1]) for l in fh if l.startswith("traffic-record:")]
+    assert recs and all(r.get("workload") == "c2" and r["kernel"] in bench.KERNEL_SOURCES for r in recs)
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2 and "one GPU" in p.stderr and p.stdout == ""
