@@ -282,13 +282,15 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
 #pragma unroll
       for (int k = 1; k < kPartSub; ++k) g += j >= sstart[k] ? 1 : 0;
       const uint32_t* rr = r + ((int64_t)g * cap + (j - sstart[g])) * RW;
+      // records are read once: non-temporal loads keep them from displacing
+      // the volume and table lines the next kernels read from the caches
       if constexpr (PACK) {
-        const uint2 t2 = *reinterpret_cast<const uint2*>(rr);
-        v[u][0] = t2.x;
-        v[u][1] = t2.y;
+        const uint64_t t64 = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(rr));
+        v[u][0] = (uint32_t)t64;
+        v[u][1] = (uint32_t)(t64 >> 32);
       } else {
 #pragma unroll
-        for (int k = 0; k < RW; ++k) v[u][k] = rr[k];
+        for (int k = 0; k < RW; ++k) v[u][k] = __builtin_nontemporal_load(rr + k);
       }
     }
   };
