@@ -304,6 +304,64 @@ def test_sorted_sampling_gradient_parity_fine_levels(precision, classes, waves, 
     assert rel2(gg[nt:], g[nt:]) <= 3e-2, "weight gradient"
 
 
+# (features, precision, ordered sampling, scatter_part, first partitioned level expected)
+WIDTH_CASES = [(1, "fp32", 1, 0, 3), (4, "fp32", 1, 0, 3), (8, "fp32", 1, 0, 3), (4, "fp32", 0, 0, 3),
+               (8, "fp32", 1, -1, 4), (1, "mixed", 1, 0, 3), (4, "mixed", 1, 0, 3), (8, "mixed", 1, 0, 3)]
+
+
+@pytest.mark.parametrize("F,precision,sort,part,lf", WIDTH_CASES)
+def test_feature_width_gradient_parity(F, precision, sort, part, lf):
+    """Feature widths other than 2 (L F <= 32: 8 levels of 1 or 4 features, 4
+    levels of 8), base 16, scale 1.5, T = 2^17: levels 0-2 dense, 3 and up
+    hashed with 2^17 entries, so with scatter_part 0 they take the
+    destination-partitioned backward (unpacked (1 + F)-word records for
+    F != 2), the coarse ones the bin-privatized or plain scatter.  One step of
+    8192 samples against the oracle's float64 gradient."""
+    L = 4 if F == 8 else 8
+    cfg = (o.Encoding(L, F, 17, 16, 1.5), o.MLP(2, 32))
+    say(f"feature width {F} ({L} levels) {precision}: ordered {sort}, partitioned from level {part}")
+    vol = gaussian_sum_field(64, seed=5)
+    lay = o.layout(*cfg)
+    assert [lv.E for lv in lay.levels][2:4] == [36 ** 3, 1 << 17]
+    p = init_param_draws(lay.n_table_params, lay.mlp_shapes, seed=6).astype(np.float64)
+    p[:lay.n_table_params] *= 1e3
+    model = make(cfg, [((64, 64, 64), 0)], precision=precision, max_batch=1 << 14, seed=17)
+    model.bind_volumes([dev(vol)])
+    model.load_params([p])
+    model.set_option("spatial_sort", sort)
+    model.set_option("priv_levels", -1)
+    model.set_option("scatter_part", part)
+    model.set_option("apply_update", 0)
+    model.set_option("use_graph", 0)
+    n = 8192
+    loss = model.train(1, n, want_loss=True)
+    torch.cuda.synchronize()
+    assert model.partitioned_levels() == (lf if part >= 0 else L)
+    nt = lay.n_table_params
+    if precision == "fp32":
+        pref = model.block_params(0).cpu().numpy().astype(np.float64)
+    else:
+        w = torch.tensor(p[nt:]).to(torch.bfloat16).to(torch.float64).numpy()
+        pref = np.concatenate([p[:nt].astype(np.float16).astype(np.float64), w])
+    x = o.training_coords(17, 0, 0, n)
+    Lo, g, _ = o.loss_and_grad(lay, pref, x, o.normalized_targets(vol, (64, 64, 64), 0, x))
+    gg = model.block_grads(0).cpu().numpy()
+    spans = [(lv.off * F, (lv.off + lv.E) * F) for lv in lay.levels]
+    if precision == "fp32":
+        assert abs(loss[0, 0].item() - Lo) <= 1e-5 * Lo
+        for l, (a, b_) in enumerate(spans):
+            assert normwise(gg[a:b_], g[a:b_]) <= 1e-5, f"level {l} table gradient"
+        assert normwise(gg[nt:], g[nt:]) <= 1e-5, "weight gradient"
+        return
+    # mixed: the bars of the 16-level mixed case (bf16 MLP inputs flip ReLU units)
+    assert abs(loss[0, 0].item() - Lo) <= 1e-2 * Lo
+    rel2 = lambda a, b: float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+    cos = lambda a, b: float(np.dot(np.asarray(a, np.float64), b) / (np.linalg.norm(a) * np.linalg.norm(b)))
+    for l, (a, b_) in enumerate(spans):
+        assert rel2(gg[a:b_], g[a:b_]) <= 1e-1 and cos(gg[a:b_], g[a:b_]) >= 0.995, f"level {l} table gradient"
+    assert rel2(gg[nt:], g[nt:]) <= 3e-2, "weight gradient"
+
+
 @pytest.mark.parametrize("decay", [False, True])
 def test_adam_update_parity_c1(decay):
     say(f"adam update c1 fp32, learning-rate decay {decay}")
