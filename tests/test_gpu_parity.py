@@ -362,6 +362,35 @@ def test_feature_width_gradient_parity(F, precision, sort, part, lf):
     assert rel2(gg[nt:], g[nt:]) <= 3e-2, "weight gradient"
 
 
+def test_phase_times_cover_the_step():
+    """dvnr_phase_times: with profile_phases on, every phase of the 16-level
+    step (levels 9-15 partitioned) is timed, the sums cover no more than the
+    steps' elapsed device time, and a second call finds the sums reset."""
+    say("per-phase device times")
+    vol = gaussian_sum_field(64, seed=3)
+    model = make(C2, [((64, 64, 64), 0)], precision="mixed", max_batch=1 << 14, seed=5)
+    model.bind_volumes([dev(vol)])
+    model.init_params(1)
+    model.set_option("scatter_part", 9)
+    model.train(3, 1 << 14)
+    model.set_option("profile_phases", 1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    model.train(10, 1 << 14)
+    e1.record()
+    torch.cuda.synchronize()
+    ph, n = model.phase_times()
+    assert n == 10 and list(ph) == list(model.PHASES)
+    assert model.partitioned_levels() == 9
+    assert all(v >= 0.0 for v in ph.values())
+    for k in ("sample", "encode", "mlp", "scatter_priv", "part_bucket", "part_accum", "reduce", "adam"):
+        assert ph[k] > 0.0, k
+    assert sum(ph.values()) <= e0.elapsed_time(e1) * 1.05
+    ph2, n2 = model.phase_times()
+    assert n2 == 0 and all(v == 0.0 for v in ph2.values())
+
+
 @pytest.mark.parametrize("decay", [False, True])
 def test_adam_update_parity_c1(decay):
     say(f"adam update c1 fp32, learning-rate decay {decay}")
