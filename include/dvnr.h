@@ -408,7 +408,7 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *  "scatter_part"    n   : destination-partitioned encoding backward of the
  *                          levels [n, n_levels) (-1, the default: for mixed
  *                          precision, the longest suffix of levels with at
- *                          least 2^16 entries that get at least one
+ *                          least 2^15 entries that get at least one
  *                          contribution per table entry per step; none for
  *                          fp32; >= n_levels: none).  Each step sorts the levels'
  *                          (sample, corner) contributions into per-slice
@@ -416,7 +416,7 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *                          each bucket in LDS, instead of one global atomic per
  *                          contribution.  Levels with more than 256 slices stay
  *                          on the atomic paths, and so do levels with fewer
- *                          than 2^16 entries (the workspace holds buckets
+ *                          than 2^15 entries (the workspace holds buckets
  *                          for the others: about 40 (1 + F) bytes per
  *                          sample of max_batch and level).
  *  "part_slice"      n   : fp32 accumulators per slice: 4096, 8192 (default)

@@ -128,7 +128,7 @@ hipError_t launch_scatter(Prec gp, const LevelDesc& ld, int l0, int l1, const Bl
 // bucket q = qbase[l] + s of that block (nq buckets per block).
 constexpr int kPartSliceMax = 16384;  // accumulators of one slice (64 KB of LDS)
 constexpr int kPartMaxSlices = 256;   // slices of one level
-constexpr int kPartMinEntries = 1 << 16;  // smallest table that may be partitioned
+constexpr int kPartMinEntries = 1 << 15;  // smallest table that may be partitioned
 constexpr int kPartSub = 16;          // sub-buckets per bucket (tile t appends to sub-bucket t % kPartSub)
 constexpr int kPartSliceRecords = 16384;  // records per slice the slice sizes aim at
 struct PartDesc {

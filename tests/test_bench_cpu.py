@@ -14,7 +14,7 @@ import bench  # noqa: E402
 
 
 def _res(batch=1 << 18):
-    # the 256^3 workload's plan: levels 0-5 privatized, 6-15 partitioned
+    # a plan of the 256^3 workload's encoding: levels 0-5 privatized, 6-15 partitioned
     ent = [min(int(16 * (16.0 ** (1 / 15)) ** l + 1e-6) ** 3, 1 << 19) for l in range(16)]
     return {"batch": batch, "priv_levels": 6, "part_levels": 6, "level_entries": ent, "n_blocks": 1,
             "n_params": sum(ent) * 2 + 6208, "phase_ms": {"part_accum": 0.1, "part_bucket": 0.05, "mlp": 0.06}}

@@ -70,7 +70,7 @@ def test_full_size_step_gradient(field, precision):
     torch.cuda.synchronize()
     lf = model.partitioned_levels()
     say(f"partitioned levels from {lf}; plan {model.plan_info()}")
-    assert lf == (9 if precision == "fp32" else 6)  # mixed default: every level with 2^16 entries or more
+    assert lf == (9 if precision == "fp32" else 4)  # mixed default: every level with 2^15 entries or more
     if precision == "fp32":
         pref = model.block_params(0).cpu().numpy().astype(np.float64)
     else:

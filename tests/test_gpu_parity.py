@@ -216,13 +216,13 @@ def test_sorted_sampling_gradient_parity(precision, priv, classes, binned):
 
 
 # (precision, LDS classes, MLP waves, concurrent, ordered, scatter_part, bucket cap, slice floats,
-#  first partitioned level expected: the first with 2^16 entries is level 6)
+#  first partitioned level expected: the first with 2^15 entries is level 4)
 FINE_CASES = [("fp32", 0, 1, 0, 1, -1, 0, 8192, 16), ("fp32", 1, 1, 0, 1, -1, 0, 8192, 16),
               ("fp32", 0, 1, 1, 1, -1, 0, 8192, 16), ("mixed", 0, 1, 0, 1, -1, 0, 8192, 16),
               ("mixed", 0, 2, 0, 1, -1, 0, 8192, 16), ("mixed", 1, 1, 1, 1, -1, 0, 8192, 16),
               # destination-partitioned levels: fine only, every eligible one (ordered and not),
               # tiny buckets (most records overflow into direct atomics), other slice sizes
-              ("fp32", 0, 1, 0, 1, 9, 0, 8192, 9), ("fp32", 0, 1, 0, 1, 0, 0, 8192, 6),
+              ("fp32", 0, 1, 0, 1, 9, 0, 8192, 9), ("fp32", 0, 1, 0, 1, 0, 0, 8192, 4),
               ("fp32", 0, 1, 0, 0, 6, 0, 16384, 6), ("fp32", 0, 1, 0, 1, 9, 8, 8192, 9),
               ("fp32", 0, 1, 0, 0, 12, 0, 4096, 12), ("mixed", 0, 1, 0, 1, 9, 0, 8192, 9),
               # 16384 samples, 64 slices per level: 4 sub-buckets per bucket
@@ -305,15 +305,17 @@ def test_sorted_sampling_gradient_parity_fine_levels(precision, classes, waves, 
 
 
 # (features, precision, ordered sampling, scatter_part, first partitioned level expected)
-WIDTH_CASES = [(1, "fp32", 1, 0, 3), (4, "fp32", 1, 0, 3), (8, "fp32", 1, 0, 3), (4, "fp32", 0, 0, 3),
-               (8, "fp32", 1, -1, 4), (1, "mixed", 1, 0, 3), (4, "mixed", 1, 0, 3), (8, "mixed", 1, 0, 3)]
+WIDTH_CASES = [(1, "fp32", 1, 0, 2), (4, "fp32", 1, 0, 2), (8, "fp32", 1, 0, 2), (4, "fp32", 0, 0, 2),
+               (8, "fp32", 1, -1, 4), (1, "mixed", 1, 0, 2), (4, "mixed", 1, 0, 2), (8, "mixed", 1, 0, 2),
+               (4, "fp32", 1, 3, 3)]
 
 
 @pytest.mark.parametrize("F,precision,sort,part,lf", WIDTH_CASES)
 def test_feature_width_gradient_parity(F, precision, sort, part, lf):
     """Feature widths other than 2 (L F <= 32: 8 levels of 1 or 4 features, 4
-    levels of 8), base 16, scale 1.5, T = 2^17: levels 0-2 dense, 3 and up
-    hashed with 2^17 entries, so with scatter_part 0 they take the
+    levels of 8), base 16, scale 1.5, T = 2^17: levels 0-2 dense (level 2:
+    36^3 entries, the first with at least 2^15), 3 and up hashed with 2^17
+    entries, so with scatter_part 0 levels 2 and up take the
     destination-partitioned backward (unpacked (1 + F)-word records for
     F != 2), the coarse ones the bin-privatized or plain scatter.  One step of
     8192 samples against the oracle's float64 gradient."""
