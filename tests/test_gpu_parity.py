@@ -364,6 +364,50 @@ def test_feature_width_gradient_parity(F, precision, sort, part, lf):
     assert rel2(gg[nt:], g[nt:]) <= 3e-2, "weight gradient"
 
 
+@pytest.mark.parametrize("empty", [0, 1])
+def test_block_without_samples_partitioned_c2(empty):
+    """Two c2 blocks, levels 9-15 partitioned with Adam in the slice pass, one
+    step on explicit coordinates where one block draws no sample: that block's
+    parameters stay bit-identical (neither pass nor the Adam kernel touches
+    it), the other takes the oracle's Adam step (bars of the fused-Adam test),
+    and every gradient is left at zero."""
+    say(f"c2, two blocks, block {empty} without samples, partitioned levels with fused Adam")
+    from paper_2304_10516_amd.dvnr import DVNR, EncodingCfg, MlpCfg, OptimCfg
+    enc, mlp = C2
+    lay = o.layout(*C2)
+    vols = [gaussian_sum_field(64, seed=3), gaussian_sum_field(64, seed=4)]
+    ps = []
+    for seed in (2, 8):
+        q = init_param_draws(lay.n_table_params, lay.mlp_shapes, seed=seed).astype(np.float64)
+        q[:lay.n_table_params] *= 1e3
+        ps.append(q)
+    model = DVNR(EncodingCfg(enc.n_levels, enc.n_features, enc.log2_table_size, enc.base_resolution,
+                             enc.per_level_scale, enc.finest_resolution), MlpCfg(mlp.n_hidden_layers, mlp.width),
+                 [((64, 64, 64), 0), ((64, 64, 64), 0)], OptimCfg(lr=1e-2), precision="fp32", max_batch=1 << 14,
+                 seed=91)
+    model.bind_volumes([dev(v) for v in vols])
+    model.load_params(ps)
+    model.set_option("scatter_part", 9)
+    before = [model.block_params(b).clone() for b in range(2)]
+    full = 1 - empty
+    x = o.training_coords(91, full, 0, 8192)
+    counts = [0, 0]
+    counts[full] = 8192
+    model.train_step_coords(dev(x), counts)
+    torch.cuda.synchronize()
+    assert model.partitioned_levels() == 9
+    assert torch.equal(model.block_params(empty), before[empty])
+    pr = before[full].cpu().numpy().astype(np.float64)
+    st, opt = o.adam_init(lay.n_params), o.Optim(lr=1e-2)
+    _, g, _ = o.loss_and_grad(lay, pr, x, o.normalized_targets(vols[full], (64, 64, 64), 0, x))
+    small = np.abs(g) < 1e-5 * np.abs(g).max()
+    ref = o.adam(pr, g, st, opt)
+    d = np.abs(model.block_params(full).cpu().numpy().astype(np.float64) - ref)
+    assert np.max(d[~small]) <= 1e-4 * opt.lr + 1e-7
+    assert np.mean(d[small] <= opt.lr * 1.01) == 1.0
+    assert float(model.grads.abs().max()) == 0.0
+
+
 def test_phase_times_cover_the_step():
     """dvnr_phase_times: with profile_phases on, every phase of the 16-level
     step (levels 9-15 partitioned) is timed, the sums cover no more than the
