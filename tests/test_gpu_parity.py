@@ -226,7 +226,9 @@ FINE_CASES = [("fp32", 0, 1, 0, 1, -1, 0, 8192, 16), ("fp32", 1, 1, 0, 1, -1, 0,
               ("fp32", 0, 1, 0, 0, 6, 0, 16384, 6), ("fp32", 0, 1, 0, 1, 9, 8, 8192, 9),
               ("fp32", 0, 1, 0, 0, 12, 0, 4096, 12), ("mixed", 0, 1, 0, 1, 9, 0, 8192, 9),
               # 16384 samples, 64 slices per level: 4 sub-buckets per bucket
-              ("fp32", 0, 1, 0, 1, 9, 0, 16384, 9, 16384)]
+              ("fp32", 0, 1, 0, 1, 9, 0, 16384, 9, 16384),
+              # ragged sample counts: a partial last tile and uneven bins
+              ("fp32", 0, 1, 0, 1, 9, 0, 8192, 9, 10000), ("mixed", 0, 1, 0, 1, 4, 0, 8192, 4, 9999)]
 FINE_CASES = [c if len(c) == 10 else c + (8192,) for c in FINE_CASES]
 
 
