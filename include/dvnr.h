@@ -395,9 +395,11 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *  "encode_binned"   0/1 : with ordered sampling, interpolate the coarse levels
  *                          (bin box within 16 KB and at most half the bin's
  *                          direct gathers) from LDS-staged boxes (default 1)
- *  "priv_classes"    0/1 : launch the privatized levels in three LDS-size
+ *  "priv_classes"  -1/0/1 : launch the privatized levels in three LDS-size
  *                          classes (small boxes, large boxes, direct) instead
- *                          of one launch (default 0)
+ *                          of one launch (-1, the default: by class when the
+ *                          destination-partitioned backward takes the fine
+ *                          levels, one launch otherwise)
  *  "scatter_strided" 0/1 : direct backward over ordered samples takes each
  *                          tile's samples strided across the block (default 1)
  *  "decode_fused"    0/1 : decode with the fused brick kernel (default 1)

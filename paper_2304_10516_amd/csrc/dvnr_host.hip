@@ -85,7 +85,7 @@ struct dvnr {
   int priv_levels = -1;  // -1: chosen per plan
   int sort_B = 0, priv_L = 0, n_groups = 0;
   int priv_small = 0, priv_direct = 0;  // LDS classes: small [0, priv_small), large up to priv_direct, then direct
-  int priv_classes = 0;                 // launch the privatized levels by LDS class (else one launch)
+  int priv_classes = -1;  // launch the privatized levels by LDS class (0: one launch; -1: when partitioned)
   int encode_binned = 1;                // ordered samples: LDS-staged encoding of the levels whose box fits
   int enc_binned = 0;                   // levels [0, enc_binned) of the current plan
   std::vector<Tile> hgroups;
@@ -876,10 +876,14 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   {
     // priv_classes 0: one launch (large class) for all privatized levels, so that
     // the LDS-bound coarse and the atomic-bound fine levels overlap on the chip;
-    // scatter_concurrent: the direct-class levels on the second stream instead
+    // -1 (default): by class when the partitioned backward has taken the fine
+    // levels (only coarse ones are left, and the small-box class runs at higher
+    // occupancy beside the partitioned passes); scatter_concurrent: the
+    // direct-class levels on the second stream instead
     const bool conc = h->scatter_concurrent != 0;
-    const int a = h->priv_classes ? std::min(h->priv_small, lp) : 0;
-    const int c = h->priv_classes || conc ? std::min(std::max(h->priv_direct, a), lp) : lp;
+    const bool classes = h->priv_classes > 0 || (h->priv_classes < 0 && lf < h->enc.n_levels);
+    const int a = classes ? std::min(h->priv_small, lp) : 0;
+    const int c = classes || conc ? std::min(std::max(h->priv_direct, a), lp) : lp;
     if (conc && c < lp) {
       HIPCHK(ensure_side(h));
       HIPCHK(hipEventRecord(h->ev_fork, s));
@@ -1634,7 +1638,7 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
   } else if (n == "encode_binned") {
     h->encode_binned = value ? 1 : 0;
   } else if (n == "priv_classes") {
-    h->priv_classes = value ? 1 : 0;
+    h->priv_classes = value < 0 ? -1 : (value ? 1 : 0);
   } else if (n == "scatter_strided") {
     h->scatter_strided = value ? 1 : 0;
   } else if (n == "xcd_map") {

@@ -186,5 +186,7 @@ def test_partitioned_backward_options():
         assert lib.dvnr_set_option(h, b"scatter_part", 9) == 0
         assert lib.dvnr_set_option(h, b"scatter_part", -1) == 0
         assert lib.dvnr_set_option(h, b"part_capacity", 8) == 0
+        for v in (-1, 0, 1):
+            assert lib.dvnr_set_option(h, b"priv_classes", v) == 0
     finally:
         lib.dvnr_destroy(h)
