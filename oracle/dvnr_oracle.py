@@ -19,11 +19,11 @@ What it computes, per partition block (one implicit neural representation,
 * uniform sampling with a counter-based generator (Philox4x32-10, Salmon et
   al., SC'11) and trilinear ground-truth fetch in cell-centered convention with
   per-block min/max normalization (`training_coords`, `sample_volume`);
-* boundary-centered half-normal samples (Sec. III-E, Eq. (4)) mixed into a
+* boundary-centered half-normal samples (Sec. III-C, Eq. (2)) mixed into a
   step's batch (`boundary_coords`, `step_coords`);
 * the step budget and the moving-average early termination (Sec. III-B)
   (`max_train_steps`, `should_stop`, `train_until`);
-* the L2 or L1 loss (Sec. III-E, Eq. (5)), the encoding backward
+* the L2 or L1 loss (Sec. III-C, Eq. (3)), the encoding backward
   (scatter-add), Adam with L2 weight decay (Sec. III-F) (`train_step`, `adam`);
 * decoding at voxel centers and PSNR over owned voxels (`decode`, `psnr`);
 * the sliding-window cache needs no oracle of its own (a snapshot must decode
@@ -337,13 +337,13 @@ BOUND_TAG = 0x44564E42  # fourth counter word of boundary-sample draws
 
 def boundary_count(n: int, frac: float) -> int:
     """Boundary samples among a block's n samples of one step: lambda * n
-    rounded half up (Sec. III-E draws (1 - lambda) N uniform and lambda N
+    rounded half up (Sec. III-C draws (1 - lambda) N uniform and lambda N
     boundary samples, so that the step always trains on N samples)."""
     return int(np.floor(frac * n + 0.5))
 
 
 def boundary_coords(seed: int, block: int, step: int, n: int, first: int, sigma: float) -> np.ndarray:
-    """Boundary-centered training coordinates (Sec. III-E, Eq. (4)).
+    """Boundary-centered training coordinates (Sec. III-C, Eq. (2)).
 
     Reading of the density: an equal-weight mixture over the six faces of the
     unit cube; a sample picks a face, sits at a half-normal distance
@@ -491,7 +491,7 @@ def loss_and_grad(lay: Layout, params: np.ndarray, x: np.ndarray, target: np.nda
     """Loss of one block, mean over its samples, and its gradient.
 
     loss "l2": L = (1/n) sum (o - y)^2, dL/do = 2 (o - y) / n.
-    loss "l1" (the unweighted L1 of Sec. III-E): L = (1/n) sum abs(o - y),
+    loss "l1" (the unweighted L1 of Sec. III-C, Eq. (3)): L = (1/n) sum abs(o - y),
     dL/do = sign(o - y) / n with sign(0) = 0.
     Returns (L, grad vector, o).
     """

@@ -1,4 +1,4 @@
-"""GPU parity of the boundary loss (Sec. III-E) against the float64 oracle.
+"""GPU parity of the boundary loss (Sec. III-C, Eqs. (2)-(3)) against the float64 oracle.
 
 * boundary-centered training samples: uniform prefix bit-exact, boundary
   coordinates within 1e-6 (the half-normal quantile is evaluated in float32 on

@@ -14,8 +14,13 @@ samples per step.  The float64 oracle computes the whole step at this size
   switched sample moves all its 128 corner entries by a macroscopic amount
   (the small-size tests cover inactive units);
 * mixed precision with its default options (those of the benchmark: levels
-  6..15 partitioned): the bars of the bf16 MLP (per-level 2-norm 1e-1 with
-  cosine >= 0.995, weights 3e-2).
+  4..15 partitioned), positive parameters as above: the bars of the bf16
+  tolerance reading -- per level within 0.1 x the level's intrinsic bf16
+  error of the rounding model (tests/precision_model.py) and within 1.25 x of
+  the exact gradient; the loss within 1e-5 of the model's.  (With random
+  signs, a few hundred of the 2^18 x 128 hidden units sit within float32
+  rounding of the kink; the bars allow each to switch, which at this size
+  adds up to several percent; the smaller tests cover that case.)
 """
 import sys
 
@@ -25,6 +30,7 @@ import torch
 
 from fixtures import init_param_draws, kolmogorov_field
 from oracle import dvnr_oracle as o
+from tests import precision_model as pm
 
 pytestmark = pytest.mark.gpu
 
@@ -57,8 +63,7 @@ def test_full_size_step_gradient(field, precision):
     lay = o.layout(*C2)
     p = init_param_draws(lay.n_table_params, lay.mlp_shapes, seed=2).astype(np.float64)
     p[:lay.n_table_params] *= 1e3
-    if precision == "fp32":
-        p = np.abs(p)
+    p = np.abs(p)  # every ReLU unit active: no unit near its kink (see above)
     model = _model(precision)
     model.bind_volumes([torch.as_tensor(field, device="cuda")])
     model.load_params([p])
@@ -71,34 +76,29 @@ def test_full_size_step_gradient(field, precision):
     lf = model.partitioned_levels()
     say(f"partitioned levels from {lf}; plan {model.plan_info()}")
     assert lf == (9 if precision == "fp32" else 4)  # mixed default: every level with 2^15 entries or more
-    if precision == "fp32":
-        pref = model.block_params(0).cpu().numpy().astype(np.float64)
-    else:
-        nt = lay.n_table_params
-        w = torch.tensor(p[nt:]).to(torch.bfloat16).to(torch.float64).numpy()
-        pref = np.concatenate([p[:nt].astype(np.float16).astype(np.float64), w])
     x = o.training_coords(3, 0, 0, N)
     tgt = o.normalized_targets(field, (256, 256, 256), 0, x)
-    L, g, _ = o.loss_and_grad(lay, pref, x, tgt)
     gg = model.block_grads(0).cpu().numpy().astype(np.float64)
     nt = lay.n_table_params
+    if precision == "mixed":
+        r = pm.check_mixed_gradient(gg, lay, pm.working_copy(lay, p), x, tgt)
+        say("following the rounding model per level (x intrinsic): " +
+            " ".join(f"{f / e:.3f}" for f, e in zip(r["follow"], r["intrinsic"])) +
+            "; intrinsic " + " ".join(f"{e:.3f}" for e in r["intrinsic"]) +
+            f"; weights {r['weights_follow']:.2e} (intrinsic {r['weights_intrinsic']:.2e})")
+        rel = abs(loss[0, 0].item() - r["loss_model"]) / r["loss_model"]
+        say(f"loss {loss[0, 0].item():.6g} vs model {r['loss_model']:.6g} (rel {rel:.2e})")
+        assert rel <= 1e-5
+        return
+    pref = model.block_params(0).cpu().numpy().astype(np.float64)
+    L, g, _ = o.loss_and_grad(lay, pref, x, tgt)
     rel = abs(loss[0, 0].item() - L) / L
     say(f"loss {loss[0, 0].item():.6g} vs oracle {L:.6g} (rel {rel:.2e})")
-    if precision == "fp32":
-        assert rel <= 1e-5
-        errs = []
-        for lvl in lay.levels:
-            a, b = lvl.off * 2, (lvl.off + lvl.E) * 2
-            errs.append(float(np.max(np.abs(gg[a:b] - g[a:b])) / np.max(np.abs(g[a:b]))))
-        say("per-level normwise error: " + " ".join(f"{e:.1e}" for e in errs))
-        assert max(errs) <= 1e-5
-        assert float(np.max(np.abs(gg[nt:] - g[nt:])) / np.max(np.abs(g[nt:]))) <= 1e-5
-        return
-    assert rel <= 1e-2
-    rel2 = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
-    cos = lambda a, b: float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)))
-    errs = [rel2(gg[l.off * 2:(l.off + l.E) * 2], g[l.off * 2:(l.off + l.E) * 2]) for l in lay.levels]
-    coss = [cos(gg[l.off * 2:(l.off + l.E) * 2], g[l.off * 2:(l.off + l.E) * 2]) for l in lay.levels]
-    say("per-level 2-norm error: " + " ".join(f"{e:.3f}" for e in errs) + f"; weights {rel2(gg[nt:], g[nt:]):.2e}")
-    assert max(errs) <= 1e-1 and min(coss) >= 0.995
-    assert rel2(gg[nt:], g[nt:]) <= 3e-2
+    assert rel <= 1e-5
+    errs = []
+    for lvl in lay.levels:
+        a, b = lvl.off * 2, (lvl.off + lvl.E) * 2
+        errs.append(float(np.max(np.abs(gg[a:b] - g[a:b])) / np.max(np.abs(g[a:b]))))
+    say("per-level normwise error: " + " ".join(f"{e:.1e}" for e in errs))
+    assert max(errs) <= 1e-5
+    assert float(np.max(np.abs(gg[nt:] - g[nt:])) / np.max(np.abs(g[nt:]))) <= 1e-5

@@ -1,4 +1,4 @@
-"""Pins of the oracle's boundary-centered sampler and L1 loss (Sec. III-E).
+"""Pins of the oracle's boundary-centered sampler and L1 loss (Sec. III-C, Eqs. (2)-(3)).
 
 * the distance of a boundary sample to the nearest face against its closed-form
   distribution (half-normal distance to the chosen face, two uniform

@@ -202,6 +202,29 @@ def test_decode_coordinates_are_voxel_centers():
     np.testing.assert_array_equal(x[[0, 8, 16], 2], np.float32([1 / 6, 0.5, 5 / 6]))
 
 
+@pytest.mark.parametrize("vmin,vmax", [(-2.5, 4.0), (3.0, 3.0), (0.25, 0.5)])
+def test_decode_denormalizes_with_the_block_range(vmin, vmax):
+    """A model whose output is a known constant c decodes to vmin + c (vmax - vmin)
+    (scale 1 for a constant block, vmax = vmin).  Construction: every table
+    entry a (the trilinear weights sum to 1, so every feature is a), first
+    layer 1/(L F) everywhere (each hidden unit sees a > 0, ReLU passes it),
+    output layer 1/width: c = a."""
+    enc, mlp = o.Encoding(4, 2, 12, 4, 2.0), o.MLP(1, 16)
+    lay = o.layout(enc, mlp)
+    a = 0.3
+    p = np.empty(lay.n_params)
+    p[:lay.n_table_params] = a
+    (w1o, w1i), (woo, woi) = lay.mlp_shapes
+    off1, off2 = lay.mlp_offsets
+    p[off1:off1 + w1o * w1i] = 1.0 / w1i
+    p[off2:off2 + woo * woi] = 1.0 / woi
+    dims = (5, 3, 4)
+    dec = o.decode(lay, p, dims, vmin, vmax)
+    assert dec.shape == (4, 3, 5)
+    want = vmin + a * ((vmax - vmin) if vmax > vmin else 1.0)
+    np.testing.assert_allclose(dec, want, rtol=0, atol=1e-14)
+
+
 def test_small_training_run_reduces_loss():
     n = 16
     vol = gaussian_sum_field(n, seed=1)
