@@ -8,8 +8,8 @@
  * value (Eq. (1)); it is a multiresolution hash-grid encoding followed by a
  * small bias-free ReLU MLP (Sec. III).  Training draws random coordinates
  * (uniform, optionally mixed with boundary-centered half-normal samples,
- * Sec. III-E), fetches trilinearly interpolated ground truth from the block's
- * voxels, and takes Adam steps on an L2 or L1 loss (Sec. III-B, III-E,
+ * Sec. III-C, Eq. (2)), fetches trilinearly interpolated ground truth from the block's
+ * voxels, and takes Adam steps on an L2 or L1 loss (Sec. III-B, III-C Eq. (3),
  * III-F).  Trained
  * models are queried at arbitrary coordinates or decoded back to the voxel
  * grid (Sec. III, on-demand inference and decoding).
@@ -130,10 +130,15 @@ typedef struct dvnr_buffers {
                                   float32 [nz+2g][ny+2g][nx+2g] (x fastest), read-only, zero-copy */
 } dvnr_buffers;
 
-/* Create a handle for n_blocks INRs sharing one configuration.
+/* Create a handle for n_blocks INRs sharing one configuration: one model per
+ * box-shaped partition, each trained only on its own partition's voxels and
+ * its ghost layer (Sec. III-A model parallelism; the INR of Eq. (1) is the
+ * encoding + MLP above).  blocks: host array of n_blocks geometries.
  * max_batch: the largest total number of training samples per step (all
  * blocks together) and the largest chunk used by decode/sample.
- * Returns DVNR_E_INVALID for out-of-range settings.  Allocates host memory only. */
+ * seed: key of the Philox sample draws.  *out receives the handle (owned by
+ * the caller, released with dvnr_destroy).  Returns DVNR_E_INVALID for
+ * out-of-range settings.  Allocates host memory only. */
 dvnr_status dvnr_create(const dvnr_encoding* enc, const dvnr_mlp* mlp, const dvnr_optim* opt,
                         dvnr_precision precision, int32_t n_blocks, const dvnr_block* blocks,
                         int64_t max_batch, uint64_t seed, dvnr_t** out);
@@ -155,8 +160,11 @@ dvnr_status dvnr_prepare(dvnr_t* h, void* stream);
 /* Host copy of the per-block ranges computed by dvnr_prepare (synchronizes the stream). */
 dvnr_status dvnr_get_ranges(dvnr_t* h, float* vmin, float* vmax, void* stream);
 
-/* Initialize masters: tables U(-1e-4, 1e-4), weights Glorot-uniform, drawn
- * with Philox4x32-10 from `seed`; clears gradients and the optimizer state. */
+/* Initialize masters (the paper does not state an initialization; this is the
+ * reading of the cited hash encoding's: tables U(-1e-4, 1e-4), weights
+ * Glorot-uniform), drawn with Philox4x32-10 from `seed`; clears gradients and
+ * the optimizer state (Sec. III-F Adam).  Needs dvnr_bind; DVNR_E_STATE
+ * before it. */
 dvnr_status dvnr_init_params(dvnr_t* h, uint64_t seed, void* stream);
 /* After the caller overwrote the master parameters: refresh the 16-bit copy
  * (mixed precision; no-op otherwise) and clear gradients. */
@@ -165,7 +173,9 @@ dvnr_status dvnr_params_updated(dvnr_t* h, void* stream);
  * moments and the step counter. */
 dvnr_status dvnr_reset_optimizer(dvnr_t* h, void* stream);
 
-/* n_steps optimizer steps.  Each step draws samples_per_step coordinates
+/* n_steps optimizer steps (Sec. III-B: per iteration, stochastic uniform
+ * samples, trilinear ground truth, one optimization step; Sec. III-F Adam).
+ * Each step draws samples_per_step coordinates
  * split over blocks in proportion to owned voxel counts (largest remainder
  * in units of 256).  Of a block's n samples, the first n - nb are uniform,
  * Philox4x32-10 counter (sample, step, block, 'DVNR') and key (seed lo,
@@ -212,11 +222,15 @@ dvnr_status dvnr_train_step_coords(dvnr_t* h, const float* coords, const int64_t
 dvnr_status dvnr_draw_training_samples(dvnr_t* h, int32_t block, int64_t step, int64_t n, float* coords,
                                        float* target, void* stream);
 
-/* On-demand inference (Sec. III): out[i] = INR_b(coords[i]) de-normalized with
- * the block range.  coords device float [n][3], out device float [n]. */
+/* On-demand inference (Sec. III and Sec. IV-A: the model is queried at any
+ * coordinate): out[i] = INR_b(coords[i]) de-normalized with the block range
+ * (Sec. III-A output normalization).  coords device float [n][3] in the
+ * block's [0,1]^3 (clamped), out device float [n]; chunks of max_batch. */
 dvnr_status dvnr_sample(dvnr_t* h, int32_t block, int64_t n, const float* coords, float* out, void* stream);
-/* Decode block b to its owned voxel grid at voxel centers (i+1/2)/n:
- * out device float [nz][ny][nx] (x fastest), de-normalized. */
+/* Decode back to the grid (Sec. III and Sec. IV-A): block b's owned voxels at
+ * voxel centers (i+1/2)/n, out device float [nz][ny][nx] (x fastest),
+ * de-normalized with the block range; block -1 decodes every block, one
+ * after the other, into consecutive grids. */
 dvnr_status dvnr_decode(dvnr_t* h, int32_t block, float* out, void* stream);
 /* Direct volume rendering of one block's INR (Sec. IV, sample streaming).
  * Rays of a pinhole camera, in the block's unit-cube coordinates, march front
@@ -287,27 +301,47 @@ dvnr_status dvnr_cache_decode(dvnr_t* h, int64_t key, int32_t block, float* out,
 dvnr_status dvnr_cache_sample(dvnr_t* h, int64_t key, int32_t block, int64_t n, const float* coords, float* out,
                               void* stream);
 
-/* Sum of squared differences (fp64 accumulation) between a decoded block and
- * the block's owned stored voxels: host *sse, *count.  Synchronizes `stream`. */
+/* Reconstruction error for the PSNR (Sec. V-B: PSNR from the mean squared
+ * error over all partitions, data normalized to [0,1]): sum of squared
+ * differences, accumulated in fp64 (the only fp64 arithmetic of the fp32 and
+ * mixed paths), between a decoded block (device float [nz][ny][nx]) and the
+ * block's owned stored voxels: host *sse, *count (owned voxels).  Summing
+ * sse and count over blocks gives the voxel-weighted global MSE.
+ * Synchronizes `stream`. */
 dvnr_status dvnr_mse_fp64(dvnr_t* h, int32_t block, const float* decoded, double* sse, int64_t* count,
                           void* stream);
 
-/* Autograd building blocks of block `block`.  Element type is double for a
- * DVNR_FP64 handle, float otherwise.  All pointers are device pointers.
- *  encode_forward : coords float [n][3] -> feats [n][L*F] using table params
+/* Autograd building blocks of block `block` (the two halves of Eq. (1)'s
+ * model, Sec. III: the multiresolution hash encoding and the ReLU MLP, with
+ * their hand-written backward).  Element type is double for a DVNR_FP64
+ * handle, float otherwise.  All pointers are device pointers.
+ *  encode_forward : coords float [n][3] -> feats [n][L*F] (sample-major) from
+ *                   the level tables `table` [n_table_params]
  *  encode_backward: dtable [n_table_params] += d(feats)/d(table)^T dfeats
- *  mlp_forward    : feats [n][L*F] -> out [n] (normalized INR output)
+ *  mlp_forward    : feats [n][L*F] -> out [n] (normalized INR output) with
+ *                   `weights` [n_mlp_params] (W_1 .. W_out, row-major)
  *  mlp_backward   : given dout [n]: dfeats [n][L*F] (overwritten), dweights
  *                   [n_mlp_params] (accumulated); recomputes the forward.
- * `table` / `weights` point at the block's table / MLP parameters. */
-dvnr_status dvnr_encode_forward(dvnr_t* h, int64_t n, const float* coords, const void* table, void* feats,
-                                void* stream);
-dvnr_status dvnr_encode_backward(dvnr_t* h, int64_t n, const float* coords, const void* dfeats, void* dtable,
-                                 void* stream);
-dvnr_status dvnr_mlp_forward(dvnr_t* h, int64_t n, const void* feats, const void* weights, void* out,
+ * A NULL table / weights stands for block `block`'s bound master parameters,
+ * a NULL dtable / dweights for its bound gradient (so that dvnr_adam_step can
+ * apply them); NULL needs dvnr_bind (DVNR_E_STATE otherwise).  DVNR_E_INVALID
+ * for block outside [0, n_blocks) or n outside [0, 2^31). */
+dvnr_status dvnr_encode_forward(dvnr_t* h, int32_t block, int64_t n, const float* coords, const void* table,
+                                void* feats, void* stream);
+dvnr_status dvnr_encode_backward(dvnr_t* h, int32_t block, int64_t n, const float* coords, const void* dfeats,
+                                 void* dtable, void* stream);
+dvnr_status dvnr_mlp_forward(dvnr_t* h, int32_t block, int64_t n, const void* feats, const void* weights, void* out,
                              void* stream);
-dvnr_status dvnr_mlp_backward(dvnr_t* h, int64_t n, const void* feats, const void* weights, const void* dout,
-                              void* dfeats, void* dweights, void* stream);
+dvnr_status dvnr_mlp_backward(dvnr_t* h, int32_t block, int64_t n, const void* feats, const void* weights,
+                              const void* dout, void* dfeats, void* dweights, void* stream);
+/* One Adam update (Sec. III-F: beta1 0.9, beta2 0.999, eps 1e-8, L2 weight
+ * decay added to the gradient, exponential learning-rate decay as in
+ * dvnr_optim) of every parameter of every block from the bound gradient
+ * buffer, e.g. filled by the building blocks above: advances the shared step
+ * counter t, refreshes the 16-bit working copy (mixed precision) and leaves
+ * the gradient at zero.  Arithmetic in the handle's precision.  Needs
+ * dvnr_bind (DVNR_E_STATE otherwise); only enqueues on `stream`. */
+dvnr_status dvnr_adam_step(dvnr_t* h, void* stream);
 
 /* Parity/debug: corner entry indices (within level `level`) and trilinear
  * weights of n coordinates: idx device uint32 [n][8], w device float [n][8]. */
@@ -354,7 +388,7 @@ dvnr_status dvnr_plan_partition(const dvnr_t* h, int32_t* first_level);
  * last dvnr_sync (DVNR_E_NONFINITE). */
 dvnr_status dvnr_sync(dvnr_t* h, void* stream);
 
-/* Loss and sampling distribution of training (Sec. III-E, Eq. (4)-(5)).
+/* Loss and sampling distribution of training (Sec. III-C, Eqs. (2)-(3)).
  *  loss          : DVNR_LOSS_L2 (mean squared error, the default) or
  *                  DVNR_LOSS_L1 (mean absolute error, dL/do = sign(o - y)/n
  *                  with sign(0) = 0).

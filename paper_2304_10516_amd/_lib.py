@@ -88,10 +88,11 @@ SIGNATURES = {
     "dvnr_sample": [P, I32, I64, VP, VP, VP],
     "dvnr_decode": [P, I32, VP, VP],
     "dvnr_mse_fp64": [P, I32, VP, C.POINTER(C.c_double), C.POINTER(C.c_int64), VP],
-    "dvnr_encode_forward": [P, I64, VP, VP, VP, VP],
-    "dvnr_encode_backward": [P, I64, VP, VP, VP, VP],
-    "dvnr_mlp_forward": [P, I64, VP, VP, VP, VP],
-    "dvnr_mlp_backward": [P, I64, VP, VP, VP, VP, VP, VP],
+    "dvnr_encode_forward": [P, I32, I64, VP, VP, VP, VP],
+    "dvnr_encode_backward": [P, I32, I64, VP, VP, VP, VP],
+    "dvnr_mlp_forward": [P, I32, I64, VP, VP, VP, VP],
+    "dvnr_mlp_backward": [P, I32, I64, VP, VP, VP, VP, VP, VP],
+    "dvnr_adam_step": [P, VP],
     "dvnr_debug_indices": [P, I32, I64, VP, VP, VP, VP],
     "dvnr_sync": [P, VP],
     "dvnr_set_option": [P, C.c_char_p, I64],

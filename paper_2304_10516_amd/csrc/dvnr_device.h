@@ -42,7 +42,7 @@ __device__ __forceinline__ float u24(uint32_t u) { return (float)(u >> 8) * 5.96
 
 // Training coordinate of sample i of a block at one step.  Samples below
 // n_uni are uniform in [0,1)^3 (Philox words 0..2 of counter (i, step, block,
-// 'DVNR')).  The others are boundary-centered (Sec. III-E, Eq. (4)), read as
+// 'DVNR')).  The others are boundary-centered (Sec. III-C, Eq. (2)), read as
 // an equal mixture over the six cube faces: counter (i, step, block, 'DVNB');
 // face = floor(6 u3 / 2^32) picks axis face/2 and side face%2, the distance
 // to the face is the half-normal quantile sigma sqrt(2) erfinv(v) of
@@ -66,6 +66,37 @@ __device__ __forceinline__ void train_coord(uint32_t i, uint32_t step, uint32_t 
   x = axis == 0 ? nc : t0;
   y = axis == 1 ? nc : (axis == 0 ? t0 : t1);
   z = axis == 2 ? nc : t1;
+}
+
+// ---------------------------------------------------------------------------
+// Adam factors of update t (t = 1, 2, ...; Sec. III-F): the bias corrections
+// 1/(1 - b1^t) and 1/(1 - b2^t), with 1 - b^t = -expm1(t ln b), and the
+// learning rate lr0 2^(((t - start) / interval) log2(base)) once t > start
+// (interval <= 0: constant).  ln b and log2(base) come from the host, so the
+// factors are evaluated in the parameters' own precision (float for the fp32
+// and mixed paths).  t, t - start and the interval are clamped to 2^30.
+// ---------------------------------------------------------------------------
+template <typename P>
+__device__ __forceinline__ void adam_factors(int64_t t, P lr0, P ln_b1, P ln_b2, P log2_decay, int64_t start,
+                                             int64_t interval, P& bc1, P& bc2, P& lr) {
+  constexpr int64_t kCap = (int64_t)1 << 30;
+  const P tp = (P)(int32_t)(t < kCap ? t : kCap);
+  lr = lr0;
+  if constexpr (sizeof(P) == 4) {
+    bc1 = 1.0f / -expm1f(tp * ln_b1);
+    bc2 = 1.0f / -expm1f(tp * ln_b2);
+  } else {
+    bc1 = 1.0 / -expm1(tp * ln_b1);
+    bc2 = 1.0 / -expm1(tp * ln_b2);
+  }
+  if (interval > 0 && t > start) {
+    const int64_t dt = t - start;
+    const P e = (P)(int32_t)(dt < kCap ? dt : kCap) / (P)(int32_t)(interval < kCap ? interval : kCap) * log2_decay;
+    if constexpr (sizeof(P) == 4)
+      lr = lr0 * exp2f(e);
+    else
+      lr = lr0 * exp2(e);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -172,7 +203,7 @@ __device__ __forceinline__ uint32_t xcc_id() {
 // With fewer levels, each XCD serves one level.
 // Any mapping is correct; this one only improves locality and balance.
 // Returns false for idle workgroups.  Levels of the launch are [l0, l0 + L).
-__device__ __forceinline__ bool level_major_item(int wg, int l0, int L, int n_tiles, int xcd_map, int& tile,
+__host__ __device__ __forceinline__ bool level_major_item(int wg, int l0, int L, int n_tiles, int xcd_map, int& tile,
                                                  int& level) {
   if (L <= 0) return false;
   if (xcd_map && L >= 8) {

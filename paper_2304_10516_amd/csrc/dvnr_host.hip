@@ -76,7 +76,7 @@ struct dvnr {
   char* cache_buf = nullptr;
   int cache_cap = 0, cache_head = 0, cache_count = 0;
   std::vector<int64_t> cache_keys;
-  // loss (Sec. III-E): 0 L2, 1 L1; fraction and spread of boundary-centered samples
+  // loss (Sec. III-C, Eq. (3)): 0 L2, 1 L1; fraction and spread of boundary-centered samples
   int loss_l1 = 0;
   double bnd_frac = 0.0, bnd_sigma = 0.005;
   SampleDist dist() const { return SampleDist{(float)(bnd_sigma * 1.4142135623730951), 0}; }
@@ -846,7 +846,9 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
     pa.b2 = (float)h->opt.beta2;
     pa.eps = (float)h->opt.eps;
     pa.wd = (float)h->opt.weight_decay;
-    pa.decay_base = h->opt.lr_decay_interval > 0 ? h->opt.lr_decay_base : 1.0;
+    pa.ln_b1 = (float)std::log(h->opt.beta1);
+    pa.ln_b2 = (float)std::log(h->opt.beta2);
+    pa.log2_decay = h->opt.lr_decay_interval > 0 ? (float)std::log2(h->opt.lr_decay_base) : 0.0f;
     pa.decay_start = h->opt.lr_decay_start;
     pa.decay_interval = h->opt.lr_decay_interval > 0 ? h->opt.lr_decay_interval : 0;
   }
@@ -1428,10 +1430,25 @@ dvnr_status dvnr_mse_fp64(dvnr_t* h, int32_t block, const float* decoded, double
   return DVNR_OK;
 }
 
-dvnr_status dvnr_encode_forward(dvnr_t* h, int64_t n, const float* coords, const void* table, void* feats,
-                                void* stream) {
+// Autograd building blocks: `block` selects the block whose bound buffers a
+// NULL table / weights / gradient pointer stands for.
+static dvnr_status building_block_ready(dvnr_t* h, int32_t block, bool needs_bound) {
   if (!h) return fail(DVNR_E_INVALID, "null handle");
-  if (n < 0 || n >= ((int64_t)1 << 31) || (n > 0 && (!coords || !table || !feats))) return fail(DVNR_E_INVALID, "bad arguments");
+  if (block < 0 || block >= h->nb) return fail(DVNR_E_INVALID, "bad block");
+  if (needs_bound && !h->bound) return fail(DVNR_E_STATE, "a NULL parameter pointer needs dvnr_bind");
+  return DVNR_OK;
+}
+
+static char* block_elem(const dvnr_t* h, void* base, int32_t block, int64_t rel) {
+  return (char*)base + (size_t)(((int64_t)block * h->stride + rel) * (int64_t)h->pelem());
+}
+
+dvnr_status dvnr_encode_forward(dvnr_t* h, int32_t block, int64_t n, const float* coords, const void* table,
+                                void* feats, void* stream) {
+  dvnr_status st = building_block_ready(h, block, !table);
+  if (st) return st;
+  if (n < 0 || n >= ((int64_t)1 << 31) || (n > 0 && (!coords || !feats))) return fail(DVNR_E_INVALID, "bad arguments");
+  if (!table) table = block_elem(h, h->buf.params, block, 0);
   const int64_t LF = h->md.in_dim;
   const Prec tp = h->prec == Prec::F64 ? Prec::F64 : Prec::F32;
   HIPCHK(launch_encode(tp, tp == Prec::F64 ? 2 : 0, h->ld, nullptr, nullptr, (int)n, 0, nullptr, coords, table, feats,
@@ -1439,10 +1456,12 @@ dvnr_status dvnr_encode_forward(dvnr_t* h, int64_t n, const float* coords, const
   return DVNR_OK;
 }
 
-dvnr_status dvnr_encode_backward(dvnr_t* h, int64_t n, const float* coords, const void* dfeats, void* dtable,
-                                 void* stream) {
-  if (!h) return fail(DVNR_E_INVALID, "null handle");
-  if (n < 0 || n >= ((int64_t)1 << 31) || (n > 0 && (!coords || !dfeats || !dtable))) return fail(DVNR_E_INVALID, "bad arguments");
+dvnr_status dvnr_encode_backward(dvnr_t* h, int32_t block, int64_t n, const float* coords, const void* dfeats,
+                                 void* dtable, void* stream) {
+  dvnr_status st = building_block_ready(h, block, !dtable);
+  if (st) return st;
+  if (n < 0 || n >= ((int64_t)1 << 31) || (n > 0 && (!coords || !dfeats))) return fail(DVNR_E_INVALID, "bad arguments");
+  if (!dtable) dtable = block_elem(h, h->buf.grads, block, 0);
   const int64_t LF = h->md.in_dim;
   const Prec gp = h->prec == Prec::F64 ? Prec::F64 : Prec::F32;
   HIPCHK(launch_scatter(gp, h->ld, 0, h->enc.n_levels, nullptr, nullptr, (int)n, 0, nullptr, coords, dfeats, LF,
@@ -1451,21 +1470,41 @@ dvnr_status dvnr_encode_backward(dvnr_t* h, int64_t n, const float* coords, cons
   return DVNR_OK;
 }
 
-dvnr_status dvnr_mlp_forward(dvnr_t* h, int64_t n, const void* feats, const void* weights, void* out, void* stream) {
-  if (!h) return fail(DVNR_E_INVALID, "null handle");
-  if (n < 0 || (n > 0 && (!feats || !weights || !out))) return fail(DVNR_E_INVALID, "bad arguments");
+dvnr_status dvnr_mlp_forward(dvnr_t* h, int32_t block, int64_t n, const void* feats, const void* weights, void* out,
+                             void* stream) {
+  dvnr_status st = building_block_ready(h, block, !weights);
+  if (st) return st;
+  if (n < 0 || (n > 0 && (!feats || !out))) return fail(DVNR_E_INVALID, "bad arguments");
+  if (!weights) weights = block_elem(h, h->buf.params, block, h->n_table);
   const Prec p = h->prec == Prec::F64 ? Prec::F64 : Prec::F32;
   HIPCHK(launch_mlp_simple_fwd(p, h->md, n, feats, weights, out, (hipStream_t)stream));
   return DVNR_OK;
 }
 
-dvnr_status dvnr_mlp_backward(dvnr_t* h, int64_t n, const void* feats, const void* weights, const void* dout,
-                              void* dfeats, void* dweights, void* stream) {
-  if (!h) return fail(DVNR_E_INVALID, "null handle");
-  if (n < 0 || (n > 0 && (!feats || !weights || !dout || !dfeats || !dweights)))
-    return fail(DVNR_E_INVALID, "bad arguments");
+dvnr_status dvnr_mlp_backward(dvnr_t* h, int32_t block, int64_t n, const void* feats, const void* weights,
+                              const void* dout, void* dfeats, void* dweights, void* stream) {
+  dvnr_status st = building_block_ready(h, block, !weights || !dweights);
+  if (st) return st;
+  if (n < 0 || (n > 0 && (!feats || !dout || !dfeats))) return fail(DVNR_E_INVALID, "bad arguments");
+  if (!weights) weights = block_elem(h, h->buf.params, block, h->n_table);
+  if (!dweights) dweights = block_elem(h, h->buf.grads, block, h->n_table);
   const Prec p = h->prec == Prec::F64 ? Prec::F64 : Prec::F32;
   HIPCHK(launch_mlp_simple_bwd(p, h->md, n, feats, weights, dout, dfeats, dweights, (hipStream_t)stream));
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_adam_step(dvnr_t* h, void* stream) {
+  if (!h) return fail(DVNR_E_INVALID, "null handle");
+  if (!h->bound) return fail(DVNR_E_STATE, "dvnr_adam_step before dvnr_bind");
+  hipStream_t s = (hipStream_t)stream;
+  // this update's index t = step + 1, then every parameter of every block
+  HIPCHK(launch_bump_step(h->d_ctr(), s));
+  HIPCHK(launch_adam(h->prec, h->buf.params, h->buf.grads, h->buf.adam_m, h->buf.adam_v,
+                     h->prec == Prec::MIXED ? (uint16_t*)h->buf.work16 : nullptr, h->nb, h->stride, h->n_table,
+                     h->n_table + h->n_mlp, nullptr, h->d_ctr(), h->opt.lr, h->opt.beta1, h->opt.beta2, h->opt.eps,
+                     h->opt.weight_decay, h->opt.lr_decay_interval > 0 ? h->opt.lr_decay_base : 1.0,
+                     h->opt.lr_decay_start, h->opt.lr_decay_interval > 0 ? h->opt.lr_decay_interval : 0, s));
+  h->host_step += 1;
   return DVNR_OK;
 }
 

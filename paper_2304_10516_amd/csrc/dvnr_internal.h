@@ -57,7 +57,7 @@ struct BlockPlan {
   int32_t pad;
 };
 
-// Sampling distribution of a step (boundary loss of Sec. III-E).
+// Sampling distribution of a step (boundary loss of Sec. III-C, Eq. (2)).
 struct SampleDist {
   float sigma_sqrt2;           // sigma * sqrt(2): half-normal quantile scale of boundary samples
   int32_t direct_n_uni;        // n_uni of the block of a direct-mode draw
@@ -90,6 +90,8 @@ hipError_t launch_init_params(Prec p, void* params, int n_blocks, int64_t block_
 hipError_t launch_refresh16(void* params, uint16_t* work16, int n_blocks, int64_t block_stride,
                             int64_t n_table_params, int64_t n_mlp, hipStream_t s);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
+// ctr->step += 1 (one thread): the index of an optimizer update taken outside a training step.
+hipError_t launch_bump_step(Counters* ctr, hipStream_t s);
 
 // Sampler: coordinates (generated when gen != 0, else read from `coords`)
 // and normalized trilinear targets.
@@ -176,7 +178,8 @@ struct PartAdam {
   uint16_t* work16;
   const Counters* ctr;
   float lr0, b1, b2, eps, wd;
-  double decay_base;
+  float ln_b1, ln_b2;      // log(b1), log(b2), evaluated on the host
+  float log2_decay;        // log2 of the learning-rate decay base
   int64_t decay_start, decay_interval;
 };
 // adam == nullptr: the slice pass adds its sums into `grad`; otherwise it
@@ -220,6 +223,7 @@ hipError_t launch_reduce_slots(const float* slots, int64_t slot_stride, const in
 
 // skip0 <= skip1: block-relative elements [skip0, skip1) are left alone (the
 // slice pass updated them).
+// Adam reads this update's index t from ctr->step (advanced before it runs).
 hipError_t launch_adam(Prec p, void* params, void* grad, void* m, void* v, uint16_t* work16, int n_blocks,
                        int64_t block_stride, int64_t n_table_params, int64_t n_used, const BlockPlan* plan,
                        const Counters* ctr, double lr, double b1, double b2, double eps, double wd,

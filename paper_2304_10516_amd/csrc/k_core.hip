@@ -444,22 +444,17 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
                                               P* __restrict__ vel, uint16_t* __restrict__ work16,
                                               int64_t block_stride, int64_t n_table, int64_t n_used,
                                               const BlockPlan* __restrict__ plan, const Counters* __restrict__ ctr,
-                                              P lr0, P b1, P b2, P eps, P wd, double decay_base, int64_t decay_start,
-                                              int64_t decay_interval, int64_t skip0, int64_t skip1) {
+                                              P lr0, P b1, P b2, P eps, P wd, P ln_b1, P ln_b2, P log2_decay,
+                                              int64_t decay_start, int64_t decay_interval, int64_t skip0,
+                                              int64_t skip1) {
   // grid (element groups of the block, blocks): no division per element, one
   // uniform skip for a block that drew no sample this step
   const int b = blockIdx.y;
   if (plan && plan[b].n == 0) return;
   __shared__ P bc[3];
   if (threadIdx.x == 0) {
-    const int64_t ti = ctr->step;  // this update's index t (1, 2, ...)
-    const double t = (double)ti;
-    bc[0] = (P)(1.0 / (1.0 - pow((double)b1, t)));
-    bc[1] = (P)(1.0 / (1.0 - pow((double)b2, t)));
-    double lr = (double)lr0;
-    if (decay_interval > 0 && ti > decay_start)
-      lr *= pow(decay_base, (double)(ti - decay_start) / (double)decay_interval);
-    bc[2] = (P)lr;
+    // this update's index t (1, 2, ...): the slot reduction advanced the counter
+    adam_factors<P>(ctr->step, lr0, ln_b1, ln_b2, log2_decay, decay_start, decay_interval, bc[0], bc[1], bc[2]);
   }
   __syncthreads();
   const P bc1 = bc[0], bc2 = bc[1], lr = bc[2];
@@ -566,14 +561,18 @@ hipError_t launch_adam(Prec p, void* params, void* grad, void* m, void* v, uint1
     gx = pre + std::max<int64_t>(0, (n_used - base + 1023) / 1024);
   }
   const dim3 grid((unsigned)gx, (unsigned)n_blocks);
+  // logarithms of the decay rates and of the learning-rate decay base, once on the host
+  const double ln_b1 = std::log(b1), ln_b2 = std::log(b2);
+  const double log2_decay = decay_interval > 0 ? std::log2(decay_base) : 0.0;
   if (p == Prec::F64)
     hipLaunchKernelGGL(k_adam<double>, grid, dim3(256), 0, s, (double*)params, (double*)grad, (double*)m, (double*)v,
-                       nullptr, block_stride, n_table_params, n_used, plan, ctr, lr, b1, b2, eps, wd, decay_base,
-                       decay_start, decay_interval, skip0, skip1);
+                       nullptr, block_stride, n_table_params, n_used, plan, ctr, lr, b1, b2, eps, wd, ln_b1, ln_b2,
+                       log2_decay, decay_start, decay_interval, skip0, skip1);
   else
     hipLaunchKernelGGL(k_adam<float>, grid, dim3(256), 0, s, (float*)params, (float*)grad, (float*)m, (float*)v,
                        work16, block_stride, n_table_params, n_used, plan, ctr, (float)lr, (float)b1, (float)b2,
-                       (float)eps, (float)wd, decay_base, decay_start, decay_interval, skip0, skip1);
+                       (float)eps, (float)wd, (float)ln_b1, (float)ln_b2, (float)log2_decay, decay_start,
+                       decay_interval, skip0, skip1);
   return hipGetLastError();
 }
 
@@ -717,6 +716,15 @@ hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
   hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, (uint32_t*)p, n);
+  return hipGetLastError();
+}
+
+__global__ void k_bump_step(Counters* __restrict__ ctr) {
+  if (threadIdx.x == 0) ctr->step += 1;
+}
+
+hipError_t launch_bump_step(Counters* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_bump_step, dim3(1), dim3(64), 0, s, ctr);
   return hipGetLastError();
 }
 

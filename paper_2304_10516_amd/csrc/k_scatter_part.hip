@@ -306,14 +306,8 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
     *fl = 0;
     if (do_adam) {
       // this update's index t = step + 1 (the slot reduction advances the counter later)
-      const int64_t ti = adam.ctr->step + 1;
-      const double t = (double)ti;
-      hbc[0] = (float)(1.0 / (1.0 - pow((double)adam.b1, t)));
-      hbc[1] = (float)(1.0 / (1.0 - pow((double)adam.b2, t)));
-      double lr = (double)adam.lr0;
-      if (adam.decay_interval > 0 && ti > adam.decay_start)
-        lr *= pow(adam.decay_base, (double)(ti - adam.decay_start) / (double)adam.decay_interval);
-      hbc[2] = (float)lr;
+      adam_factors<float>(adam.ctr->step + 1, adam.lr0, adam.ln_b1, adam.ln_b2, adam.log2_decay, adam.decay_start,
+                          adam.decay_interval, hbc[0], hbc[1], hbc[2]);
     }
   }
   // software pipeline: the next batch's loads are issued before this batch's
@@ -346,7 +340,8 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
     }
   }
   __syncthreads();
-  const double unit = 1.0 / (double)scale;
+  // fixed-point sums back to float: a correctly rounded int64 -> float
+  // conversion and an exact scaling by 2^-K
   const int64_t e0 = (int64_t)s << sh;
   const int nf = (int)min((int64_t)1 << sh, (int64_t)pd.E[l] - e0) * F;
   const int64_t el0 = meta[b].param_off + ((int64_t)ld.off[l] + e0) * F;  // first element of the slice
@@ -366,7 +361,7 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
         const int i = tid + NT * (k0 + k);
         if (i < nf) {
           const long long a = (long long)acc[i];
-          if (a != 0) g[i] = gv[k] + (float)((double)a * unit);
+          if (a != 0) g[i] = gv[k] + ldexpf((float)a, -K);
         }
       }
       continue;
@@ -384,7 +379,7 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
     for (int k = 0; k < KB; ++k) {
       const int i = tid + NT * (k0 + k);
       if (i >= nf) continue;
-      const float gg = gv[k] + (float)((double)(long long)acc[i] * unit) + adam.wd * th[k];
+      const float gg = gv[k] + ldexpf((float)(long long)acc[i], -K) + adam.wd * th[k];
       const float m1 = adam.b1 * mm[k] + (1.0f - adam.b1) * gg;
       const float v1 = adam.b2 * vv[k] + (1.0f - adam.b2) * gg * gg;
       const float t1 = th[k] - lr * (m1 * bc1) / (sqrtf(v1 * bc2) + adam.eps);

@@ -156,7 +156,7 @@ class DVNR:
 
     def set_loss(self, loss: str = "l2", boundary_frac: float = 0.0, sigma: float = 0.005):
         """Training loss ("l2" or "l1") and the share / spread of
-        boundary-centered samples (Sec. III-E; the paper uses l1, 0.15, 0.005)."""
+        boundary-centered samples (Sec. III-C, Eqs. (2)-(3); the paper uses l1, 0.15, 0.005)."""
         if loss not in self.LOSSES:
             raise ValueError(f"unknown loss {loss!r}")
         L.check(self.lib.dvnr_set_loss(self.h, self.LOSSES[loss], float(boundary_frac), float(sigma)))
@@ -327,30 +327,42 @@ class DVNR:
         return sse.value, cnt.value
 
     # -- autograd building blocks ------------------------------------------------
-    def encode_forward(self, coords, table, stream=None):
+    # A tensor argument of None stands for block `block`'s bound parameters
+    # (table, weights) or gradients (dtable, dweights).
+    @staticmethod
+    def _ptr(t):
+        return t.data_ptr() if t is not None else None
+
+    def encode_forward(self, coords, table=None, block: int = 0, stream=None):
         n = coords.shape[0]
-        feats = torch.empty((n, self.enc.n_levels * self.enc.n_features), dtype=table.dtype, device=self.device)
-        L.check(self.lib.dvnr_encode_forward(self.h, n, coords.data_ptr(), table.data_ptr(), feats.data_ptr(),
-                                             _stream_ptr(stream)))
+        dt = table.dtype if table is not None else self.pdtype
+        feats = torch.empty((n, self.enc.n_levels * self.enc.n_features), dtype=dt, device=self.device)
+        L.check(self.lib.dvnr_encode_forward(self.h, int(block), n, coords.data_ptr(), self._ptr(table),
+                                             feats.data_ptr(), _stream_ptr(stream)))
         return feats
 
-    def encode_backward(self, coords, dfeats, dtable, stream=None):
-        L.check(self.lib.dvnr_encode_backward(self.h, coords.shape[0], coords.data_ptr(), dfeats.data_ptr(),
-                                              dtable.data_ptr(), _stream_ptr(stream)))
+    def encode_backward(self, coords, dfeats, dtable=None, block: int = 0, stream=None):
+        L.check(self.lib.dvnr_encode_backward(self.h, int(block), coords.shape[0], coords.data_ptr(),
+                                              dfeats.data_ptr(), self._ptr(dtable), _stream_ptr(stream)))
         return dtable
 
-    def mlp_forward(self, feats, weights, stream=None):
+    def mlp_forward(self, feats, weights=None, block: int = 0, stream=None):
         out = torch.empty(feats.shape[0], dtype=feats.dtype, device=self.device)
-        L.check(self.lib.dvnr_mlp_forward(self.h, feats.shape[0], feats.data_ptr(), weights.data_ptr(),
+        L.check(self.lib.dvnr_mlp_forward(self.h, int(block), feats.shape[0], feats.data_ptr(), self._ptr(weights),
                                           out.data_ptr(), _stream_ptr(stream)))
         return out
 
-    def mlp_backward(self, feats, weights, dout, dweights, stream=None):
+    def mlp_backward(self, feats, weights, dout, dweights=None, block: int = 0, stream=None):
         dfeats = torch.empty_like(feats)
-        L.check(self.lib.dvnr_mlp_backward(self.h, feats.shape[0], feats.data_ptr(), weights.data_ptr(),
-                                           dout.data_ptr(), dfeats.data_ptr(), dweights.data_ptr(),
-                                           _stream_ptr(stream)))
+        L.check(self.lib.dvnr_mlp_backward(self.h, int(block), feats.shape[0], feats.data_ptr(),
+                                           self._ptr(weights), dout.data_ptr(), dfeats.data_ptr(),
+                                           self._ptr(dweights), _stream_ptr(stream)))
         return dfeats
+
+    def adam_step(self, stream=None):
+        """One fused Adam update of every block from the gradient buffer (`grads`);
+        leaves the gradient at zero and advances the shared step counter."""
+        L.check(self.lib.dvnr_adam_step(self.h, _stream_ptr(stream)))
 
     def debug_indices(self, level: int, coords, stream=None):
         n = coords.shape[0]

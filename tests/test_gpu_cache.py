@@ -84,3 +84,42 @@ def test_cache_window_and_bit_exact_replay(precision, fused):
         say(f"block {b}: cached t=1 vs field t=1 {own:.2f} dB, vs field t=2 {other:.2f} dB")
         assert own > other + 3.0
     model.sync()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("mixed", 1e-2)])
+def test_cached_decode_matches_oracle(precision, tol):
+    """A cached timestep decodes as the oracle decodes the parameters that were
+    pushed, de-normalized with the value range at push time (the working copy
+    for mixed precision: the bf16 MLP output bar), also after the live model
+    trained on and its voxels and range changed."""
+    from paper_2304_10516_amd.dvnr import DVNR, EncodingCfg, MlpCfg, OptimCfg
+    say(f"cached decode vs oracle {precision}")
+    enc, mlp = o.Encoding(6, 2, 14, 4, 1.6), o.MLP(2, 32)
+    lay = o.layout(enc, mlp)
+    dims, g = (24, 20, 16), 1
+    model = DVNR(EncodingCfg(6, 2, 14, 4, 1.6), MlpCfg(2, 32), [(dims, g)], OptimCfg(lr=1e-2),
+                 precision=precision, max_batch=8192, seed=5)
+    f0 = gaussian_sum_field(48, n_gauss=10, seed=200)
+    vol = np.ascontiguousarray(f0[:dims[2] + 2 * g, :dims[1] + 2 * g, :dims[0] + 2 * g]) * 3.0 - 1.0
+    model.bind_volumes([torch.as_tensor(vol, device="cuda")])
+    model.cache_bind(2)
+    model.init_params(4)
+    model.train(30, 4096)
+    model.cache_push(7)
+    pushed = model.block_params(0).cpu().numpy().astype(np.float64)
+    lo, hi = model.ranges()
+    # the live model moves on, on other voxels with another range
+    model._vols[0].copy_(torch.as_tensor(vol * 0.5 + 2.0, device="cuda"))
+    model.prepare()
+    model.train(20, 4096)
+    dec = model.cache_decode(7, 0).cpu().numpy()
+    pe = pushed
+    if precision == "mixed":
+        from tests import precision_model as pm
+        pe = pm.working_copy(lay, pushed)
+    ref = o.decode(lay, pe, dims, lo[0], hi[0])
+    err = float(np.max(np.abs(dec - ref)) / np.max(np.abs(ref - lo[0])))
+    say(f"cached decode vs oracle: normwise {err:.2e} (range [{lo[0]:.3f}, {hi[0]:.3f}])")
+    assert lo[0] < 0.0 < hi[0]
+    assert err <= tol
+    model.sync()
