@@ -1,23 +1,40 @@
 """Benchmark of the DVNR hot path on one MI355X.
 
-Default workload (the configuration the headline metric is quoted on): one
-256^3 block of a seeded turbulence-like field (random-phase Fourier modes,
-shell energy ~ k^-5/3), multiresolution hash grid L=16, T=2^19, F=2, base 16,
-finest 256, MLP 2 hidden layers of 64, L2 loss, Adam lr 1e-2, 2^18 samples per
-step.  `--workload c3`: 64 blocks with per-axis extents U{96..160} and a
-1-voxel periodic ghost layer cut from one seeded k^-5/3 field, one model per
-block (T=2^17, finest 160), 2^20 samples per step apportioned by voxel count.
+Default workload (the batched configuration the headline metric names): 64
+blocks cut from one seeded periodic k^-5/3 field with per-axis extents
+U{96..160} and a 1-voxel periodic ghost layer, one INR per block (hash grid
+L=16, T=2^17, F=2, base 16, finest 160; MLP 2 hidden layers of 64), L2 loss,
+Adam lr 1e-2, 2^20 samples per step apportioned by owned voxel count.
+`--workload c2`: one 256^3 block (T=2^19, finest 256, 2^18 samples per step);
+`c4`: the warm-started 40-timestep series; `c5`: 512 blocks of 128^3 (2^21
+samples per step).
 
 A step is one pass of the whole training path: coordinate sampling and
 ground-truth fetch, encoding, MLP forward / loss / backward, encoding
-backward, weight-gradient reduction and Adam.  Two runs of K steps each:
-mixed precision (fp16 tables, bf16 MFMA MLP, fp32 masters; the headline
-`value`) and the plain fp32 path.  Each run is then decoded to the full grid
-(voxels/s) and scored by PSNR with an fp64 reduction.  The float64 CPU oracle
-is timed on one full training step of one block as the CPU baseline.
+backward, weight-gradient reduction and Adam.  Three legs per workload:
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3]
-                       [--no-cpu-baseline] [--precisions mixed,fp32]
+* mixed: fp16 tables, bf16 MFMA MLP, fp32 masters, the default plan (ordered
+  sampling, bin-privatized coarse levels, destination-partitioned fine
+  levels) -- the headline `value`;
+* fp32_plain: the fp32 path with its own defaults (unordered samples,
+  one thread per sample and level, plain atomics);
+* fp32_same_plan: the fp32 path on the mixed leg's plan (same ordered
+  sampling, grouped and privatized scatter, same partitioned levels), so that
+  the ratio to it isolates precision.
+
+Per leg: K timed steps (hipGraph replays; inputs resident in HBM), per-phase
+device times from a short eager run with HIP events between the phases, and a
+quality run: Q steps from the initial parameters with the learning rate
+decaying exponentially to 0.1x over the Q steps, then a decode of every block
+(voxels/s) and the fp64 PSNR over all owned voxels.  The speedups are quoted
+with the PSNR gap of the quality runs ("equal PSNR": within 0.3 dB).  With
+the default workload the 256^3 workload is measured as a secondary record.
+The float64 CPU oracle is timed on one training step of a subset of the
+blocks, over a pool of worker processes (blocks are independent).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c4|c5]
+                       [--quality-steps Q] [--no-secondary] [--no-cpu-baseline]
+                       [--legs mixed,fp32_plain,fp32_same_plan]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -36,6 +53,11 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 L_LEVELS, F_FEAT = 16, 2
 ADAM_BYTES_PER_PARAM = {"mixed": 34, "fp32": 32}
+# algorithmic payload of one training sample (fp16 tables): 16 levels x 8 corners
+# x 4 B gathered, 32 B of ground-truth voxels, 256 fp32 gradient adds of 4 B
+PAYLOAD_BYTES_PER_SAMPLE = 512 + 32 + 1024
+METRIC = "train samples/s & decode voxels/s at fixed PSNR; BF16 batched vs FP32 plain"
+LEGS = ("mixed", "fp32_plain", "fp32_same_plan")
 
 
 def log(msg):
@@ -89,72 +111,103 @@ def phase_bytes(precision, phase, res):
 
 
 def make_workload(name, torch):
+    """(config, blocks [(dims, ghost)], device volumes, description)."""
     from paper_2304_10516_amd import presets
     cfg = presets.get(name)
     if name == "c2":
         from fixtures import kolmogorov_field
         log("[bench] generating the 256^3 k^-5/3 field")
         vol = kolmogorov_field(256, seed=2)
-        blocks = [((256, 256, 256), 0)]
-        vols = [torch.tensor(vol, device="cuda")]
         desc = ("single 256^3 block of a seeded k^-5/3 field; hash grid L=16, T=2^19, F=2, base 16, finest 256; "
-                "MLP 2x64 ReLU; L2 loss")
-        return cfg, blocks, vols, desc, vol
-    if name in ("c3", "c5"):
-        from fixtures import kolmogorov_field_torch, uneven_block_sizes
-        if name == "c3":
-            sx, sy, sz = uneven_block_sizes(4, 96, 160, seed=3)
-            seed = 3
-        else:
-            sx = sy = sz = np.full(8, 128)
-            seed = 5
-        nb_axis = len(sx)
-        shape = (int(sz.sum()), int(sy.sum()), int(sx.sum()))
-        log(f"[bench] generating the {shape} periodic k^-5/3 field on the GPU and cutting {nb_axis ** 3} blocks")
-        f = kolmogorov_field_torch(shape, seed=seed)
-        fp = torch.nn.functional.pad(f[None, None], (1, 1, 1, 1, 1, 1), mode="circular")[0, 0]
-        del f
-        ox, oy, oz = [np.concatenate([[0], np.cumsum(s)[:-1]]) for s in (sx, sy, sz)]
-        blocks, vols = [], []
-        for iz in range(nb_axis):
-            for iy in range(nb_axis):
-                for ix in range(nb_axis):
-                    d = (int(sx[ix]), int(sy[iy]), int(sz[iz]))
-                    z0, y0, x0 = int(oz[iz]), int(oy[iy]), int(ox[ix])
-                    vols.append(fp[z0:z0 + d[2] + 2, y0:y0 + d[1] + 2, x0:x0 + d[0] + 2].contiguous())
-                    blocks.append((d, 1))
-        del fp
-        torch.cuda.empty_cache()
-        if name == "c3":
-            desc = ("64 blocks, extents U{96..160} per axis, 1-voxel periodic ghost layer, cut from one seeded "
-                    f"k^-5/3 field of {shape[2]}x{shape[1]}x{shape[0]}; per block L=16, T=2^17, F=2, base 16, "
-                    "finest 160, MLP 2x64; samples per block proportional to voxels")
-        else:
-            desc = ("one GPU's share at scale: 1024^3 seeded k^-5/3 field cut into 512 blocks of 128^3 with a "
-                    "1-voxel periodic ghost layer; per block L=16, T=2^19, F=2, base 16, finest 128, MLP 2x64; "
-                    "2^21 samples per step (4096 per block)")
-        return cfg, blocks, vols, desc, None
-    raise ValueError(name)
+                "MLP 2x64 ReLU; L2 loss; 2^18 samples per step")
+        return cfg, [((256, 256, 256), 0)], [torch.tensor(vol, device="cuda")], desc
+    from fixtures import kolmogorov_field_torch, uneven_block_sizes
+    if name == "c3":
+        sx, sy, sz = uneven_block_sizes(4, 96, 160, seed=3)
+        seed = 3
+    else:
+        sx = sy = sz = np.full(8, 128)
+        seed = 5
+    nb_axis = len(sx)
+    shape = (int(sz.sum()), int(sy.sum()), int(sx.sum()))
+    log(f"[bench] generating the {shape} periodic k^-5/3 field on the GPU and cutting {nb_axis ** 3} blocks")
+    f = kolmogorov_field_torch(shape, seed=seed)
+    fp = torch.nn.functional.pad(f[None, None], (1, 1, 1, 1, 1, 1), mode="circular")[0, 0]
+    del f
+    ox, oy, oz = [np.concatenate([[0], np.cumsum(s)[:-1]]) for s in (sx, sy, sz)]
+    blocks, vols = [], []
+    for iz in range(nb_axis):
+        for iy in range(nb_axis):
+            for ix in range(nb_axis):
+                d = (int(sx[ix]), int(sy[iy]), int(sz[iz]))
+                z0, y0, x0 = int(oz[iz]), int(oy[iy]), int(ox[ix])
+                vols.append(fp[z0:z0 + d[2] + 2, y0:y0 + d[1] + 2, x0:x0 + d[0] + 2].contiguous())
+                blocks.append((d, 1))
+    del fp
+    torch.cuda.empty_cache()
+    if name == "c3":
+        desc = ("64 blocks, extents U{96..160} per axis, 1-voxel periodic ghost layer, cut from one seeded "
+                f"k^-5/3 field of {shape[2]}x{shape[1]}x{shape[0]}; one INR per block: L=16, T=2^17, F=2, base 16, "
+                "finest 160, MLP 2x64 ReLU; L2 loss; 2^20 samples per step apportioned by voxel count")
+    else:
+        desc = ("one GPU's share at scale: 1024^3 seeded k^-5/3 field cut into 512 blocks of 128^3 with a "
+                "1-voxel periodic ghost layer; one INR per block: L=16, T=2^19, F=2, base 16, finest 128, MLP 2x64; "
+                "2^21 samples per step (4096 per block)")
+    return cfg, blocks, vols, desc
 
 
-def run_precision(torch, DVNR, cfg, blocks, vols, precision, steps, warmup, seed=3):
+def _optim_over(cfg, n_steps):
+    """The workload's Adam with the learning rate decaying exponentially to 0.1x
+    over n_steps (Sec. III-F names an exponential decay)."""
+    import dataclasses
+    return dataclasses.replace(cfg["optim"], lr_decay_base=0.1, lr_decay_start=0, lr_decay_interval=max(n_steps, 1))
+
+
+def run_leg(torch, DVNR, cfg, blocks, vols, leg, steps, warmup, quality_steps, plan=None, seed=3):
+    """One leg: timed steps, per-phase times, quality run, decode and PSNR."""
+    precision = "mixed" if leg == "mixed" else "fp32"
     batch = cfg["batch"]
-    model = DVNR(cfg["enc"], cfg["mlp"], blocks, cfg["optim"], precision=precision, max_batch=batch, seed=seed)
+    model = DVNR(cfg["enc"], cfg["mlp"], blocks, _optim_over(cfg, quality_steps), precision=precision,
+                 max_batch=batch, seed=seed)
     model.bind_volumes(vols)
+    if leg == "fp32_same_plan":
+        model.set_option("spatial_sort", 1)
+        model.set_option("scatter_grouped", 1)
+        model.set_option("scatter_part", plan["part_levels"])
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         model.init_params(1, stream=stream)
         if warmup:
-            model.train(warmup, batch, stream=stream)
-        model.init_params(1, stream=stream)  # the timed run starts from the initial state
+            model.train(warmup, batch, stream=stream)  # plan, graph capture, clocks
+        model.init_params(1, stream=stream)
         stream.synchronize()
-        log(f"[bench] {precision}: timing {steps} steps of {batch} samples over {len(blocks)} block(s)")
+        log(f"[bench] {leg}: timing {steps} steps of {batch} samples over {len(blocks)} block(s)")
         t0 = time.perf_counter()
-        loss = model.train(steps, batch, want_loss=True, stream=stream)  # hipGraph replays
+        model.train(steps, batch, stream=stream)  # hipGraph replays
         stream.synchronize()
         t1 = time.perf_counter()
         bins, priv = model.plan_info()
         part = model.partitioned_levels()
+        # per-phase device times: a short eager run with HIP events between the
+        # phases, the concurrent branches run one after the other (each phase is
+        # then one kernel's time)
+        model.set_option("profile_phases", 1)
+        model.set_option("part_concurrent", 0)
+        model.set_option("encode_concurrent", 0)
+        model.phase_times()
+        model.train(min(max(steps, 10), 50), batch, stream=stream)
+        stream.synchronize()
+        phases, nsteps = model.phase_times()
+        model.set_option("profile_phases", 0)
+        model.set_option("part_concurrent", 1)
+        model.set_option("encode_concurrent", 1)
+        # quality run from the initial parameters
+        model.init_params(1, stream=stream)
+        stream.synchronize()
+        q0 = time.perf_counter()
+        loss = model.train(quality_steps, batch, want_loss=True, stream=stream)
+        stream.synchronize()
+        q_ms = (time.perf_counter() - q0) * 1e3 / max(quality_steps, 1)
         outs = [torch.empty((d[2], d[1], d[0]), dtype=torch.float32, device="cuda") for d, _ in blocks]
         for b in range(len(blocks)):  # warm
             model.decode(b, out=outs[b], stream=stream)
@@ -170,22 +223,9 @@ def run_precision(torch, DVNR, cfg, blocks, vols, precision, steps, warmup, seed
             s, c = model.squared_error(b, outs[b], stream=stream)
             sse += s
             cnt += c
-        # per-phase device times: a further short run with HIP events between the
-        # phases (eager launches), after the quality of the timed run was measured
-        # (the concurrent branches of the step run one after the other here, so
-        # that each phase is one kernel's time)
-        model.set_option("profile_phases", 1)
-        model.set_option("part_concurrent", 0)
-        model.set_option("encode_concurrent", 0)
-        model.phase_times()
-        model.train(min(steps, 200), batch, stream=stream)
-        stream.synchronize()
-        phases, nsteps = model.phase_times()
-        model.set_option("profile_phases", 0)
-        model.set_option("part_concurrent", 1)
-        model.set_option("encode_concurrent", 1)
+        del outs
         render = None
-        if len(blocks) == 1:
+        if len(blocks) == 1 and leg == "mixed":
             # sample-streaming direct volume rendering of the trained block, 1024^2 rays
             lo, hi = model.ranges()
             tf = torch.tensor([[0.05, 0.1, 0.6, 0.0], [0.1, 0.6, 0.7, 0.05], [0.9, 0.8, 0.2, 0.3],
@@ -205,57 +245,52 @@ def run_precision(torch, DVNR, cfg, blocks, vols, precision, steps, warmup, seed
     lossv = loss.float().mean(dim=1).cpu().numpy()
     res = dict(ms_per_step=ms, samples_per_s=batch / (ms * 1e-3), decode_ms=dec_ms,
                decode_voxels_per_s=cnt / (dec_ms * 1e-3), psnr=float(10 * np.log10(cnt / sse)),
-               loss_first=float(lossv[0]), loss_last=float(lossv[-1]),
+               quality_ms_per_step=q_ms, loss_first=float(lossv[0]), loss_last=float(lossv[-1]),
                phase_ms={k: v / max(nsteps, 1) for k, v in phases.items()}, n_params=model.sizes.n_params,
                bins_per_axis=bins, priv_levels=priv, part_levels=part, batch=batch, render=render,
                level_entries=model.level_info()[3], n_blocks=len(blocks))
-    log(f"[bench] {precision}: {ms:.3f} ms/step, {res['samples_per_s'] / 1e6:.1f} M samples/s, "
-        f"psnr {res['psnr']:.2f} dB, decode {dec_ms:.2f} ms, bins {bins}^3, privatized levels {priv}, partitioned from level {part}, phases " +
+    log(f"[bench] {leg}: {ms:.3f} ms/step, {res['samples_per_s'] / 1e6:.1f} M samples/s, quality run "
+        f"{q_ms:.3f} ms/step, psnr {res['psnr']:.2f} dB after {quality_steps} steps, decode {dec_ms:.2f} ms, "
+        f"bins {bins}^3, privatized levels {priv}, partitioned from level {part}, phases " +
         ", ".join(f"{k} {v:.3f}" for k, v in res["phase_ms"].items()))
     del model
+    torch.cuda.empty_cache()
     return res
 
 
-def run_timeseries(torch, DVNR, cfg, precision, n_timesteps, steps_per_t, seed=3):
-    """In situ time series: every timestep of the advected-blob field is compressed by
-    training the previous timestep's model for `steps_per_t` steps (weights kept,
-    Adam moments and step reset: warm start); reports per-timestep latency."""
-    from fixtures import advected_blobs_series_torch
-    n = 256
-    batch = cfg["batch"]
-    series = advected_blobs_series_torch(n, n_timesteps, 16, seed=4)
-    vol = next(series).contiguous()
-    model = DVNR(cfg["enc"], cfg["mlp"], [((n, n, n), 0)], cfg["optim"], precision=precision, max_batch=batch,
-                 seed=seed)
-    model.bind_volumes([vol])
-    vol_bound = model._vols[0]
-    stream = torch.cuda.Stream()
-    lat, psnr = [], []
-    out = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
-    with torch.cuda.stream(stream):
-        model.init_params(1, stream=stream)
-        model.train(5, batch, stream=stream)  # build the plan and the graph
-        model.init_params(1, stream=stream)
-        stream.synchronize()
-        for t in range(n_timesteps):
-            if t > 0:
-                vol_bound.copy_(next(series))
-            stream.synchronize()
-            t0 = time.perf_counter()
-            model.prepare(stream=stream)
-            model.reset_optimizer(stream=stream)
-            model.train(steps_per_t, batch, stream=stream)
-            stream.synchronize()
-            lat.append((time.perf_counter() - t0) * 1e3)
-            model.decode(0, out=out, stream=stream)
-            sse, cnt = model.squared_error(0, out, stream=stream)
-            psnr.append(float(10 * np.log10(cnt / sse)))
-            log(f"[bench] c4 {precision} timestep {t}: {lat[-1]:.1f} ms, psnr {psnr[-1]:.2f} dB")
-        model.sync(stream=stream)
-    del model
-    ms = float(np.mean(lat)) / steps_per_t
-    return dict(ms_per_step=ms, samples_per_s=batch / (ms * 1e-3), latency_ms=lat, psnr_per_t=psnr,
-                psnr=float(np.mean(psnr)), batch=batch)
+def leg_record(r):
+    return {"samples_per_s": r["samples_per_s"], "ms_per_step": r["ms_per_step"],
+            "decode_voxels_per_s": r["decode_voxels_per_s"], "psnr_db": r["psnr"],
+            "quality_ms_per_step": r["quality_ms_per_step"], "phase_ms": r["phase_ms"],
+            "plan": {"bins_per_axis": r["bins_per_axis"], "priv_levels": r["priv_levels"],
+                     "part_from_level": r["part_levels"]}}
+
+
+def run_workload(torch, DVNR, name, legs, steps, warmup, quality_steps):
+    cfg, blocks, vols, desc = make_workload(name, torch)
+    results = {}
+    for leg in legs:
+        plan = results.get("mixed")
+        if leg == "fp32_same_plan" and plan is None:
+            raise ValueError("fp32_same_plan needs the mixed leg first")
+        results[leg] = run_leg(torch, DVNR, cfg, blocks, vols, leg, steps, warmup, quality_steps, plan=plan)
+    rec = {leg: leg_record(results[leg]) for leg in legs}
+    rec.update(speedups(results))
+    return cfg, blocks, vols, desc, results, rec
+
+
+def speedups(results):
+    """Mixed-leg throughput over each fp32 leg's, with the PSNR gap of the
+    quality runs and whether it is within 0.3 dB (equal PSNR)."""
+    out = {}
+    if "mixed" in results:
+        for leg in ("fp32_plain", "fp32_same_plan"):
+            if leg in results:
+                gap = results["mixed"]["psnr"] - results[leg]["psnr"]
+                out[f"speedup_vs_{leg}"] = results["mixed"]["samples_per_s"] / results[leg]["samples_per_s"]
+                out[f"psnr_gap_vs_{leg}_db"] = gap
+                out[f"equal_psnr_vs_{leg}"] = bool(abs(gap) <= 0.3)
+    return out
 
 
 PHASE_KERNEL = {"scatter_priv": "k_scatter_priv", "scatter": "k_scatter", "adam": "k_adam", "encode": "k_encode",
@@ -326,41 +361,139 @@ def roofline_for(precision, res, workload):
             "algorithmic_bytes_per_launch": per_launch, "avg_launch_ms": ph[dom], "other_phases_frac": others}
 
 
-def cpu_baseline(cfg, vol, dims, n_samples):
-    """The float64 oracle, untuned, on one full training step of one block (single thread)."""
+def run_timeseries(torch, DVNR, cfg, precision, n_timesteps, steps_per_t, seed=3):
+    """In situ time series: every timestep of the advected-blob field is compressed by
+    training the previous timestep's model for `steps_per_t` steps (weights kept,
+    Adam moments and step reset: warm start); reports per-timestep latency."""
+    from fixtures import advected_blobs_series_torch
+    n = 256
+    batch = cfg["batch"]
+    series = advected_blobs_series_torch(n, n_timesteps, 16, seed=4)
+    vol = next(series).contiguous()
+    model = DVNR(cfg["enc"], cfg["mlp"], [((n, n, n), 0)], cfg["optim"], precision=precision, max_batch=batch,
+                 seed=seed)
+    model.bind_volumes([vol])
+    vol_bound = model._vols[0]
+    stream = torch.cuda.Stream()
+    lat, psnr = [], []
+    out = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
+    with torch.cuda.stream(stream):
+        model.init_params(1, stream=stream)
+        model.train(5, batch, stream=stream)  # build the plan and the graph
+        model.init_params(1, stream=stream)
+        stream.synchronize()
+        for t in range(n_timesteps):
+            if t > 0:
+                vol_bound.copy_(next(series))
+            stream.synchronize()
+            t0 = time.perf_counter()
+            model.prepare(stream=stream)
+            model.reset_optimizer(stream=stream)
+            model.train(steps_per_t, batch, stream=stream)
+            stream.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e3)
+            model.decode(0, out=out, stream=stream)
+            sse, cnt = model.squared_error(0, out, stream=stream)
+            psnr.append(float(10 * np.log10(cnt / sse)))
+            log(f"[bench] c4 {precision} timestep {t}: {lat[-1]:.1f} ms, psnr {psnr[-1]:.2f} dB")
+        model.sync(stream=stream)
+    del model
+    ms = float(np.mean(lat)) / steps_per_t
+    return dict(ms_per_step=ms, samples_per_s=batch / (ms * 1e-3), latency_ms=lat, psnr_per_t=psnr,
+                psnr=float(np.mean(psnr)), batch=batch)
+
+
+def step_payload_bytes(res):
+    """Algorithmic HBM payload of one mixed-precision step: the per-sample gather,
+    ground-truth and scatter bytes of every sample plus 34 B of Adam traffic per
+    parameter."""
+    return PAYLOAD_BYTES_PER_SAMPLE * res["batch"] + ADAM_BYTES_PER_PARAM["mixed"] * res["n_params"]
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_block_step(task):
+    """One float64 oracle training step of one block (a pool worker, one thread)."""
+    path, dims, ghost, n, seed, block, enc, mlp = task
     from threadpoolctl import threadpool_limits
 
     from fixtures import init_param_draws
     from oracle import dvnr_oracle as o
-    enc, mlp = cfg["enc"], cfg["mlp"]
-    lay = o.layout(o.Encoding(enc.n_levels, enc.n_features, enc.log2_table_size, enc.base_resolution,
-                              enc.per_level_scale, enc.finest_resolution), o.MLP(mlp.n_hidden_layers, mlp.width))
+    vol = np.array(np.load(path, mmap_mode="r"))
+    lay = o.layout(o.Encoding(*enc), o.MLP(*mlp))
     p = init_param_draws(lay.n_table_params, lay.mlp_shapes, seed=1).astype(np.float64)
     st = o.adam_init(lay.n_params)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        x = o.training_coords(3, 0, 0, n_samples)
-        tgt = o.normalized_targets(vol, dims, 0, x)
+        x = o.training_coords(seed, block, 0, n)
+        tgt = o.normalized_targets(vol, dims, ghost, x)
         o.train_step(lay, p, st, o.Optim(lr=1e-2), x, tgt)
-        dt = time.perf_counter() - t0
-    return {"value": n_samples / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full training step ({n_samples} samples, dense Adam over {lay.n_params} params) "
-                      f"of one {dims[0]}x{dims[1]}x{dims[2]} block of the workload, float64 numpy, 1 thread, "
-                      f"{dt:.1f} s"}
+        return time.perf_counter() - t0
+
+
+def cpu_baseline(cfg, blocks, vols, max_workers=16):
+    """The float64 oracle, untuned, on one training step of the workload's first
+    blocks (each with its own apportioned sample count), one block per task over
+    a pool of single-threaded worker processes (at most 16: the machine's CPU share
+    of one GPU)."""
+    import multiprocessing as mp
+    import shutil
+    import tempfile
+
+    from oracle import dvnr_oracle as o
+    nproc = os.cpu_count() or 1
+    workers = max(1, min(max_workers, nproc))
+    nb = len(blocks)
+    n = [cfg["batch"]] if nb == 1 else [int(v) for v in o.apportion([d[0] * d[1] * d[2] for d, _ in blocks],
+                                                                       cfg["batch"])]
+    k = nb if nb <= 2 * workers else 2 * workers
+    enc, mlp = cfg["enc"], cfg["mlp"]
+    e = (enc.n_levels, enc.n_features, enc.log2_table_size, enc.base_resolution, enc.per_level_scale,
+         enc.finest_resolution)
+    tmp = tempfile.mkdtemp(prefix="dvnr_cpu_", dir=os.environ.get("TMPDIR", "/tmp"))
+    try:
+        tasks = []
+        for b in range(k):
+            path = os.path.join(tmp, f"b{b}.npy")
+            np.save(path, vols[b].cpu().numpy())
+            tasks.append((path, blocks[b][0], blocks[b][1], n[b], 3, b, e, (mlp.n_hidden_layers, mlp.width)))
+        used = min(workers, k)
+        with mp.get_context("spawn").Pool(used) as pool:
+            pool.map(_cpu_block_step, tasks[:1])  # workers started and modules imported
+            t0 = time.perf_counter()
+            per = pool.map(_cpu_block_step, tasks, chunksize=1)
+            wall = time.perf_counter() - t0
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    samples = sum(n[:k])
+    return {"value": samples / wall, "unit": "samples/s", "cores": used, "kind": "oracle",
+            "sample": f"one float64 training step (dense Adam) of {k} of the workload's {nb} block(s), "
+                      f"{samples} samples, one block per task over {used} single-threaded worker processes: "
+                      f"{wall:.1f} s wall, {sum(per):.1f} s of worker compute",
+            "nproc": nproc, "cpu_model": _cpu_model()}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 5000 for c2, 2000 for c3)")
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 500 for c3, 2000 for c2)")
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--quality-steps", type=int, default=None,
+                    help="steps of each leg's quality run (default: 1000 for c3, 2000 for c2, 300 for c5)")
     ap.add_argument("--timesteps", type=int, default=40, help="c4: timesteps of the series")
+    ap.add_argument("--legs", default=",".join(LEGS))
+    ap.add_argument("--no-secondary", action="store_true", help="c3: skip the secondary 256^3 record")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precisions", default="mixed,fp32")
-    ap.add_argument("--lr-final", type=float, default=0.1,
-                    help="c2/c3: learning rate at the last timed step as a fraction of the initial 1e-2 "
-                         "(exponential decay over the run; 1 keeps it constant)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy kernel (counter calibration for profiles)")
     args = ap.parse_args()
@@ -368,35 +501,32 @@ def main():
         print("bench.py measures one GPU: the DVNR hot path trains independent per-block models with no "
               "inter-GPU exchange, and this build targets a single MI355X; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    steps = args.steps if args.steps is not None else {"c2": 5000, "c3": 2000, "c4": 500, "c5": 100}[args.workload]
+    wl = args.workload
+    steps = args.steps if args.steps is not None else {"c2": 2000, "c3": 500, "c4": 500, "c5": 50}[wl]
+    qsteps = args.quality_steps if args.quality_steps is not None else {"c2": 2000, "c3": 1000, "c5": 300}.get(wl, 0)
+    legs = [l for l in args.legs.split(",") if l]
     import torch
 
     from paper_2304_10516_amd.dvnr import DVNR
-    if args.workload == "c4":
+    if wl == "c4":
         from paper_2304_10516_amd import presets
         cfg = presets.get("c4")
-        res = {p: run_timeseries(torch, DVNR, cfg, p, args.timesteps, steps) for p in args.precisions.split(",")}
+        precs = ["mixed" if l == "mixed" else "fp32" for l in legs if l in ("mixed", "fp32_plain")]
+        res = {p: run_timeseries(torch, DVNR, cfg, p, args.timesteps, steps) for p in precs}
         head_prec = "mixed" if "mixed" in res else next(iter(res))
         head = res[head_prec]
-        out = {"metric": "train samples/s & decode voxels/s at fixed PSNR; BF16 batched vs FP32 plain",
-               "value": head["samples_per_s"], "unit": "samples/s", "n_gpus": 1, "steps": steps * args.timesteps,
-               "warmup": 5, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-               "vs_baseline": None, "dtype": "bf16" if head_prec == "mixed" else "f32", "data": "synthetic",
+        out = {"metric": METRIC, "value": head["samples_per_s"], "unit": "samples/s", "n_gpus": 1,
+               "steps": steps * args.timesteps, "warmup": 5, "ms_per_step": head["ms_per_step"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "bf16" if head_prec == "mixed" else "f32", "data": "synthetic",
                "config": {"workload": f"in situ time series: {args.timesteps} timesteps of a 256^3 field of 16 "
                                       "Gaussian blobs advected by a seeded divergence-free flow; per timestep "
-                                      f"{steps} warm-started steps of 2^18 samples; c2 model",
+                                      f"{steps} warm-started steps of 2^18 samples; 256^3 model",
                           "name": "c4", "timesteps": args.timesteps, "steps_per_timestep": steps},
                "timestep_latency_ms": {p: r["latency_ms"] for p, r in res.items()},
                "psnr_per_timestep_db": {p: r["psnr_per_t"] for p, r in res.items()}}
         print(json.dumps(out), flush=True)
         return
-    cfg, blocks, vols, desc, host_vol = make_workload(args.workload, torch)
-    if args.workload in ("c2", "c3") and args.lr_final != 1.0:
-        # Adam with exponential learning-rate decay (Sec. III-F): lr 1e-2 * lr_final^(t / steps)
-        import dataclasses
-        cfg["optim"] = dataclasses.replace(cfg["optim"], lr_decay_base=args.lr_final, lr_decay_start=0,
-                                           lr_decay_interval=steps)
-        desc += f"; Adam lr 1e-2 decaying exponentially to {args.lr_final:g} x over the {steps} timed steps"
     if args.calibrate_copy:
         a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -404,13 +534,17 @@ def main():
             torch.mul(a, 1.0, out=b)  # reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         del a, b
-    results = {}
-    for prec in args.precisions.split(","):
-        results[prec] = run_precision(torch, DVNR, cfg, blocks, vols, prec, steps, args.warmup)
-    head_prec = "mixed" if "mixed" in results else next(iter(results))
-    head = results[head_prec]
+    cfg, blocks, vols, desc, results, rec = run_workload(torch, DVNR, wl, legs, steps, args.warmup, qsteps)
+    head_leg = "mixed" if "mixed" in results else legs[0]
+    head = results[head_leg]
+    head_prec = "mixed" if head_leg == "mixed" else "fp32"
+    roof = roofline_for(head_prec, head, wl)
+    if head_prec == "mixed":
+        pay = step_payload_bytes(head)
+        roof["step_payload_bytes"] = pay
+        roof["step_frac"] = pay / (head["ms_per_step"] * 1e-3) / 1e9 / PEAK_HBM_GBS
     out = {
-        "metric": "train samples/s & decode voxels/s at fixed PSNR; BF16 batched vs FP32 plain",
+        "metric": METRIC,
         "value": head["samples_per_s"],
         "unit": "samples/s",
         "n_gpus": 1,
@@ -422,31 +556,41 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16" if head_prec == "mixed" else "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "name": args.workload, "blocks": len(blocks), "batch": cfg["batch"],
-                   "steps": steps, "precision": head_prec},
+        "config": {"workload": desc, "name": wl, "blocks": len(blocks), "batch": cfg["batch"], "steps": steps,
+                   "precision": head_prec, "quality_steps": qsteps},
         "decode_voxels_per_s": head["decode_voxels_per_s"],
         "psnr_db": head["psnr"],
         "phase_ms": head["phase_ms"],
-        "roofline": roofline_for(head_prec, head, args.workload),
+        "roofline": roof,
     }
     if head.get("render"):
         out["render"] = head["render"]
-    if "fp32" in results and "mixed" in results:
-        f = results["fp32"]
-        out["fp32_plain"] = {"samples_per_s": f["samples_per_s"], "ms_per_step": f["ms_per_step"],
-                             "decode_voxels_per_s": f["decode_voxels_per_s"], "psnr_db": f["psnr"],
-                             "phase_ms": f["phase_ms"]}
-        out["speedup_vs_fp32_plain"] = head["samples_per_s"] / f["samples_per_s"]
-        out["psnr_gap_db"] = head["psnr"] - f["psnr"]
+    for leg in legs:
+        if leg != head_leg:
+            out[leg] = rec[leg]
+    for k, v in rec.items():
+        if k.startswith(("speedup_", "psnr_gap_", "equal_psnr_")):
+            out[k] = v
     if not args.no_cpu_baseline:
-        log("[bench] timing the float64 CPU oracle on one full step of one block")
-        if host_vol is None:
-            d, g = blocks[0]
-            host_vol = vols[0][g:g + d[2], g:g + d[1], g:g + d[0]].contiguous().cpu().numpy()
-        d = blocks[0][0]
-        n0 = cfg["batch"] if len(blocks) == 1 else max(256, cfg["batch"] * d[0] * d[1] * d[2] //
-                                                        sum(b[0][0] * b[0][1] * b[0][2] for b in blocks))
-        out["cpu_baseline"] = cpu_baseline(cfg, host_vol, d, n0)
+        log("[bench] timing the float64 CPU oracle on one training step of a subset of the blocks")
+        out["cpu_baseline"] = cpu_baseline(cfg, blocks, vols)
+    del vols
+    torch.cuda.empty_cache()
+    if wl == "c3" and not args.no_secondary:
+        log("[bench] secondary record: the 256^3 workload")
+        q2 = 2000 if args.quality_steps is None else args.quality_steps
+        _, _, v2, d2, r2, rec2 = run_workload(torch, DVNR, "c2", legs, steps, args.warmup, q2)
+        sec = {"workload": d2, "quality_steps": q2}
+        sec.update(rec2)
+        if "mixed" in r2:
+            sec["roofline"] = roofline_for("mixed", r2["mixed"], "c2")
+            pay = step_payload_bytes(r2["mixed"])
+            sec["roofline"]["step_payload_bytes"] = pay
+            sec["roofline"]["step_frac"] = pay / (r2["mixed"]["ms_per_step"] * 1e-3) / 1e9 / PEAK_HBM_GBS
+            if r2["mixed"].get("render"):
+                sec["render"] = r2["mixed"]["render"]
+        out["secondary"] = {"c2": sec}
+        del v2
     print(json.dumps(out), flush=True)
 
 

@@ -50,7 +50,50 @@ def test_traffic_record_scoped_to_workload_and_sources(tmp_path, monkeypatch):
 def test_committed_traffic_records_name_their_workload():
     with open(bench.TRAFFIC_FILE) as fh:
         recs = [json.loads(l.split(":", 1)[1]) for l in fh if l.startswith("traffic-record:")]
-    assert recs and all(r.get("workload") == "c2" and r["kernel"] in bench.KERNEL_SOURCES for r in recs)
+    assert recs and all(r.get("workload") in ("c2", "c3", "c5") and r["kernel"] in bench.KERNEL_SOURCES
+                        for r in recs)
+
+
+def test_step_payload_of_the_batched_and_256cube_workloads():
+    """The step payload: 1568 B per sample (gathers, ground truth, scatter adds)
+    plus 34 B of Adam traffic per parameter -- 7.35 GB for the 64-block step
+    (167.9 M parameters, 2^20 samples), 0.715 GB for the 256^3 step."""
+    c3 = {"batch": 1 << 20, "n_params": 64 * (1308419 * 2 + 6208)}
+    c2 = {"batch": 1 << 18, "n_params": 4461462 * 2 + 6208}
+    assert bench.step_payload_bytes(c3) == pytest.approx(7.35e9, rel=2e-3)
+    assert bench.step_payload_bytes(c2) == pytest.approx(0.715e9, rel=2e-3)
+
+
+def test_leg_records_and_equal_psnr():
+    legs = {"mixed": dict(samples_per_s=4e8, psnr=37.0), "fp32_plain": dict(samples_per_s=1e8, psnr=36.8),
+            "fp32_same_plan": dict(samples_per_s=2e8, psnr=36.5)}
+    base = dict(ms_per_step=1.0, decode_voxels_per_s=1.0, quality_ms_per_step=1.0, phase_ms={}, bins_per_axis=2,
+                priv_levels=5, part_levels=5)
+    for r in legs.values():
+        r.update(base)
+    rec = {leg: bench.leg_record(r) for leg, r in legs.items()}
+    assert rec["mixed"]["plan"] == {"bins_per_axis": 2, "priv_levels": 5, "part_from_level": 5}
+    out = bench.speedups(legs)
+    assert out["speedup_vs_fp32_plain"] == pytest.approx(4.0) and out["speedup_vs_fp32_same_plan"] == pytest.approx(2.0)
+    assert out["equal_psnr_vs_fp32_plain"] and not out["equal_psnr_vs_fp32_same_plan"]
+
+
+def test_cpu_baseline_pool_runs_the_oracle():
+    """The CPU baseline's worker pool (spawned processes, one block per task) on
+    a tiny two-block configuration: samples of the blocks processed, cores and
+    host recorded."""
+    import numpy as np
+    import torch
+
+    from paper_2304_10516_amd.dvnr import EncodingCfg, MlpCfg, OptimCfg
+    cfg = dict(enc=EncodingCfg(4, 2, 12, 4, 2.0), mlp=MlpCfg(1, 16), optim=OptimCfg(lr=1e-2), batch=1024)
+    blocks = [((12, 10, 9), 1), ((9, 11, 14), 1)]
+    rng = np.random.default_rng(0)
+    vols = [torch.tensor(rng.random((d[2] + 2, d[1] + 2, d[0] + 2), dtype=np.float32)) for d, _ in blocks]
+    r = bench.cpu_baseline(cfg, blocks, vols, max_workers=2)
+    assert r["kind"] == "oracle" and r["unit"] == "samples/s" and r["value"] > 0
+    assert r["cores"] == 2 and r["nproc"] >= 1 and r["cpu_model"]
+    assert "1024 samples" in r["sample"]
 
 
 def test_more_than_one_gpu_is_refused():
