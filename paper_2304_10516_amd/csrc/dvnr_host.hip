@@ -846,6 +846,8 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
     pa.b2 = (float)h->opt.beta2;
     pa.eps = (float)h->opt.eps;
     pa.wd = (float)h->opt.weight_decay;
+    pa.omb1 = (float)(1.0 - h->opt.beta1);
+    pa.omb2 = (float)(1.0 - h->opt.beta2);
     pa.ln_b1 = (float)std::log(h->opt.beta1);
     pa.ln_b2 = (float)std::log(h->opt.beta2);
     pa.log2_decay = h->opt.lr_decay_interval > 0 ? (float)std::log2(h->opt.lr_decay_base) : 0.0f;

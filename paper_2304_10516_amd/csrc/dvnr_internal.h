@@ -178,6 +178,7 @@ struct PartAdam {
   uint16_t* work16;
   const Counters* ctr;
   float lr0, b1, b2, eps, wd;
+  float omb1, omb2;        // 1 - b1, 1 - b2, evaluated on the host and rounded once
   float ln_b1, ln_b2;      // log(b1), log(b2), evaluated on the host
   float log2_decay;        // log2 of the learning-rate decay base
   int64_t decay_start, decay_interval;

@@ -444,9 +444,9 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
                                               P* __restrict__ vel, uint16_t* __restrict__ work16,
                                               int64_t block_stride, int64_t n_table, int64_t n_used,
                                               const BlockPlan* __restrict__ plan, const Counters* __restrict__ ctr,
-                                              P lr0, P b1, P b2, P eps, P wd, P ln_b1, P ln_b2, P log2_decay,
-                                              int64_t decay_start, int64_t decay_interval, int64_t skip0,
-                                              int64_t skip1) {
+                                              P lr0, P b1, P b2, P omb1, P omb2, P eps, P wd, P ln_b1,
+                                              P ln_b2, P log2_decay, int64_t decay_start,
+                                              int64_t decay_interval, int64_t skip0, int64_t skip1) {
   // grid (element groups of the block, blocks): no division per element, one
   // uniform skip for a block that drew no sample this step
   const int b = blockIdx.y;
@@ -509,8 +509,8 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
     }
     if (keep[k]) continue;
     const P gg = g[k] + wd * th[k];
-    m[k] = b1 * m[k] + (P(1) - b1) * gg;
-    v[k] = b2 * v[k] + (P(1) - b2) * gg * gg;
+    m[k] = b1 * m[k] + omb1 * gg;
+    v[k] = b2 * v[k] + omb2 * gg * gg;
     th[k] = th[k] - lr * (m[k] * bc1) / (sqrt(v[k] * bc2) + eps);
     g[k] = 0;
   }
@@ -561,18 +561,21 @@ hipError_t launch_adam(Prec p, void* params, void* grad, void* m, void* v, uint1
     gx = pre + std::max<int64_t>(0, (n_used - base + 1023) / 1024);
   }
   const dim3 grid((unsigned)gx, (unsigned)n_blocks);
-  // logarithms of the decay rates and of the learning-rate decay base, once on the host
+  // once on the host: 1 - b (rounded once, not formed from the rounded b: with
+  // b2 = 0.999, 1 - (float)b2 is 1.3e-5 away from 1 - b2), the logarithms of
+  // the decay rates and of the learning-rate decay base
+  const double omb1 = 1.0 - b1, omb2 = 1.0 - b2;
   const double ln_b1 = std::log(b1), ln_b2 = std::log(b2);
   const double log2_decay = decay_interval > 0 ? std::log2(decay_base) : 0.0;
   if (p == Prec::F64)
     hipLaunchKernelGGL(k_adam<double>, grid, dim3(256), 0, s, (double*)params, (double*)grad, (double*)m, (double*)v,
-                       nullptr, block_stride, n_table_params, n_used, plan, ctr, lr, b1, b2, eps, wd, ln_b1, ln_b2,
-                       log2_decay, decay_start, decay_interval, skip0, skip1);
+                       nullptr, block_stride, n_table_params, n_used, plan, ctr, lr, b1, b2, omb1, omb2, eps, wd,
+                       ln_b1, ln_b2, log2_decay, decay_start, decay_interval, skip0, skip1);
   else
     hipLaunchKernelGGL(k_adam<float>, grid, dim3(256), 0, s, (float*)params, (float*)grad, (float*)m, (float*)v,
                        work16, block_stride, n_table_params, n_used, plan, ctr, (float)lr, (float)b1, (float)b2,
-                       (float)eps, (float)wd, (float)ln_b1, (float)ln_b2, (float)log2_decay, decay_start,
-                       decay_interval, skip0, skip1);
+                       (float)omb1, (float)omb2, (float)eps, (float)wd, (float)ln_b1, (float)ln_b2,
+                       (float)log2_decay, decay_start, decay_interval, skip0, skip1);
   return hipGetLastError();
 }
 

@@ -380,8 +380,8 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
       const int i = tid + NT * (k0 + k);
       if (i >= nf) continue;
       const float gg = gv[k] + ldexpf((float)(long long)acc[i], -K) + adam.wd * th[k];
-      const float m1 = adam.b1 * mm[k] + (1.0f - adam.b1) * gg;
-      const float v1 = adam.b2 * vv[k] + (1.0f - adam.b2) * gg * gg;
+      const float m1 = adam.b1 * mm[k] + adam.omb1 * gg;
+      const float v1 = adam.b2 * vv[k] + adam.omb2 * gg * gg;
       const float t1 = th[k] - lr * (m1 * bc1) / (sqrtf(v1 * bc2) + adam.eps);
       const int64_t e = el0 + i;
       adam.params[e] = t1;

@@ -14,6 +14,7 @@ import torch
 from fixtures import adversarial_coords, gaussian_sum_field, init_param_draws, uniform_coords
 from oracle import dvnr_oracle as o
 from tests import precision_model as pm
+from tests.adam_bound import adam_bound, excess_report
 
 pytestmark = pytest.mark.gpu
 
@@ -391,11 +392,9 @@ def test_block_without_samples_partitioned_c2(empty):
     pr = before[full].cpu().numpy().astype(np.float64)
     st, opt = o.adam_init(lay.n_params), o.Optim(lr=1e-2)
     _, g, _ = o.loss_and_grad(lay, pr, x, o.normalized_targets(vols[full], (64, 64, 64), 0, x))
-    small = np.abs(g) < 1e-5 * np.abs(g).max()
-    ref = o.adam(pr, g, st, opt)
-    d = np.abs(model.block_params(full).cpu().numpy().astype(np.float64) - ref)
-    assert np.max(d[~small]) <= 1e-4 * opt.lr + 1e-7
-    assert np.mean(d[small] <= opt.lr * 1.01) == 1.0
+    ref, bar = adam_bound(pr, [g], opt)
+    got = model.block_params(full).cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= bar), excess_report(got, ref, bar, [g])
     assert float(model.grads.abs().max()) == 0.0
 
 
@@ -446,21 +445,19 @@ def test_adam_update_parity_c1(decay):
     st = o.adam_init(lay.n_params)
     opt = o.Optim(lr=1e-2, lr_decay_base=0.5, lr_decay_start=1, lr_decay_interval=1) if decay else o.Optim(lr=1e-2)
     pr = model.block_params(0).cpu().numpy().astype(np.float64)
-    gmax_hist = []
-    small = np.zeros(lay.n_params, bool)
+    p_start, grads = pr.copy(), []
     for step in range(3):
         x = o.training_coords(77, 0, step, 4096)
         model.train_step_coords(dev(x), [4096])
         tgt = o.normalized_targets(vol, (64, 64, 64), 0, x)
         L, g, _ = o.loss_and_grad(lay, pr, x, tgt)
-        gmax_hist.append(np.abs(g).max())
-        small |= np.abs(g) < 1e-5 * np.abs(g).max()  # update direction ill-conditioned there
+        grads.append(g)
         pr = o.adam(pr, g, st, opt)
     torch.cuda.synchronize()
-    pg = model.block_params(0).cpu().numpy().astype(np.float64)
-    d = np.abs(pg - pr)
-    assert np.max(d[~small]) <= 1e-4 * opt.lr * 3 + 1e-7
-    assert np.mean(d[small] <= 3 * opt.lr * 1.01) == 1.0
+    ref, bar = adam_bound(p_start, grads, opt)
+    assert np.array_equal(ref, pr)
+    got = model.block_params(0).cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= bar), excess_report(got, ref, bar, grads)
 
 
 @pytest.mark.parametrize("decay", [False, True])
@@ -489,7 +486,7 @@ def test_adam_fused_in_slice_pass_c2(decay):
         model.set_option("part_adam", fused)
         pr = model.block_params(0).cpu().numpy().astype(np.float64)
         st, opt = o.adam_init(lay.n_params), o.Optim(**kw)
-        small = np.zeros(lay.n_params, bool)
+        p_start, grads = pr.copy(), []
         for step in range(3):
             x = o.training_coords(91, 0, step, 8192)
             model.train_step_coords(dev(x), [8192])
@@ -497,13 +494,12 @@ def test_adam_fused_in_slice_pass_c2(decay):
             if step == 0:
                 first[fused] = model.block_params(0).cpu().numpy().astype(np.float64)
             L, g, _ = o.loss_and_grad(lay, pr, x, o.normalized_targets(vol, (64, 64, 64), 0, x))
-            small |= np.abs(g) < 1e-5 * np.abs(g).max()
+            grads.append(g)
             pr = o.adam(pr, g, st, opt)
         torch.cuda.synchronize()
         out[fused] = model.block_params(0).cpu().numpy().astype(np.float64)
-        d = np.abs(out[fused] - pr)
-        assert np.max(d[~small]) <= 1e-4 * opt.lr * 3 + 1e-7
-        assert np.mean(d[small] <= 3 * opt.lr * 1.01) == 1.0
+        ref, bar = adam_bound(p_start, grads, opt)
+        assert np.all(np.abs(out[fused] - ref) <= bar), excess_report(out[fused], ref, bar, grads)
         assert float(model.grads.abs().max()) == 0.0  # every gradient is left at zero for the next step
     # after the first step: the partitioned levels' sums are fixed point (order
     # independent), so both ways apply Adam to the same gradient there (later
@@ -754,7 +750,7 @@ def test_autograd_training_with_the_fused_adam_step():
     ref = [model.block_params(b).cpu().numpy().astype(np.float64) for b in range(2)]
     states = [o.adam_init(lay.n_params) for _ in range(2)]
     opt = o.Optim(lr=1e-2)
-    small = np.zeros(lay.n_params, bool)
+    p_start, grads = ref[1].copy(), []
     for step in range(2):
         x = o.training_coords(3, 1, step, 2048)
         tgt = o.normalized_targets(vol, (32, 32, 32), 0, x)
@@ -769,13 +765,14 @@ def test_autograd_training_with_the_fused_adam_step():
         model.adam_step()
         L, g, _ = o.loss_and_grad(lay, ref[1], x, tgt)
         assert abs(loss.item() - L) <= 1e-5 * L
-        small |= np.abs(g) < 1e-5 * np.abs(g).max()
+        grads.append(g)
         ref[1] = o.adam(ref[1], g, states[1], opt)
         ref[0] = o.adam(ref[0], np.zeros(lay.n_params), states[0], opt)
     torch.cuda.synchronize()
-    d1 = np.abs(model.block_params(1).cpu().numpy().astype(np.float64) - ref[1])
-    assert np.max(d1[~small]) <= 1e-4 * opt.lr * 2 + 1e-7
-    assert np.all(d1[small] <= 2 * opt.lr * 1.01)
+    exact, bar = adam_bound(p_start, grads, opt)
+    assert np.array_equal(exact, ref[1])
+    got = model.block_params(1).cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref[1]) <= bar), excess_report(got, ref[1], bar, grads)
     d0 = np.abs(model.block_params(0).cpu().numpy().astype(np.float64) - ref[0])
     assert np.max(d0) <= 1e-7
     assert float(model.grads.abs().max()) == 0.0  # the Adam step leaves the gradient at zero

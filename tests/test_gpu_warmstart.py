@@ -20,6 +20,7 @@ import torch
 
 from fixtures import advected_blobs_field, init_param_draws
 from oracle import dvnr_oracle as o
+from tests.adam_bound import adam_bound, excess_report
 
 pytestmark = pytest.mark.gpu
 
@@ -79,12 +80,11 @@ def test_warm_start_first_gradient_and_update(series):
     model.reset_optimizer()
     model.train(1, BATCH)
     torch.cuda.synchronize()
-    ref = o.adam(p1, g, o.adam_init(lay.n_params), o.Optim(lr=1e-2))
-    d = np.abs(model.block_params(0).cpu().numpy().astype(np.float64) - ref)
-    small = np.abs(g) < 1e-5 * np.abs(g).max()  # the update direction is ill-conditioned there
-    say(f"first warm update: largest deviation {d[~small].max():.2e} (lr 1e-2)")
-    assert np.max(d[~small]) <= 1e-4 * 1e-2 + 1e-7
-    assert np.all(d[small] <= 1e-2 * 1.01)
+    ref, bar = adam_bound(p1, [g], o.Optim(lr=1e-2))
+    got = model.block_params(0).cpu().numpy().astype(np.float64)
+    say(f"first warm update: largest distance {np.abs(got - ref).max():.2e}")
+    assert np.all(np.abs(got - ref) <= bar), excess_report(got, ref, bar, [g])
+    small = np.abs(g) < 1e-5 * np.abs(g).max()
     # the t = 1 update moves every well-conditioned entry by about lr (Adam's first step)
     assert np.median(np.abs(ref - p1)[~small]) > 0.5e-2
 
