@@ -198,3 +198,39 @@ def check_mixed_gradient(gpu_grad, lay, params, x, target, loss="l2", follow=0.1
     assert we <= excess * werr + floor + slack, \
         f"weights: {we:.2e} from the exact gradient (intrinsic {werr:.2e}, kink slack {slack:.1e})"
     return out
+
+
+def infer(lay, params, x):
+    """Normalized INR output with the mixed path's roundings of the forward
+    (features and hidden-layer inputs in bfloat16, float32 activations);
+    `params` is the working copy."""
+    W = o.mlp_weights(lay, params)
+    a = round_bf16(round_f32(o.encode(lay, params, x)))
+    for k in range(len(W) - 1):
+        z, _ = o.mlp_forward([W[k]], a)
+        h = round_f32(np.maximum(z, 0.0))
+        a = round_bf16(h) if k + 2 < len(W) else h
+    out, _ = o.mlp_forward([W[-1]], a)
+    return out[:, 0]
+
+
+def decode(lay, params, dims, vmin, vmax, chunk=1 << 16):
+    """oracle.decode with the mixed path's forward (`infer`) on the working
+    copy of the float64 masters `params`."""
+    wc = working_copy(lay, params)
+    x = o.voxel_center_coords(dims)
+    out = np.concatenate([infer(lay, wc, x[i:i + chunk]) for i in range(0, len(x), chunk)])
+    return (out * (vmax - vmin) + vmin).reshape(dims[2], dims[1], dims[0])
+
+
+def train(lay, params0, vol, dims, ghost, n_steps, batch, seed, opt, block=0):
+    """oracle.train's loop (uniform samples, L2) with the mixed path's
+    roundings: each step's gradient is `loss_and_grad` on the working copy of
+    the float64 masters, and the oracle's Adam updates the masters."""
+    p = np.asarray(params0, np.float64).copy()
+    st = o.adam_init(p.size)
+    for step in range(n_steps):
+        x = o.training_coords(seed, block, step, batch)
+        _, g = loss_and_grad(lay, working_copy(lay, p), x, o.normalized_targets(vol, dims, ghost, x))
+        p = o.adam(p, g, st, opt)
+    return p

@@ -10,7 +10,8 @@ is then replaced by timestep 1 in place, the value range recomputed and the
 optimizer reset.  Checked against the oracle started from the GPU's
 parameters with a fresh Adam state: the first step's gradient (fp32, 1e-5),
 the first update (the bars of the plain Adam test) and, after 100
-warm-started steps, the reconstruction PSNR (0.3 dB, fp32 and mixed).
+warm-started steps, the reconstruction PSNR (0.3 dB; for mixed precision
+against the oracle trained under the mixed path's rounding model).
 """
 import sys
 
@@ -20,6 +21,7 @@ import torch
 
 from fixtures import advected_blobs_field, init_param_draws
 from oracle import dvnr_oracle as o
+from tests import precision_model as pm
 from tests.adam_bound import adam_bound, excess_report
 
 pytestmark = pytest.mark.gpu
@@ -89,16 +91,11 @@ def test_warm_start_first_gradient_and_update(series):
     assert np.median(np.abs(ref - p1)[~small]) > 0.5e-2
 
 
-@pytest.mark.parametrize("precision", ["fp32", "mixed"])
-def test_warm_started_psnr_within_03db(series, precision):
-    say(f"warm-started training {precision}: 100 steps on timestep 1")
-    model, lay = _trained_on_t0(precision, series)
+def test_warm_started_psnr_within_03db_fp32(series):
+    say("warm-started training fp32: 100 steps on timestep 1")
+    model, lay = _trained_on_t0("fp32", series)
     p1 = model.block_params(0).cpu().numpy().astype(np.float64)
-    model.train(100, BATCH)
-    dec = model.decode(0)
-    sse, cnt = model.squared_error(0, dec)
-    torch.cuda.synchronize()
-    gpu_psnr = o.psnr(sse, cnt)
+    gpu_psnr = _warm_psnr(model)
     vol1 = series[1]
     params, losses, _ = o.train(lay, p1, vol1, (N, N, N), 0, n_steps=100, batch=BATCH, seed=SEED,
                                 opt=o.Optim(lr=1e-2))
@@ -109,3 +106,42 @@ def test_warm_started_psnr_within_03db(series, precision):
     assert abs(gpu_psnr - ref_psnr) <= 0.3
     assert ref_psnr > cold  # the warm-started run improved on the cached weights
     model.sync()
+
+
+def _warm_psnr(model):
+    model.train(100, BATCH)
+    dec = model.decode(0)
+    sse, cnt = model.squared_error(0, dec)
+    torch.cuda.synchronize()
+    return o.psnr(sse, cnt)
+
+
+def test_warm_started_psnr_within_03db_mixed(series):
+    """Mixed precision ends this run near 61 dB, where bf16 rounding decides
+    part of the error and the trajectory is chaotic: the oracle trained under
+    the mixed path's rounding model (tests/precision_model.py) from the same
+    start ends anywhere in about 61.37-61.52 dB when its start moves by
+    float32 rounding, and one GPU run in eight has ended 0.4 dB below the
+    others.  The compared quantities are therefore medians: of five GPU runs,
+    and of three rounding-model runs from the first GPU run's start, perturbed
+    by 2^-24 relative (the size of a float32 summation-order difference)."""
+    say("warm-started training mixed: 5 runs of 100 steps on timestep 1")
+    gpu, starts = [], []
+    for r in range(5):
+        model, lay = _trained_on_t0("mixed", series)
+        starts.append(model.block_params(0).cpu().numpy().astype(np.float64))
+        gpu.append(_warm_psnr(model))
+        model.sync()
+    vol1 = series[1]
+    vmin, vmax = o.block_value_range(vol1)
+    rng = np.random.default_rng(5)
+    ref = []
+    for r in range(3):
+        p1 = starts[0] * (1.0 + (2.0 ** -24) * rng.standard_normal(starts[0].size)) if r else starts[0]
+        params = pm.train(lay, p1, vol1, (N, N, N), 0, 100, BATCH, SEED, o.Optim(lr=1e-2))
+        ref.append(o.psnr(*o.squared_error(pm.decode(lay, params, (N, N, N), vmin, vmax), vol1)))
+    cold = o.psnr(*o.squared_error(pm.decode(lay, starts[0], (N, N, N), vmin, vmax), vol1))
+    say("psnr gpu " + " ".join(f"{v:.3f}" for v in gpu) + " | rounding model " + " ".join(f"{v:.3f}" for v in ref)
+        + f" | timestep-0 model on timestep 1 {cold:.3f}")
+    assert abs(float(np.median(gpu)) - float(np.median(ref))) <= 0.3
+    assert min(gpu) > cold

@@ -111,3 +111,46 @@ def test_mixed_gradient_bars_catch_a_level_error():
     bad[nt:nt + 100] *= 1.05
     with pytest.raises(AssertionError, match="weights"):
         pm.check_mixed_gradient(bad, lay, pw, x, tgt)
+
+
+def test_mixed_forward_is_the_oracle_when_every_rounding_is_exact():
+    """pm.infer rounds features and hidden-layer inputs to bf16 and activations
+    to fp32: with tables, weights and coordinates chosen so that every one of
+    those values is already a bf16 number, it equals the oracle's forward
+    exactly; a non-representable weight makes them differ.  Levels R = 3, 5:
+    coordinates k/4 are vertices of the fine level and cell midpoints (weights
+    1/2) of the coarse one; tables in quarters and first-layer weights of
+    +-1/2 keep features and hidden values within 8 significant bits."""
+    enc, mlp = o.Encoding(2, 2, 10, 3, 5.0 / 3.0), o.MLP(2, 16)
+    lay = o.layout(enc, mlp)
+    assert [lv.R for lv in lay.levels] == [3, 5]
+    rng = np.random.default_rng(3)
+    p = np.empty(lay.n_params)
+    nt = lay.n_table_params
+    (o1, o2, o3) = lay.mlp_offsets
+    p[:nt] = rng.integers(-4, 5, nt) / 4.0
+    p[o1:o2] = rng.integers(-1, 2, o2 - o1) / 2.0
+    p[o2:o3] = rng.integers(-1, 2, o3 - o2) / 4.0
+    p[o3:] = rng.integers(-8, 9, lay.n_params - o3) / 16.0
+    assert np.array_equal(pm.working_copy(lay, p), p)
+    x = (rng.integers(0, 5, (300, 3)) / 4.0).astype(np.float32)
+    ref = o.infer(lay, p, x)
+    assert np.array_equal(pm.infer(lay, p, x), ref) and np.abs(ref).max() > 0
+    q = p.copy()
+    q[o1:o2] += rng.uniform(-1, 1, o2 - o1) * 2.0 ** -10  # first-layer weights off the bf16 grid
+    assert not np.array_equal(pm.infer(lay, pm.working_copy(lay, q), x), o.infer(lay, q, x))
+
+
+def test_mixed_training_loop_takes_the_rounded_gradient_and_the_oracle_adam():
+    enc, mlp = C1
+    lay = o.layout(enc, mlp)
+    vol = gaussian_sum_field(16, seed=1)
+    p0 = init_param_draws(lay.n_table_params, lay.mlp_shapes, seed=0).astype(np.float64)
+    assert np.array_equal(pm.train(lay, p0, vol, (16, 16, 16), 0, 0, 256, 5, o.Optim()), p0)
+    p = pm.train(lay, p0, vol, (16, 16, 16), 0, 2, 256, 5, o.Optim())
+    st, q = o.adam_init(lay.n_params), p0.copy()
+    for step in range(2):
+        x = o.training_coords(5, 0, step, 256)
+        _, g = pm.loss_and_grad(lay, pm.working_copy(lay, q), x, o.normalized_targets(vol, (16, 16, 16), 0, x))
+        q = o.adam(q, g, st, o.Optim())
+    assert np.array_equal(p, q)
