@@ -19,7 +19,8 @@
  *    (allocated by the caller, e.g. with torch); "host" pointers are ordinary
  *    host memory.  The library allocates no device memory of its own: the
  *    caller sizes the buffers with dvnr_get_sizes() and hands them over with
- *    dvnr_bind().  Device buffers must be 256-byte aligned.
+ *    dvnr_bind().  Device buffers must be 256-byte aligned.  The one device
+ *    array the library holds is the static scratch of dvnr_render_static.
  *  - Every entry point that launches work takes a hipStream_t (passed as
  *    void*; NULL = the default stream) and only enqueues; no entry point
  *    synchronizes except dvnr_sync() and dvnr_mse_fp64() (which returns a host
@@ -272,6 +273,24 @@ typedef struct dvnr_render_params {
 dvnr_status dvnr_render_workspace_bytes(const dvnr_t* h, int32_t width, int32_t height, int64_t* bytes);
 dvnr_status dvnr_render(dvnr_t* h, int32_t block, const dvnr_camera* cam, const dvnr_render_params* params,
                         const float* tf, void* workspace, float* image, int64_t* samples_out, void* stream);
+
+/* dvnr_render for callers that cannot allocate device memory (code under
+ * stream or graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same renderer and the same image, but the per-ray state (the
+ * `workspace` of dvnr_render) lives in one static device array of the library,
+ * one copy per GPU, sized for at most DVNR_RENDER_STATIC_MAX_RAYS pixels
+ * (width * height; 28 MiB of device memory per GPU the library runs on, held
+ * until the process ends).  Larger images: DVNR_E_INVALID, nothing enqueued.
+ * Calls no allocator.  The first call on a device looks up that device's copy
+ * (the current device) and may return DVNR_E_HIP if that fails.  Every call on
+ * one GPU, from any handle or thread, shares that GPU's array and the array
+ * keeps the last call's contents; calls that overlap on one GPU (different
+ * streams or threads) race and must be serialized by the caller.  The
+ * handle's own bound workspace carries the sample batches, as in
+ * dvnr_render.  Synchronizes `stream`. */
+#define DVNR_RENDER_STATIC_MAX_RAYS (1 << 20)
+dvnr_status dvnr_render_static(dvnr_t* h, int32_t block, const dvnr_camera* cam, const dvnr_render_params* params,
+                               const float* tf, float* image, int64_t* samples_out, void* stream);
 
 /* Sliding-window model cache (Sec. III-E weight caching; Sec. IV temporal
  * caching): snapshots of the trained models of past timesteps, kept on the

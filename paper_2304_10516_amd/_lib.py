@@ -100,6 +100,7 @@ SIGNATURES = {
     "dvnr_cache_snapshot_bytes": [P, C.POINTER(C.c_int64)],
     "dvnr_render_workspace_bytes": [P, I32, I32, C.POINTER(C.c_int64)],
     "dvnr_render": [P, I32, C.POINTER(Camera), C.POINTER(RenderParams), VP, VP, VP, C.POINTER(C.c_int64), VP],
+    "dvnr_render_static": [P, I32, C.POINTER(Camera), C.POINTER(RenderParams), VP, VP, C.POINTER(C.c_int64), VP],
     "dvnr_cache_bind": [P, I32, VP],
     "dvnr_cache_push": [P, I64, VP],
     "dvnr_cache_keys": [P, C.POINTER(C.c_int64), C.POINTER(C.c_int32)],

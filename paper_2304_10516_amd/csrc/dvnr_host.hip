@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1166,7 +1167,7 @@ dvnr_status dvnr_draw_training_samples(dvnr_t* h, int32_t block, int64_t step, i
 }
 
 // INR output at `n` coordinates of block b (chunks of max_batch), de-normalized.
-static int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+static constexpr int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
 // Parameters a query reads: the inference copy of every block (the fp16 / bf16
 // working copy for mixed precision, fp32 masters otherwise) and the block
@@ -1246,7 +1247,7 @@ dvnr_status dvnr_decode(dvnr_t* h, int32_t block, float* out, void* stream) {
 // ---------------------------------------------------------------------------
 // Direct volume rendering (sample streaming)
 // ---------------------------------------------------------------------------
-static int64_t render_ws_bytes(int64_t n) {
+static constexpr int64_t render_ws_bytes(int64_t n) {
   // directions [n][3], (t0, t1) [n][2], two active-ray lists [n], two counters
   return align256(12 * n) + align256(8 * n) + 2 * align256(4 * n) + 256;
 }
@@ -1258,20 +1259,28 @@ dvnr_status dvnr_render_workspace_bytes(const dvnr_t* h, int32_t width, int32_t 
   return DVNR_OK;
 }
 
-dvnr_status dvnr_render(dvnr_t* h, int32_t block, const dvnr_camera* cam, const dvnr_render_params* rp,
-                        const float* tf, void* workspace, float* image, int64_t* samples_out, void* stream) {
+// Argument checks shared by both render entry points (the workspace aside).
+static dvnr_status render_args(dvnr_t* h, int32_t block, const dvnr_camera* cam, const dvnr_render_params* rp,
+                               const float* tf, float* image) {
+  dvnr_status st = access_ready(h, block);
+  if (st) return st;
+  if (!cam || !rp || !tf || !image) return fail(DVNR_E_INVALID, "null argument");
+  if (cam->width < 1 || cam->height < 1 || (int64_t)cam->width * cam->height > (1 << 28))
+    return fail(DVNR_E_INVALID, "bad image size");
+  if (!(cam->fovy_deg > 0.0f && cam->fovy_deg < 180.0f)) return fail(DVNR_E_INVALID, "fovy must be in (0, 180)");
+  if (!(rp->step > 0.0f) || !(rp->ref_step > 0.0f) || rp->n_tf < 2 || !(rp->tf_hi > rp->tf_lo) ||
+      !(rp->alpha_stop > 0.0f && rp->alpha_stop <= 1.0f) || rp->samples_per_round < 1 ||
+      rp->samples_per_round > h->max_batch)
+    return fail(DVNR_E_INVALID, "bad render parameters");
+  return DVNR_OK;
+}
+
+// The renderer proper on a checked argument set; `workspace` holds
+// render_ws_bytes(width * height) bytes, 256-byte aligned.
+static dvnr_status render_impl(dvnr_t* h, int32_t block, const dvnr_camera* cam, const dvnr_render_params* rp,
+                               const float* tf, void* workspace, float* image, int64_t* samples_out, void* stream) {
   try {
-    dvnr_status st = access_ready(h, block);
-    if (st) return st;
-    if (!cam || !rp || !tf || !workspace || !image) return fail(DVNR_E_INVALID, "null argument");
-    if (cam->width < 1 || cam->height < 1 || (int64_t)cam->width * cam->height > (1 << 28))
-      return fail(DVNR_E_INVALID, "bad image size");
-    if (!(cam->fovy_deg > 0.0f && cam->fovy_deg < 180.0f)) return fail(DVNR_E_INVALID, "fovy must be in (0, 180)");
-    if (!(rp->step > 0.0f) || !(rp->ref_step > 0.0f) || rp->n_tf < 2 || !(rp->tf_hi > rp->tf_lo) ||
-        !(rp->alpha_stop > 0.0f && rp->alpha_stop <= 1.0f) || rp->samples_per_round < 1 ||
-        rp->samples_per_round > h->max_batch)
-      return fail(DVNR_E_INVALID, "bad render parameters");
-    if (((uintptr_t)workspace) % 256) return fail(DVNR_E_INVALID, "workspace must be 256-byte aligned");
+    dvnr_status st = DVNR_OK;
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = (int64_t)cam->width * cam->height;
     char* ws = (char*)workspace;
@@ -1320,6 +1329,55 @@ dvnr_status dvnr_render(dvnr_t* h, int32_t block, const dvnr_camera* cam, const 
   } catch (...) {
     return fail(DVNR_E_INVALID, "render failed");
   }
+}
+
+dvnr_status dvnr_render(dvnr_t* h, int32_t block, const dvnr_camera* cam, const dvnr_render_params* rp,
+                        const float* tf, void* workspace, float* image, int64_t* samples_out, void* stream) {
+  dvnr_status st = render_args(h, block, cam, rp, tf, image);
+  if (st) return st;
+  if (!workspace) return fail(DVNR_E_INVALID, "null workspace");
+  if (((uintptr_t)workspace) % 256) return fail(DVNR_E_INVALID, "workspace must be 256-byte aligned");
+  return render_impl(h, block, cam, rp, tf, workspace, image, samples_out, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Rendering without a caller workspace: the ray state lives in one static
+// device array per GPU.  Host code never passes `scratch` itself to a kernel
+// (on the host its name is only a stand-in for the symbol): its device address
+// is looked up once per device and used instead.
+// ---------------------------------------------------------------------------
+static constexpr int64_t kRenderStaticBytes = render_ws_bytes(DVNR_RENDER_STATIC_MAX_RAYS);  // 28 MiB + 256 B
+static __device__ __align__(256) char scratch[kRenderStaticBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_ptr;  // per device ordinal; nullptr until looked up
+
+// Device address of this GPU's `scratch` (the current device's copy).
+static dvnr_status static_scratch(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || ((uintptr_t)p) % 256) return fail(DVNR_E_HIP, "static render scratch has no aligned device address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DVNR_OK;
+}
+
+dvnr_status dvnr_render_static(dvnr_t* h, int32_t block, const dvnr_camera* cam, const dvnr_render_params* rp,
+                               const float* tf, float* image, int64_t* samples_out, void* stream) {
+  dvnr_status st = render_args(h, block, cam, rp, tf, image);
+  if (st) return st;
+  if ((int64_t)cam->width * cam->height > DVNR_RENDER_STATIC_MAX_RAYS)
+    return fail(DVNR_E_INVALID, "dvnr_render_static: image larger than DVNR_RENDER_STATIC_MAX_RAYS pixels");
+  void* ws = nullptr;
+  st = static_scratch(&ws);
+  if (st) return st;
+  return render_impl(h, block, cam, rp, tf, ws, image, samples_out, stream);
 }
 
 // ---------------------------------------------------------------------------

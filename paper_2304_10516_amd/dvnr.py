@@ -267,22 +267,33 @@ class DVNR:
     # -- direct volume rendering ----------------------------------------------------
     def render(self, block: int, eye, center, up, fovy_deg: float, width: int, height: int, tf: torch.Tensor,
                tf_range, step: float, ref_step: float | None = None, alpha_stop: float = 1.0,
-               samples_per_round: int = 64, stream=None) -> torch.Tensor:
+               samples_per_round: int = 64, stream=None, static_scratch: bool = False,
+               out: torch.Tensor | None = None) -> torch.Tensor:
         """Front-to-back ray marching of block `block`'s INR through a pinhole
         camera (unit-cube coordinates of the block); tf: [n][4] RGBA over
-        tf_range.  Returns the premultiplied RGBA image [height][width][4]."""
+        tf_range (float32, on the device).  Returns the premultiplied RGBA image
+        [height][width][4] (written into `out` when given).  static_scratch:
+        call dvnr_render_static, which keeps the ray state in the library's
+        static device array instead of a workspace allocated here."""
         cam = L.Camera((C.c_float * 3)(*eye), (C.c_float * 3)(*center), (C.c_float * 3)(*up), float(fovy_deg),
                        int(width), int(height))
         tf = tf.to(device=self.device, dtype=torch.float32).contiguous()
         rp = L.RenderParams(float(step), float(ref_step if ref_step is not None else step), float(alpha_stop),
                             float(tf_range[0]), float(tf_range[1]), int(tf.shape[0]), int(samples_per_round))
-        nb = C.c_int64()
-        L.check(self.lib.dvnr_render_workspace_bytes(self.h, int(width), int(height), C.byref(nb)))
-        ws, off = _aligned_empty(nb.value, self.device)
-        img = torch.empty((height, width, 4), dtype=torch.float32, device=self.device)
+        if out is not None and (tuple(out.shape) != (height, width, 4) or out.dtype != torch.float32
+                                or not out.is_contiguous() or out.device.type != "cuda"):
+            raise ValueError("out must be a contiguous float32 device tensor of shape (height, width, 4)")
+        img = out if out is not None else torch.empty((height, width, 4), dtype=torch.float32, device=self.device)
         n = C.c_int64()
-        L.check(self.lib.dvnr_render(self.h, block, C.byref(cam), C.byref(rp), tf.data_ptr(), ws.data_ptr() + off,
-                                     img.data_ptr(), C.byref(n), _stream_ptr(stream)))
+        if static_scratch:
+            L.check(self.lib.dvnr_render_static(self.h, block, C.byref(cam), C.byref(rp), tf.data_ptr(),
+                                                img.data_ptr(), C.byref(n), _stream_ptr(stream)))
+        else:
+            nb = C.c_int64()
+            L.check(self.lib.dvnr_render_workspace_bytes(self.h, int(width), int(height), C.byref(nb)))
+            ws, off = _aligned_empty(nb.value, self.device)
+            L.check(self.lib.dvnr_render(self.h, block, C.byref(cam), C.byref(rp), tf.data_ptr(),
+                                         ws.data_ptr() + off, img.data_ptr(), C.byref(n), _stream_ptr(stream)))
         self.last_render_samples = n.value
         return img
 
