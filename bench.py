@@ -32,8 +32,14 @@ the default workload the 256^3 workload is measured as a secondary record.
 The float64 CPU oracle is timed on one training step of a subset of the
 blocks, over a pool of worker processes (blocks are independent).
 
+Before the workload, the measurement kernels of include/dvnr_micro.h give
+the attainable rate of each phase's access pattern (streaming copy, random
+gathers and fp32 atomics at several table footprints, bf16 MFMA); the line
+reports them under "micro" and each phase's fraction of its own pattern's
+rate under roofline.phases_vs_micro (`--no-micro` skips them).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c4|c5]
-                       [--quality-steps Q] [--no-secondary] [--no-cpu-baseline]
+                       [--quality-steps Q] [--no-secondary] [--no-cpu-baseline] [--no-micro]
                        [--legs mixed,fp32_plain,fp32_same_plan]
 Prints one JSON line.
 """
@@ -403,6 +409,116 @@ def run_timeseries(torch, DVNR, cfg, precision, n_timesteps, steps_per_t, seed=3
                 psnr=float(np.mean(psnr)), batch=batch)
 
 
+MICRO_FOOTPRINTS_MB = (4, 16, 64, 256, 1024)
+
+
+def micro_rates(torch):
+    """Attainable rates of the step's access patterns (include/dvnr_micro.h),
+    timed with HIP events on the stream the kernels run on: streaming copy
+    (plain and non-temporal), random 4-byte gathers and random fp32 atomic adds
+    (scattered and in groups of 4 consecutive lanes) at several table
+    footprints, and the dense bf16 MFMA rate."""
+    import ctypes as C
+
+    from paper_2304_10516_amd import _lib as L
+    lib = L.lib()
+    st = torch.cuda.Stream()
+    sp = C.c_void_p(st.cuda_stream)
+
+    def timed(launch, reps=5):
+        with torch.cuda.stream(st):
+            launch()  # warm
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(reps):
+                launch()
+            e1.record(st)
+        st.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    def ok(code):
+        if code != 0:
+            raise RuntimeError(f"micro kernel returned {code}")
+
+    out = {}
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for nt in (0, 1):
+        t = timed(lambda: ok(lib.dvnr_micro_copy(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
+                                                 C.c_int64(nbytes), nt, sp)))
+        out["copy_nontemporal_gbs" if nt else "copy_gbs"] = 2 * nbytes / t / 1e9
+    del a, b
+    n_threads, per = 1 << 21, 64
+    res = torch.empty(n_threads, dtype=torch.int32, device="cuda")
+    gather, atomic, atomic4 = {}, {}, {}
+    for mb in MICRO_FOOTPRINTS_MB:
+        n = (mb << 20) // 4
+        tab = torch.zeros(n, dtype=torch.float32, device="cuda")
+        t = timed(lambda: ok(lib.dvnr_micro_gather(C.c_void_p(tab.data_ptr()), C.c_int64(n), C.c_int64(n_threads),
+                                                   per, 12345, C.c_void_p(res.data_ptr()), sp)))
+        gather[f"{mb}MB"] = n_threads * per / t / 1e9
+        for grp, dst in ((1, atomic), (4, atomic4)):
+            t = timed(lambda: ok(lib.dvnr_micro_atomic(C.c_void_p(tab.data_ptr()), C.c_int64(n),
+                                                       C.c_int64(n_threads), 16, grp, 777, sp)), reps=3)
+            dst[f"{mb}MB"] = n_threads * 16 / t / 1e9
+        del tab
+    out["gather_4byte_g_per_s"] = gather
+    out["atomic_fp32_g_per_s"] = atomic
+    out["atomic_fp32_groups_of_4_g_per_s"] = atomic4
+    nwg, iters = 4096, 2000
+    o = torch.empty(nwg * 256, dtype=torch.float32, device="cuda")
+    t = timed(lambda: ok(lib.dvnr_micro_mfma_bf16(C.c_int64(nwg), iters, C.c_void_p(o.data_ptr()), sp)), reps=3)
+    out["mfma_bf16_tflops"] = nwg * 4 * iters * 8 * 16384 / t / 1e12
+    torch.cuda.empty_cache()
+    log("[bench] micro: copy {:.0f} GB/s (non-temporal {:.0f}), gather {} G/s, atomics {} G/s, groups of 4 {} G/s, "
+        "bf16 MFMA {:.0f} TFLOP/s".format(out["copy_gbs"], out["copy_nontemporal_gbs"],
+                                          {k: round(v, 1) for k, v in gather.items()},
+                                          {k: round(v, 1) for k, v in atomic.items()},
+                                          {k: round(v, 1) for k, v in atomic4.items()}, out["mfma_bf16_tflops"]))
+    return out
+
+
+def _footprint_key(nbytes):
+    """The smallest measured footprint at least as large as nbytes (the largest otherwise)."""
+    for mb in MICRO_FOOTPRINTS_MB:
+        if nbytes <= mb << 20:
+            return f"{mb}MB"
+    return f"{MICRO_FOOTPRINTS_MB[-1]}MB"
+
+
+def phases_vs_micro(precision, res, micro):
+    """Each phase's rate against the attainable rate of its own access pattern:
+    encode (table lookups, one per corner, level and sample) against random
+    4-byte gathers at the step's table footprint; the direct-atomic backward
+    (scatter) against random fp32 atomics at that footprint; the MLP against
+    the measured bf16 MFMA rate; the streaming phases (sampling, bucketing,
+    slice pass, Adam) against the non-temporal copy."""
+    ph, batch = res["phase_ms"], res["batch"]
+    te = 4 if precision == "mixed" else 8  # bytes per table entry: F = 2 fp16 or fp32 values
+    table_bytes = sum(res["level_entries"]) * te * res["n_blocks"]
+    key = _footprint_key(table_bytes)
+    out = {"table_footprint_bytes": table_bytes, "footprint_point": key}
+    if ph.get("encode", 0) > 0:
+        rate = batch * L_LEVELS * 8 / (ph["encode"] * 1e-3) / 1e9
+        out["encode"] = {"g_lookups_per_s": rate, "micro": micro["gather_4byte_g_per_s"][key],
+                         "frac": rate / micro["gather_4byte_g_per_s"][key]}
+    nd = res["part_levels"] - res["priv_levels"]
+    if ph.get("scatter", 0) > 0.01 and nd > 0:
+        rate = batch * nd * 8 * F_FEAT / (ph["scatter"] * 1e-3) / 1e9
+        out["scatter"] = {"g_atomics_per_s": rate, "micro": micro["atomic_fp32_g_per_s"][key],
+                          "frac": rate / micro["atomic_fp32_g_per_s"][key]}
+    if ph.get("mlp", 0) > 0 and precision == "mixed":
+        tf = 37248.0 * batch / (ph["mlp"] * 1e-3) / 1e12
+        out["mlp"] = {"tflops": tf, "micro": micro["mfma_bf16_tflops"], "frac": tf / micro["mfma_bf16_tflops"]}
+    for k in ("sample", "part_bucket", "part_accum", "adam"):
+        bts = phase_bytes(precision, k, res)
+        if bts and ph.get(k, 0) > 0:
+            gbs = bts / (ph[k] * 1e-3) / 1e9
+            out[k] = {"gbs": gbs, "micro": micro["copy_nontemporal_gbs"], "frac": gbs / micro["copy_nontemporal_gbs"]}
+    return out
+
+
 def step_payload_bytes(res):
     """Algorithmic HBM payload of one mixed-precision step: the per-sample gather,
     ground-truth and scatter bytes of every sample plus 34 B of Adam traffic per
@@ -494,6 +610,7 @@ def main():
     ap.add_argument("--legs", default=",".join(LEGS))
     ap.add_argument("--no-secondary", action="store_true", help="c3: skip the secondary 256^3 record")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-micro", action="store_true", help="skip the measurement kernels (roofline denominators)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy kernel (counter calibration for profiles)")
     args = ap.parse_args()
@@ -534,11 +651,14 @@ def main():
             torch.mul(a, 1.0, out=b)  # reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         del a, b
+    micro = None if args.no_micro else micro_rates(torch)
     cfg, blocks, vols, desc, results, rec = run_workload(torch, DVNR, wl, legs, steps, args.warmup, qsteps)
     head_leg = "mixed" if "mixed" in results else legs[0]
     head = results[head_leg]
     head_prec = "mixed" if head_leg == "mixed" else "fp32"
     roof = roofline_for(head_prec, head, wl)
+    if micro:
+        roof["phases_vs_micro"] = phases_vs_micro(head_prec, head, micro)
     if head_prec == "mixed":
         pay = step_payload_bytes(head)
         roof["step_payload_bytes"] = pay
@@ -563,6 +683,8 @@ def main():
         "phase_ms": head["phase_ms"],
         "roofline": roof,
     }
+    if micro:
+        out["micro"] = micro
     if head.get("render"):
         out["render"] = head["render"]
     for leg in legs:
@@ -587,6 +709,8 @@ def main():
             pay = step_payload_bytes(r2["mixed"])
             sec["roofline"]["step_payload_bytes"] = pay
             sec["roofline"]["step_frac"] = pay / (r2["mixed"]["ms_per_step"] * 1e-3) / 1e9 / PEAK_HBM_GBS
+            if micro:
+                sec["roofline"]["phases_vs_micro"] = phases_vs_micro("mixed", r2["mixed"], micro)
             if r2["mixed"].get("render"):
                 sec["render"] = r2["mixed"]["render"]
         out["secondary"] = {"c2": sec}

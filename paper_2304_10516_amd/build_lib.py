@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdvnr.so")
 SOURCES = ["dvnr_host.hip", "k_core.hip", "k_mlp.hip", "k_sort.hip", "k_decode.hip", "k_render.hip", "k_encode_bin.hip",
-           "k_scatter_part.hip"]
+           "k_scatter_part.hip", "micro.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

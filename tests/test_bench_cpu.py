@@ -100,3 +100,27 @@ def test_more_than_one_gpu_is_refused():
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert p.returncode == 2 and "one GPU" in p.stderr and p.stdout == ""
+
+
+def test_phases_against_the_measured_rates_of_their_access_patterns():
+    """Encode lookups against random gathers at the smallest measured footprint
+    that holds the tables (the 64 MB point for the 17.8 MB fp16 tables of the
+    256^3 workload), the MLP against the measured MFMA rate, streaming phases
+    against the non-temporal copy."""
+    res = _res()
+    res["phase_ms"] = {"encode": 0.08, "mlp": 0.064, "part_accum": 0.1, "part_bucket": 0.07, "scatter": 0.0,
+                       "sample": 0.04, "adam": 0.01}
+    pts = {f"{mb}MB": float(mb) for mb in bench.MICRO_FOOTPRINTS_MB}
+    micro = {"copy_nontemporal_gbs": 5000.0, "copy_gbs": 4000.0, "gather_4byte_g_per_s": pts,
+             "atomic_fp32_g_per_s": pts, "atomic_fp32_groups_of_4_g_per_s": pts, "mfma_bf16_tflops": 2000.0}
+    r = bench.phases_vs_micro("mixed", res, micro)
+    table = sum(res["level_entries"]) * 4
+    assert r["table_footprint_bytes"] == table and 16 << 20 < table <= 64 << 20 and r["footprint_point"] == "64MB"
+    lookups = (1 << 18) * 16 * 8 / 0.08e-3 / 1e9
+    assert r["encode"]["g_lookups_per_s"] == pytest.approx(lookups)
+    assert r["encode"]["frac"] == pytest.approx(lookups / 64.0)
+    assert r["mlp"]["frac"] == pytest.approx(37248.0 * (1 << 18) / 0.064e-3 / 1e12 / 2000.0)
+    gbs = bench.phase_bytes("mixed", "part_accum", res) / 0.1e-3 / 1e9
+    assert r["part_accum"]["frac"] == pytest.approx(gbs / 5000.0)
+    assert "scatter" not in r  # no direct-atomic levels in this plan
+    assert bench._footprint_key(1) == "4MB" and bench._footprint_key(1 << 40) == "1024MB"
