@@ -442,6 +442,9 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *                          (default 1 for mixed, 0 for fp32); enables the
  *                          bin-privatized backward of the coarse levels
  *  "priv_levels"     n   : privatize levels [0, n) (-1: chosen per plan)
+ *  "sort_bins"       n   : spatial bins per axis of ordered sampling, 1..8
+ *                          (0, the default: the most that keep at least 192
+ *                          samples per bin in the block with the fewest)
  *  "scatter_concurrent" 0/1 : run the privatized levels whose bin boxes never
  *                          fit LDS (direct atomics) on a second stream,
  *                          concurrently with the others (default 0)
@@ -452,7 +455,7 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *                          classes (small boxes, large boxes, direct) instead
  *                          of one launch (-1, the default: by class when the
  *                          destination-partitioned backward takes the fine
- *                          levels, one launch otherwise)
+ *                          levels of a single block, one launch otherwise)
  *  "scatter_strided" 0/1 : direct backward over ordered samples takes each
  *                          tile's samples strided across the block (default 1)
  *  "decode_fused"    0/1 : decode with the fused brick kernel (default 1)
@@ -471,7 +474,7 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *                          each bucket in LDS, instead of one global atomic per
  *                          contribution.  Levels with more than 256 slices stay
  *                          on the atomic paths, and so do levels with fewer
- *                          than 2^15 entries (the workspace holds buckets
+ *                          than 2^12 entries (the workspace holds buckets
  *                          for the others: about 40 (1 + F) bytes per
  *                          sample of max_batch and level).
  *  "part_slice"      n   : fp32 accumulators per slice: 4096, 8192 (default)

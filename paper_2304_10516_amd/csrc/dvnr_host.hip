@@ -84,9 +84,10 @@ struct dvnr {
   // spatially ordered sampling and bin-privatized scatter of the coarse levels
   int spatial_sort = 0;
   int priv_levels = -1;  // -1: chosen per plan
+  int sort_bins = 0;     // bins per axis of ordered sampling (0: at least kBinSamples samples per bin)
   int sort_B = 0, priv_L = 0, n_groups = 0;
   int priv_small = 0, priv_direct = 0;  // LDS classes: small [0, priv_small), large up to priv_direct, then direct
-  int priv_classes = -1;  // launch the privatized levels by LDS class (0: one launch; -1: when partitioned)
+  int priv_classes = -1;  // launch the privatized levels by LDS class (0: one launch; -1: one block, partitioned)
   int encode_binned = 1;                // ordered samples: LDS-staged encoding of the levels whose box fits
   int enc_binned = 0;                   // levels [0, enc_binned) of the current plan
   std::vector<Tile> hgroups;
@@ -531,10 +532,11 @@ static std::vector<int64_t> apportion(const dvnr_t* h, int64_t total) {
 static int64_t boundary_count(int64_t n, double frac) { return (int64_t)std::floor(frac * (double)n + 0.5); }
 
 // Levels of the destination-partitioned backward and their bucket layout.
-// Auto choice (mixed precision): the longest suffix of the levels from
-// part_min (tables of at least kPartMinEntries entries, sized into the
-// workspace) whose tables receive at least one contribution per entry per
-// step on average over the sampled blocks.  Only levels with at most
+// Auto choice (mixed precision): the longest suffix of the levels with at
+// least kPartAutoMinEntries entries whose tables receive at least one
+// contribution per entry per step on average over the sampled blocks.  The
+// workspace holds buckets from part_min (tables of at least kPartMinEntries
+// entries), so "scatter_part" may ask for coarser levels too.  Only levels with at most
 // kPartMaxSlices slices qualify.
 static dvnr_status plan_partition(dvnr_t* h, const std::vector<int64_t>& n, hipStream_t s) {
   const int L = h->enc.n_levels, F = h->enc.n_features;
@@ -550,7 +552,9 @@ static dvnr_status plan_partition(dvnr_t* h, const std::vector<int64_t>& n, hipS
   if (h->scatter_part >= 0) {
     lf = std::min(h->scatter_part, L);
   } else if (h->prec == Prec::MIXED) {
-    while (lf > h->part_min && 8.0 * avg >= (double)level_entries(h, lf - 1)) --lf;
+    while (lf > h->part_min && level_entries(h, lf - 1) >= kPartAutoMinEntries &&
+           8.0 * avg >= (double)level_entries(h, lf - 1))
+      --lf;
   }
   lf = std::max(lf, h->part_min);
   for (int l = lf; l < L; ++l)
@@ -669,9 +673,10 @@ static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_
   }
   h->n_groups = (int)h->hgroups.size();
   if (h->n_groups > h->max_groups) return fail(DVNR_E_INVALID, "too many sort groups");
-  // about 512 samples per bin
+  // at least kBinSamples samples per bin in the block with the fewest
   int B = 1;
-  while (B < 8 && (int64_t)(B + 1) * (B + 1) * (B + 1) * 512 <= min_n) ++B;
+  while (B < 8 && (int64_t)(B + 1) * (B + 1) * (B + 1) * kBinSamples <= min_n) ++B;
+  if (h->sort_bins > 0) B = h->sort_bins;
   h->sort_B = B;
   // Ordered sampling privatizes every level by default: a (bin, level)
   // workgroup accumulates in LDS when the bin's cell box fits, and otherwise
@@ -882,11 +887,12 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
     // priv_classes 0: one launch (large class) for all privatized levels, so that
     // the LDS-bound coarse and the atomic-bound fine levels overlap on the chip;
     // -1 (default): by class when the partitioned backward has taken the fine
-    // levels (only coarse ones are left, and the small-box class runs at higher
-    // occupancy beside the partitioned passes); scatter_concurrent: the
-    // direct-class levels on the second stream instead
+    // levels of a single block (only coarse ones are left, and the small-box
+    // class runs at higher occupancy beside the partitioned passes; with many
+    // blocks one launch measured faster); scatter_concurrent: the direct-class
+    // levels on the second stream instead
     const bool conc = h->scatter_concurrent != 0;
-    const bool classes = h->priv_classes > 0 || (h->priv_classes < 0 && lf < h->enc.n_levels);
+    const bool classes = h->priv_classes > 0 || (h->priv_classes < 0 && lf < h->enc.n_levels && h->nb == 1);
     const int a = classes ? std::min(h->priv_small, lp) : 0;
     const int c = classes || conc ? std::min(std::max(h->priv_direct, a), lp) : lp;
     if (conc && c < lp) {
@@ -1748,6 +1754,10 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
     h->decode_fused = value ? 1 : 0;
   } else if (n == "spatial_sort") {
     h->spatial_sort = value ? 1 : 0;
+  } else if (n == "sort_bins") {
+    if (value < 0 || value > 8) return fail(DVNR_E_INVALID, "sort_bins: 0 (automatic) or 1..8");
+    h->sort_bins = (int)value;
+    h->plan_total = -1;
   } else if (n == "priv_levels") {
     h->priv_levels = (int)std::max<int64_t>(-1, std::min<int64_t>(value, kMaxLevels));
     h->plan_total = -1;  // recompute the plan's privatized level count

@@ -12,6 +12,7 @@ constexpr int kTile = 256;        // samples per tile (work item of the training
 constexpr int kMlpGrid = 256;     // workgroups of the persistent MLP kernel (one per CU)
 constexpr int kLossRing = 1024;   // steps of per-block loss history kept on the device
 constexpr int kMaxBins = 512;     // spatial bins per block (B^3, B <= 8) of the ordered sampler
+constexpr int kBinSamples = 192;  // fewest samples per bin the automatic bin count keeps
 constexpr int kSortGroup = 1024;  // samples per counting-sort group
 constexpr int kPrivCells = 4096;  // cells of a bin's box in the privatized backward (LDS counters)
 constexpr int kPrivVertFloats = 8192;  // box vertices x features accumulated in LDS
@@ -130,7 +131,8 @@ hipError_t launch_scatter(Prec gp, const LevelDesc& ld, int l0, int l1, const Bl
 // bucket q = qbase[l] + s of that block (nq buckets per block).
 constexpr int kPartSliceMax = 16384;  // accumulators of one slice (64 KB of LDS)
 constexpr int kPartMaxSlices = 256;   // slices of one level
-constexpr int kPartMinEntries = 1 << 15;  // smallest table that may be partitioned
+constexpr int kPartMinEntries = 1 << 12;      // smallest table that may be partitioned ("scatter_part")
+constexpr int kPartAutoMinEntries = 1 << 15;  // smallest table the automatic choice partitions
 constexpr int kPartSub = 16;          // sub-buckets per bucket (tile t appends to sub-bucket t % kPartSub)
 constexpr int kPartSliceRecords = 16384;  // records per slice the slice sizes aim at
 struct PartDesc {

@@ -287,7 +287,7 @@ def test_sorted_sampling_gradient_parity_fine_levels(precision, classes, waves, 
     model.set_option("use_graph", 0)
     loss = model.train(1, n, want_loss=True)
     torch.cuda.synchronize()
-    bins = max(B for B in range(1, 9) if B ** 3 * 512 <= n)  # about 512 samples per bin
+    bins = max(B for B in range(1, 9) if B ** 3 * 192 <= n)  # at least 192 samples per bin
     assert model.plan_info() == ((bins, lf) if sort else (0, 0))
     assert model.partitioned_levels() == lf
     x = o.training_coords(91, 0, 0, n)
