@@ -125,19 +125,29 @@ hipError_t launch_sample(const BlockMeta* meta, const BlockRange* range, const B
 }
 
 // ===========================================================================
-// Encoding forward: one thread per (sample, level); level-major workgroups.
+// Encoding forward: two lanes per (sample, level); level-major workgroups of
+// one tile (kTile samples) and one level.
 // y[l*F + f] = sum_c w_c * table[(off_l + idx_c) * F + f]
+// Lane cx of a sample's pair gathers the four corners with that x offset, so
+// that one load instruction reads both x-neighbours of a (cy, cz) pair from
+// adjacent lanes: adjacent entries on dense levels, and on hashed levels
+// entries that differ in their low index bits only (the x prime is 1), which
+// mostly share a cache line and are served by one request.  Each lane sums its
+// four corners in the order (cy, cz) = (0,0), (1,0), (0,1), (1,1); the pair's
+// sums are added (cx = 0 first).
 // ===========================================================================
 template <typename TT, typename WT, typename OT, int F>
-__global__ __launch_bounds__(256) void k_encode(LevelDesc ld, const BlockMeta* __restrict__ meta,
-                                                const Tile* __restrict__ tiles, int n_tiles, int64_t n_direct,
-                                                int direct_block, const BlockPlan* __restrict__ plan,
-                                                const float* __restrict__ coords, const TT* __restrict__ table,
-                                                OT* __restrict__ out, int64_t ss, int64_t ls, int xcd_map,
-                                                int l0, int nl) {
+__global__ __launch_bounds__(2 * kTile) void k_encode(LevelDesc ld, const BlockMeta* __restrict__ meta,
+                                                      const Tile* __restrict__ tiles, int n_tiles, int64_t n_direct,
+                                                      int direct_block, const BlockPlan* __restrict__ plan,
+                                                      const float* __restrict__ coords, const TT* __restrict__ table,
+                                                      OT* __restrict__ out, int64_t ss, int64_t ls, int xcd_map,
+                                                      int l0, int nl) {
   int tile, l;
   if (!level_major_item(blockIdx.x, l0, nl, n_tiles, xcd_map, tile, l)) return;
-  const SampleRef r = sample_ref(tiles, plan, tile, n_direct, direct_block, threadIdx.x);
+  const uint32_t cx = threadIdx.x & 1;
+  // both lanes of a pair share the sample, so they leave together
+  const SampleRef r = sample_ref(tiles, plan, tile, n_direct, direct_block, threadIdx.x >> 1);
   if (!r.valid) return;
   const float x = coords[3 * r.gi + 0], y = coords[3 * r.gi + 1], z = coords[3 * r.gi + 2];
   int ix, iy, iz;
@@ -148,29 +158,41 @@ __global__ __launch_bounds__(256) void k_encode(LevelDesc ld, const BlockMeta* _
   grid_pos(z, ld.scale[l], R, iz, tz);
   const TT* tab = table + (meta ? meta[r.block].param_off : 0) + (int64_t)ld.off[l] * F;
   const int dense = ld.dense[l];
+  const WT wx = cx ? (WT)tx : (WT)1 - (WT)tx;
+  const WT wy[2] = {(WT)1 - (WT)ty, (WT)ty};
+  const WT wz[2] = {(WT)1 - (WT)tz, (WT)tz};
+  TT v[4][F];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {  // loads first, all in flight together
+    const uint32_t cy = k & 1, cz = k >> 1;
+    const uint32_t e = corner_index(dense, R, ld.T_mask, ix + cx, iy + cy, iz + cz);
+#pragma unroll
+    for (int f = 0; f < F; ++f) v[k][f] = tab[(int64_t)e * F + f];
+  }
   WT acc[F];
 #pragma unroll
   for (int f = 0; f < F; ++f) acc[f] = 0;
-  const WT wx[2] = {(WT)1 - (WT)tx, (WT)tx};
-  const WT wy[2] = {(WT)1 - (WT)ty, (WT)ty};
-  const WT wz[2] = {(WT)1 - (WT)tz, (WT)tz};
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const uint32_t cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
-    const uint32_t e = corner_index(dense, R, ld.T_mask, ix + cx, iy + cy, iz + cz);
-    const WT w = wx[cx] * wy[cy] * wz[cz];
-    const TT* p = tab + (int64_t)e * F;
+  for (int k = 0; k < 4; ++k) {
+    const WT w = wx * wy[k & 1] * wz[k >> 1];
 #pragma unroll
     for (int f = 0; f < F; ++f) {
       if constexpr (sizeof(WT) == 8)
-        acc[f] += w * to_d(p[f]);
+        acc[f] += w * to_d(v[k][f]);
       else
-        acc[f] += w * to_f(p[f]);
+        acc[f] += w * to_f(v[k][f]);
     }
   }
-  OT* o = out + r.gi * ss + (int64_t)l * ls;
 #pragma unroll
-  for (int f = 0; f < F; ++f) o[f] = (OT)acc[f];
+  for (int f = 0; f < F; ++f) {
+    const WT o = __shfl_xor(acc[f], 1, 64);
+    acc[f] = cx ? o + acc[f] : acc[f] + o;  // (cx = 0 sum) + (cx = 1 sum) on both lanes
+  }
+  if (cx == 0) {
+    OT* o = out + r.gi * ss + (int64_t)l * ls;
+#pragma unroll
+    for (int f = 0; f < F; ++f) o[f] = (OT)acc[f];
+  }
 }
 
 template <typename TT, typename WT, typename OT>
@@ -182,10 +204,10 @@ static hipError_t enc_dispatch(const LevelDesc& ld, const BlockMeta* meta, const
   const TT* t = (const TT*)table;
   OT* o = (OT*)out;
   switch (ld.F) {
-    case 1: hipLaunchKernelGGL((k_encode<TT, WT, OT, 1>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
-    case 2: hipLaunchKernelGGL((k_encode<TT, WT, OT, 2>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
-    case 4: hipLaunchKernelGGL((k_encode<TT, WT, OT, 4>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
-    case 8: hipLaunchKernelGGL((k_encode<TT, WT, OT, 8>), dim3(grid), dim3(kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
+    case 1: hipLaunchKernelGGL((k_encode<TT, WT, OT, 1>), dim3(grid), dim3(2 * kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
+    case 2: hipLaunchKernelGGL((k_encode<TT, WT, OT, 2>), dim3(grid), dim3(2 * kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
+    case 4: hipLaunchKernelGGL((k_encode<TT, WT, OT, 4>), dim3(grid), dim3(2 * kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
+    case 8: hipLaunchKernelGGL((k_encode<TT, WT, OT, 8>), dim3(grid), dim3(2 * kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -87,9 +87,11 @@ __global__ __launch_bounds__(256) void k_encode_binned(LevelDesc ld, int l0, int
     const int lx = ix - bo[0], ly = iy - bo[1], lz = iz - bo[2];
     const bool in_box = staged && (unsigned)lx < (unsigned)bn[0] && (unsigned)ly < (unsigned)bn[1] &&
                         (unsigned)lz < (unsigned)bn[2];
-    float acc[F];
+    // the tile encoding's order: per x offset cx, the four (cy, cz) corners in
+    // order (0,0), (1,0), (0,1), (1,1); then (cx = 0 sum) + (cx = 1 sum)
+    float acc[2][F];
 #pragma unroll
-    for (int f = 0; f < F; ++f) acc[f] = 0.0f;
+    for (int f = 0; f < F; ++f) acc[0][f] = acc[1][f] = 0.0f;
     const float wx[2] = {1.0f - tx, tx};
     const float wy[2] = {1.0f - ty, ty};
     const float wz[2] = {1.0f - tz, tz};
@@ -100,17 +102,17 @@ __global__ __launch_bounds__(256) void k_encode_binned(LevelDesc ld, int l0, int
       if (in_box) {
         const TT* p = box + (int64_t)((lx + cx) + vx * ((ly + cy) + vy * (lz + cz))) * F;
 #pragma unroll
-        for (int f = 0; f < F; ++f) acc[f] += w * enc_val(p[f]);
+        for (int f = 0; f < F; ++f) acc[cx][f] += w * enc_val(p[f]);
       } else {
         const uint32_t e = corner_index(dense, R, ld.T_mask, ix + cx, iy + cy, iz + cz);
         const TT* p = tab + (int64_t)e * F;
 #pragma unroll
-        for (int f = 0; f < F; ++f) acc[f] += w * enc_val(p[f]);
+        for (int f = 0; f < F; ++f) acc[cx][f] += w * enc_val(p[f]);
       }
     }
     OT* o = out + gi * ss + (int64_t)l * ls;
 #pragma unroll
-    for (int f = 0; f < F; ++f) o[f] = (OT)acc[f];
+    for (int f = 0; f < F; ++f) o[f] = (OT)(acc[0][f] + acc[1][f]);
   }
 }
 

@@ -236,13 +236,14 @@ def test_sorted_sampling_gradient_parity(precision, priv, classes, binned):
 
 
 # (precision, LDS classes, MLP waves, concurrent, ordered, scatter_part, bucket cap, slice floats,
-#  first partitioned level expected: the first with 2^15 entries is level 4)
+#  first partitioned level expected: scatter_part = 0 asks for every level, and every level of this
+#  encoding has at least the 2^12 entries a partitioned table needs)
 FINE_CASES = [("fp32", 0, 1, 0, 1, -1, 0, 8192, 16), ("fp32", 1, 1, 0, 1, -1, 0, 8192, 16),
               ("fp32", 0, 1, 1, 1, -1, 0, 8192, 16), ("mixed", 0, 1, 0, 1, -1, 0, 8192, 16),
               ("mixed", 0, 2, 0, 1, -1, 0, 8192, 16), ("mixed", 1, 1, 1, 1, -1, 0, 8192, 16),
               # destination-partitioned levels: fine only, every eligible one (ordered and not),
               # tiny buckets (most records overflow into direct atomics), other slice sizes
-              ("fp32", 0, 1, 0, 1, 9, 0, 8192, 9), ("fp32", 0, 1, 0, 1, 0, 0, 8192, 4),
+              ("fp32", 0, 1, 0, 1, 9, 0, 8192, 9), ("fp32", 0, 1, 0, 1, 0, 0, 8192, 0),
               ("fp32", 0, 1, 0, 0, 6, 0, 16384, 6), ("fp32", 0, 1, 0, 1, 9, 8, 8192, 9),
               ("fp32", 0, 1, 0, 0, 12, 0, 4096, 12), ("mixed", 0, 1, 0, 1, 9, 0, 8192, 9),
               # 16384 samples, 64 slices per level: 4 sub-buckets per bucket
@@ -307,9 +308,9 @@ def test_sorted_sampling_gradient_parity_fine_levels(precision, classes, waves, 
 
 
 # (features, precision, ordered sampling, scatter_part, first partitioned level expected)
-WIDTH_CASES = [(1, "fp32", 1, 0, 2), (4, "fp32", 1, 0, 2), (8, "fp32", 1, 0, 2), (4, "fp32", 0, 0, 2),
-               (8, "fp32", 1, -1, 4), (1, "mixed", 1, 0, 2), (4, "mixed", 1, 0, 2), (8, "mixed", 1, 0, 2),
-               (4, "fp32", 1, 3, 3)]
+WIDTH_CASES = [(1, "fp32", 1, 2, 2), (4, "fp32", 1, 2, 2), (8, "fp32", 1, 2, 2), (4, "fp32", 0, 2, 2),
+               (8, "fp32", 1, -1, 4), (1, "mixed", 1, 2, 2), (4, "mixed", 1, 2, 2), (8, "mixed", 1, 2, 2),
+               (4, "fp32", 1, 3, 3), (4, "fp32", 1, 0, 0), (1, "mixed", 1, 0, 0)]
 
 
 @pytest.mark.parametrize("F,precision,sort,part,lf", WIDTH_CASES)
@@ -317,10 +318,12 @@ def test_feature_width_gradient_parity(F, precision, sort, part, lf):
     """Feature widths other than 2 (L F <= 32: 8 levels of 1 or 4 features, 4
     levels of 8), base 16, scale 1.5, T = 2^17: levels 0-2 dense (level 2:
     36^3 entries, the first with at least 2^15), 3 and up hashed with 2^17
-    entries, so with scatter_part 0 levels 2 and up take the
+    entries, so with scatter_part 2 levels 2 and up take the
     destination-partitioned backward (unpacked (1 + F)-word records for
-    F != 2), the coarse ones the bin-privatized or plain scatter.  One step of
-    8192 samples against the oracle's float64 gradient."""
+    F != 2), the coarse ones the bin-privatized or plain scatter; scatter_part
+    0 partitions every level (each has at least the 2^12 entries a
+    partitioned table needs).  One step of 8192 samples against the oracle's
+    float64 gradient."""
     L = 4 if F == 8 else 8
     cfg = (o.Encoding(L, F, 17, 16, 1.5), o.MLP(2, 32))
     say(f"feature width {F} ({L} levels) {precision}: ordered {sort}, partitioned from level {part}")

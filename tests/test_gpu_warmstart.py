@@ -10,8 +10,8 @@ is then replaced by timestep 1 in place, the value range recomputed and the
 optimizer reset.  Checked against the oracle started from the GPU's
 parameters with a fresh Adam state: the first step's gradient (fp32, 1e-5),
 the first update (the bars of the plain Adam test) and, after 100
-warm-started steps, the reconstruction PSNR (0.3 dB; for mixed precision
-against the oracle trained under the mixed path's rounding model).
+warm-started steps, the reconstruction PSNR (0.3 dB; mixed precision on a
+field that keeps the model away from its bf16 floor).
 """
 import sys
 
@@ -19,7 +19,7 @@ import numpy as np
 import pytest
 import torch
 
-from fixtures import advected_blobs_field, init_param_draws
+from fixtures import advected_blobs_field, init_param_draws, kolmogorov_field
 from oracle import dvnr_oracle as o
 from tests import precision_model as pm
 from tests.adam_bound import adam_bound, excess_report
@@ -116,32 +116,43 @@ def _warm_psnr(model):
     return o.psnr(sse, cnt)
 
 
-def test_warm_started_psnr_within_03db_mixed(series):
-    """Mixed precision ends this run near 61 dB, where bf16 rounding decides
-    part of the error and the trajectory is chaotic: the oracle trained under
-    the mixed path's rounding model (tests/precision_model.py) from the same
-    start ends anywhere in about 61.37-61.52 dB when its start moves by
-    float32 rounding, and one GPU run in eight has ended 0.4 dB below the
-    others.  The compared quantities are therefore medians: of five GPU runs,
-    and of three rounding-model runs from the first GPU run's start, perturbed
-    by 2^-24 relative (the size of a float32 summation-order difference)."""
-    say("warm-started training mixed: 5 runs of 100 steps on timestep 1")
-    gpu, starts = [], []
-    for r in range(5):
-        model, lay = _trained_on_t0("mixed", series)
-        starts.append(model.block_params(0).cpu().numpy().astype(np.float64))
-        gpu.append(_warm_psnr(model))
-        model.sync()
-    vol1 = series[1]
+def test_warm_started_psnr_within_03db_mixed():
+    """Mixed precision on the blob series ends near 61 dB, at the bf16 floor of
+    this small model: there the final error is set by rounding noise, and
+    trajectories that differ by float32 rounding end up to 0.4 dB apart, in
+    the oracle run under the mixed path's rounding model
+    (tests/precision_model.py) as on the GPU.  The mixed check therefore uses a
+    field the model cannot fit to that floor: a 64^3 k^-5/3 field and the same
+    field advected by one voxel along x (periodic), where warm-started
+    training goes from about 24 to 26 dB and both the fp64 oracle and the
+    rounding model end within 0.001 dB of themselves under such
+    perturbations.  The GPU's PSNR after 100 warm-started steps must lie within
+    0.3 dB of the fp64 oracle's and of the rounding model's from the same start."""
+    from paper_2304_10516_amd.dvnr import DVNR, EncodingCfg, MlpCfg, OptimCfg
+    say("warm-started training mixed: k^-5/3 field advected by one voxel")
+    f = kolmogorov_field(N, seed=7)
+    pair = [f, np.roll(f, 1, axis=2)]
+    enc, mlp = C1
+    lay = o.layout(*C1)
+    model = DVNR(EncodingCfg(enc.n_levels, enc.n_features, enc.log2_table_size, enc.base_resolution,
+                             enc.per_level_scale), MlpCfg(mlp.n_hidden_layers, mlp.width), [((N, N, N), 0)],
+                 OptimCfg(lr=1e-2), precision="mixed", max_batch=BATCH, seed=SEED)
+    model.bind_volumes([torch.as_tensor(pair[0], device="cuda")])
+    model.load_params([init_param_draws(lay.n_table_params, lay.mlp_shapes, seed=3).astype(np.float64)])
+    model.train(60, BATCH)
+    model._vols[0].copy_(torch.as_tensor(pair[1], device="cuda"))
+    model.prepare()
+    model.reset_optimizer()
+    p1 = model.block_params(0).cpu().numpy().astype(np.float64)
+    gpu_psnr = _warm_psnr(model)
+    model.sync()
+    vol1 = pair[1]
     vmin, vmax = o.block_value_range(vol1)
-    rng = np.random.default_rng(5)
-    ref = []
-    for r in range(3):
-        p1 = starts[0] * (1.0 + (2.0 ** -24) * rng.standard_normal(starts[0].size)) if r else starts[0]
-        params = pm.train(lay, p1, vol1, (N, N, N), 0, 100, BATCH, SEED, o.Optim(lr=1e-2))
-        ref.append(o.psnr(*o.squared_error(pm.decode(lay, params, (N, N, N), vmin, vmax), vol1)))
-    cold = o.psnr(*o.squared_error(pm.decode(lay, starts[0], (N, N, N), vmin, vmax), vol1))
-    say("psnr gpu " + " ".join(f"{v:.3f}" for v in gpu) + " | rounding model " + " ".join(f"{v:.3f}" for v in ref)
-        + f" | timestep-0 model on timestep 1 {cold:.3f}")
-    assert abs(float(np.median(gpu)) - float(np.median(ref))) <= 0.3
-    assert min(gpu) > cold
+    params, _, _ = o.train(lay, p1, vol1, (N, N, N), 0, n_steps=100, batch=BATCH, seed=SEED, opt=o.Optim(lr=1e-2))
+    ref = o.psnr(*o.squared_error(o.decode(lay, params, (N, N, N), vmin, vmax), vol1))
+    pmix = pm.train(lay, p1, vol1, (N, N, N), 0, 100, BATCH, SEED, o.Optim(lr=1e-2))
+    ref_mixed = o.psnr(*o.squared_error(pm.decode(lay, pmix, (N, N, N), vmin, vmax), vol1))
+    cold = o.psnr(*o.squared_error(pm.decode(lay, p1, (N, N, N), vmin, vmax), vol1))
+    say(f"psnr gpu {gpu_psnr:.3f} oracle {ref:.3f} rounding model {ref_mixed:.3f} (start on the new field: {cold:.3f})")
+    assert abs(gpu_psnr - ref) <= 0.3 and abs(gpu_psnr - ref_mixed) <= 0.3
+    assert gpu_psnr > cold + 1.0
