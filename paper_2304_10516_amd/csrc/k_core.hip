@@ -533,7 +533,10 @@ __global__ __launch_bounds__(256) void k_adam(P* __restrict__ params, P* __restr
     const P gg = g[k] + wd * th[k];
     m[k] = b1 * m[k] + omb1 * gg;
     v[k] = b2 * v[k] + omb2 * gg * gg;
-    th[k] = th[k] - lr * (m[k] * bc1) / (sqrt(v[k] * bc2) + eps);
+    if constexpr (sizeof(P) == 4)  // hardware square root and reciprocal (about 1 ulp each)
+      th[k] = th[k] - lr * bc1 * m[k] * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(v[k] * bc2) + eps);
+    else
+      th[k] = th[k] - lr * (m[k] * bc1) / (sqrt(v[k] * bc2) + eps);
     g[k] = 0;
   }
   if constexpr (sizeof(P) == 4) {

@@ -294,6 +294,31 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
       }
     }
   };
+  // the slice's elements and its Adam operands (loaded after the record sums:
+  // issuing the first batch before them measured slower)
+  const int64_t e0 = (int64_t)s << sh;
+  const int nf = (int)min((int64_t)1 << sh, (int64_t)pd.E[l] - e0) * F;
+  const int64_t el0 = meta[b].param_off + ((int64_t)ld.off[l] + e0) * F;  // first element of the slice
+  constexpr int VW = F % 2 == 0 ? 2 : 1;  // elements per access (the slice starts at an even element)
+  constexpr int PT = SF / NT / VW, KB = PT < 4 ? PT : 4;
+  typedef float fv __attribute__((ext_vector_type(VW)));
+  const int nv = nf / VW;  // accesses covering the slice (nf is a multiple of F)
+  auto ldv = [&](const float* base, int a) {
+    fv x;
+    __builtin_memcpy(&x, base + a * VW, sizeof(fv));
+    return x;
+  };
+  auto stv = [&](float* base, int a, fv x) { __builtin_memcpy(base + a * VW, &x, sizeof(fv)); };
+  fv th[KB], mm[KB], vv[KB];  // Adam operands of the batch in flight
+  auto load_adam = [&](int k0) {
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int a = min(tid + NT * (k0 + k), nv - 1);
+      th[k] = ldv(adam.params + el0, a);
+      mm[k] = ldv(adam.m + el0, a);
+      vv[k] = ldv(adam.v + el0, a);
+    }
+  };
   uint32_t vn[U][RW];
   if (n > 0) load_batch(0, vn);
   // while the first batch is in flight: this bucket's overflow flag and the
@@ -342,56 +367,74 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
   __syncthreads();
   // fixed-point sums back to float: a correctly rounded int64 -> float
   // conversion and an exact scaling by 2^-K
-  const int64_t e0 = (int64_t)s << sh;
-  const int nf = (int)min((int64_t)1 << sh, (int64_t)pd.E[l] - e0) * F;
-  const int64_t el0 = meta[b].param_off + ((int64_t)ld.off[l] + e0) * F;  // first element of the slice
   float* g = grad + el0;
   // overflow records of this bucket went to the gradient by atomics
   const bool rd_g = !do_adam || has_ovf;
-  // read-add-write of the slice (or its Adam update): batches of unconditional
-  // loads (clamped to the slice) so that a lane's loads overlap
-  constexpr int PT = SF / NT, KB = PT < 8 ? PT : 8;
+  if (do_adam) load_adam(0);
+  // read-add-write of the slice (or its Adam update) in batches of KB accesses
+  // per lane (clamped to the slice, so that a lane's loads overlap); with Adam
+  // the next batch's operands are loaded before this batch is updated.
+  // Addresses are 32-bit offsets from the slice's first element.
   for (int k0 = 0; k0 < PT; k0 += KB) {
-    float gv[KB];
+    fv gv[KB];
 #pragma unroll
-    for (int k = 0; k < KB; ++k) gv[k] = rd_g ? g[min(tid + NT * (k0 + k), nf - 1)] : 0.0f;
+    for (int k = 0; k < KB; ++k) {
+      const int a = min(tid + NT * (k0 + k), nv - 1);
+      if (rd_g)
+        gv[k] = ldv(g, a);
+      else
+        gv[k] = fv(0.0f);
+    }
     if (!do_adam) {
 #pragma unroll
       for (int k = 0; k < KB; ++k) {
-        const int i = tid + NT * (k0 + k);
-        if (i < nf) {
-          const long long a = (long long)acc[i];
-          if (a != 0) g[i] = gv[k] + ldexpf((float)a, -K);
+        const int a = tid + NT * (k0 + k);
+        if (a < nv) {
+#pragma unroll
+          for (int c = 0; c < VW; ++c) {
+            const long long s64 = (long long)acc[a * VW + c];
+            if (s64 != 0) g[a * VW + c] = gv[k][c] + ldexpf((float)s64, -K);
+          }
         }
       }
       continue;
     }
-    float th[KB], mm[KB], vv[KB];
+    fv th0[KB], mm0[KB], vv0[KB];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
-      const int64_t e = el0 + min(tid + NT * (k0 + k), nf - 1);
-      th[k] = adam.params[e];
-      mm[k] = adam.m[e];
-      vv[k] = adam.v[e];
+      th0[k] = th[k];
+      mm0[k] = mm[k];
+      vv0[k] = vv[k];
     }
-    const float bc1 = hbc[0], bc2 = hbc[1], lr = hbc[2];
+    if (k0 + KB < PT) load_adam(k0 + KB);
+    const float bc2 = hbc[1], lrbc1 = hbc[2] * hbc[0];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
-      const int i = tid + NT * (k0 + k);
-      if (i >= nf) continue;
-      const float gg = gv[k] + ldexpf((float)(long long)acc[i], -K) + adam.wd * th[k];
-      const float m1 = adam.b1 * mm[k] + adam.omb1 * gg;
-      const float v1 = adam.b2 * vv[k] + adam.omb2 * gg * gg;
-      const float t1 = th[k] - lr * (m1 * bc1) / (sqrtf(v1 * bc2) + adam.eps);
-      const int64_t e = el0 + i;
-      adam.params[e] = t1;
-      adam.m[e] = m1;
-      adam.v[e] = v1;
-      if (adam.work16) {
-        const __half hv = __float2half_rn(t1);
-        adam.work16[e] = *reinterpret_cast<const uint16_t*>(&hv);
+      const int a = tid + NT * (k0 + k);
+      if (a >= nv) continue;
+      fv t1, m1, v1;
+#pragma unroll
+      for (int c = 0; c < VW; ++c) {
+        const float gg = gv[k][c] + ldexpf((float)(long long)acc[a * VW + c], -K) + adam.wd * th0[k][c];
+        m1[c] = adam.b1 * mm0[k][c] + adam.omb1 * gg;
+        v1[c] = adam.b2 * vv0[k][c] + adam.omb2 * gg * gg;
+        // hardware square root and reciprocal (about 1 ulp each): the step
+        // lr m_hat / (sqrt(v_hat) + eps) is within a few float roundings
+        t1[c] = th0[k][c] - lrbc1 * m1[c] * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(v1[c] * bc2) + adam.eps);
       }
-      if (has_ovf) g[i] = 0.0f;
+      stv(adam.params + el0, a, t1);
+      stv(adam.m + el0, a, m1);
+      stv(adam.v + el0, a, v1);
+      if (adam.work16) {
+        uint16_t h16[VW];
+#pragma unroll
+        for (int c = 0; c < VW; ++c) {
+          const __half hv = __float2half_rn(t1[c]);
+          h16[c] = *reinterpret_cast<const uint16_t*>(&hv);
+        }
+        __builtin_memcpy(adam.work16 + el0 + a * VW, h16, sizeof(h16));
+      }
+      if (has_ovf) stv(g, a, fv(0.0f));
     }
   }
 }
