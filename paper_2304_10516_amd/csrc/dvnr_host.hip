@@ -50,6 +50,9 @@ struct dvnr {
   // workspace layout (byte offsets)
   int64_t o_meta = 0, o_range = 0, o_plan = 0, o_ctr = 0, o_vox = 0, o_tiles = 0, o_ranges = 0, o_coords = 0,
           o_target = 0, o_feat = 0, o_dfeat = 0, o_out = 0, o_slots = 0, o_ring = 0, o_mse = 0, ws_bytes = 0;
+  // second set of a step's samples (coordinates, targets, bin starts): the
+  // sampler of step i + 1 fills one set while step i trains on the other
+  int64_t o_coords2 = 0, o_target2 = 0, o_binstart2 = 0;
   int64_t max_tiles = 0, slot_stride = 0, n_slots = 0, feat_elem = 0;
 
   dvnr_buffers buf{};
@@ -114,6 +117,9 @@ struct dvnr {
   Tile* d_tiles() const { return (Tile*)(ws() + o_tiles); }
   int32_t* d_ranges() const { return (int32_t*)(ws() + o_ranges); }
   float* d_coords() const { return (float*)(ws() + o_coords); }
+  float* d_coords(int set) const { return (float*)(ws() + (set ? o_coords2 : o_coords)); }
+  float* d_target(int set) const { return (float*)(ws() + (set ? o_target2 : o_target)); }
+  int32_t* d_binstart(int set) const { return (int32_t*)(ws() + (set ? o_binstart2 : o_binstart)); }
   float* d_target() const { return (float*)(ws() + o_target); }
   void* d_feat() const { return (void*)(ws() + o_feat); }
   float* d_dfeat() const { return (float*)(ws() + o_dfeat); }
@@ -138,6 +144,12 @@ struct dvnr {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_fork2 = nullptr, ev_join2 = nullptr, ev_fork3 = nullptr,
              ev_join3 = nullptr;
+  // sampler look-ahead (option "sample_ahead", graph replays with ordered
+  // sampling): a third stream draws step i + 1's samples while step i trains
+  int sample_ahead = 1;
+  hipStream_t ahead = nullptr;
+  hipEvent_t ev_fork4 = nullptr, ev_join4 = nullptr;
+  hipGraphExec_t graph_ahead[2] = {nullptr, nullptr};  // the step on sample set p, drawing into 1 - p
   // destination-partitioned backward of the fine levels [part_l0, L): bucket
   // layout, cursors and records in one library-owned allocation (grown on demand)
   int scatter_part = -1;  // option: first partitioned level (-1: chosen per plan; >= L: none)
@@ -155,12 +167,25 @@ struct dvnr {
   uint32_t* d_precs() const { return (uint32_t*)(ws() + o_precs); }
   ~dvnr() {
     if (graph) (void)hipGraphExecDestroy(graph);
+    for (hipGraphExec_t g : graph_ahead)
+      if (g) (void)hipGraphExecDestroy(g);
     for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {ev_fork, ev_join, ev_fork2, ev_join2, ev_fork3, ev_join3})
+    for (hipEvent_t e : {ev_fork, ev_join, ev_fork2, ev_join2, ev_fork3, ev_join3, ev_fork4, ev_join4})
       if (e) (void)hipEventDestroy(e);
     if (side) (void)hipStreamDestroy(side);
+    if (ahead) (void)hipStreamDestroy(ahead);
   }
 };
+
+// Drop the captured step graphs (their kernels' arguments no longer hold).
+static void drop_graphs(dvnr_t* h) {
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  h->graph = nullptr;
+  for (hipGraphExec_t& g : h->graph_ahead) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+}
 
 static int64_t owned_voxels(const dvnr_block& b) { return (int64_t)b.dims[0] * b.dims[1] * b.dims[2]; }
 static int64_t stored_voxels(const dvnr_block& b) {
@@ -328,6 +353,8 @@ dvnr_status dvnr_create(const dvnr_encoding* enc, const dvnr_mlp* mlp, const dvn
     h->o_ranges = take(sizeof(int32_t) * 2 * n_blocks);
     h->o_coords = take(sizeof(float) * 3 * max_batch);
     h->o_target = take(sizeof(float) * max_batch);
+    h->o_coords2 = take(sizeof(float) * 3 * max_batch);
+    h->o_target2 = take(sizeof(float) * max_batch);
     h->o_feat = take(h->feat_elem * in_dim * max_batch);
     h->o_dfeat = take((h->prec == Prec::F64 ? 8 : 4) * in_dim * max_batch);
     h->o_out = take(sizeof(float) * max_batch);
@@ -339,6 +366,7 @@ dvnr_status dvnr_create(const dvnr_encoding* enc, const dvnr_mlp* mlp, const dvn
     h->o_grange = take(sizeof(int32_t) * 2 * n_blocks);
     h->o_counts = take(sizeof(uint32_t) * kMaxBins * h->max_groups);
     h->o_binstart = take(sizeof(int32_t) * (kMaxBins + 1) * n_blocks);
+    h->o_binstart2 = take(sizeof(int32_t) * (kMaxBins + 1) * n_blocks);
     h->o_totals = take(sizeof(uint32_t) * kMaxBins * n_blocks);
     // destination-partitioned backward: the suffix of levels whose tables have
     // at least kPartMinEntries entries and fit kPartMaxSlices of the largest slices
@@ -432,10 +460,7 @@ dvnr_status dvnr_bind(dvnr_t* h, const dvnr_buffers* b) {
     HIPCHK(hipMemset(h->d_ring(), 0, sizeof(float) * kLossRing * h->nb));
     h->host_step = 0;
     h->plan_total = -1;
-    if (h->graph) {
-      (void)hipGraphExecDestroy(h->graph);
-      h->graph = nullptr;
-    }
+    drop_graphs(h);
     h->bound = true;
     h->prepared = false;
     return DVNR_OK;
@@ -732,10 +757,7 @@ static dvnr_status set_plan(dvnr_t* h, const std::vector<int64_t>& n, hipStream_
     HIPCHK(hipMemcpyAsync(h->d_groups(), h->hgroups.data(), sizeof(Tile) * h->n_groups, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(h->d_grange(), h->hgrange.data(), sizeof(int32_t) * 2 * h->nb, hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (h->graph) {
-    (void)hipGraphExecDestroy(h->graph);
-    h->graph = nullptr;
-  }
+  drop_graphs(h);
   return DVNR_OK;
 }
 
@@ -788,20 +810,44 @@ static hipError_t ensure_side(dvnr_t* h) {
 }
 
 // One training step on the current plan (coordinates generated when gen != 0).
-static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
+// Ordered sampler of the step `step_off` steps after the device counter's,
+// into sample set `set`.
+static dvnr_status enqueue_sorted_sample(dvnr_t* h, int set, uint32_t step_off, hipStream_t s) {
+  HIPCHK(launch_sorted_sample(h->d_groups(), h->n_groups, h->d_grange(), h->nb, h->sort_B, h->seed, h->dist(),
+                              h->d_ctr(), step_off, h->d_counts(), h->d_totals(), h->d_binstart(set), h->d_meta(),
+                              h->d_range(), h->d_plan(), h->d_coords(set), h->d_target(set), s));
+  return DVNR_OK;
+}
+
+// One training step on the current plan.  gen != 0: the step's samples are
+// generated (Philox draws at the device step counter), else the coordinates
+// are given in sample set 0.  set: the sample set the step trains on.
+// ahead (ordered sampling only): this step's samples are already in `set`,
+// and a third stream draws the next step's into 1 - set while this step
+// trains (joined before the slot reduction advances the counter).
+static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s, int set = 0, bool ahead = false) {
   const bool mixed = h->prec == Prec::MIXED;
   const int64_t F = h->enc.n_features;
   const bool sorted = gen && h->spatial_sort && h->n_groups > 0;
+  if (ahead && !sorted) return fail(DVNR_E_STATE, "sampler look-ahead needs ordered sampling");
   PROF(0);
-  if (sorted) {
-    HIPCHK(launch_sorted_sample(h->d_groups(), h->n_groups, h->d_grange(), h->nb, h->sort_B, h->seed, h->dist(),
-                                h->d_ctr(),
-                                h->d_counts(), h->d_totals(), h->d_binstart(), h->d_meta(), h->d_range(), h->d_plan(),
-                                h->d_coords(),
-                                h->d_target(), s));
+  if (ahead) {
+    if (!h->ahead) {
+      HIPCHK(hipStreamCreateWithFlags(&h->ahead, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&h->ev_fork4, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&h->ev_join4, hipEventDisableTiming));
+    }
+    HIPCHK(hipEventRecord(h->ev_fork4, s));
+    HIPCHK(hipStreamWaitEvent(h->ahead, h->ev_fork4, 0));
+    dvnr_status st = enqueue_sorted_sample(h, 1 - set, 1, h->ahead);
+    if (st) return st;
+    HIPCHK(hipEventRecord(h->ev_join4, h->ahead));
+  } else if (sorted) {
+    dvnr_status st = enqueue_sorted_sample(h, set, 0, s);
+    if (st) return st;
   } else {
     HIPCHK(launch_sample(h->d_meta(), h->d_range(), h->d_plan(), h->d_tiles(), h->n_tiles, 0, gen, h->seed,
-                         h->dist(), h->d_ctr(), -1, h->d_coords(), h->d_target(), s));
+                         h->dist(), h->d_ctr(), -1, h->d_coords(set), h->d_target(set), s));
   }
   PROF(1);
   const void* table = mixed ? h->buf.work16 : h->buf.params;
@@ -817,18 +863,18 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   }
   if (le > 0)
     HIPCHK(launch_encode_binned(h->prec, mixed ? 1 : 0, h->ld, 0, le, h->sort_B, h->nb, h->d_meta(), h->d_plan(),
-                                h->d_binstart(), h->d_coords(), table, h->d_feat(), F, h->max_batch * F,
+                                h->d_binstart(set), h->d_coords(set), table, h->d_feat(), F, h->max_batch * F,
                                 econc ? h->side : s));
   if (econc) HIPCHK(hipEventRecord(h->ev_join3, h->side));
   HIPCHK(launch_encode(h->prec, mixed ? 1 : 0, h->ld, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
-                       h->d_coords(), table, h->d_feat(), F, h->max_batch * F, h->xcd_map, s, le,
+                       h->d_coords(set), table, h->d_feat(), F, h->max_batch * F, h->xcd_map, s, le,
                        h->enc.n_levels));
   if (econc) HIPCHK(hipStreamWaitEvent(s, h->ev_join3, 0));
   PROF(2);
   const void* wsrc = mixed ? (const void*)((const uint16_t*)h->buf.work16 + h->n_table)
                            : (const void*)((const float*)h->buf.params + h->n_table);
   HIPCHK(launch_mlp_train(h->prec, h->md, h->ld, h->d_meta(), h->d_plan(), h->d_tiles(), h->n_tiles, h->d_feat(),
-                          h->d_target(), wsrc, h->d_dfeat(), h->max_batch, h->d_slots(), h->slot_stride, h->mlp_grid,
+                          h->d_target(set), wsrc, h->d_dfeat(), h->max_batch, h->d_slots(), h->slot_stride, h->mlp_grid,
                           h->loss_l1, h->mlp_waves, s));
   PROF(3);
   const int lf = h->part_l0;  // levels [lf, L): destination-partitioned
@@ -862,7 +908,7 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   }
   auto part_bucket = [&](hipStream_t st) {
     return launch_part_bucket(h->ld, h->pdesc, h->d_meta(), h->d_tiles(), h->n_tiles, h->d_plan(), h->d_pblk(),
-                              h->d_coords(), h->d_dfeat(), h->max_batch * F, h->d_pcur(), h->d_precs(),
+                              h->d_coords(set), h->d_dfeat(), h->max_batch * F, h->d_pcur(), h->d_precs(),
                               h->d_ptmax(), h->d_povf(), (float*)h->buf.grads, st);
   };
   auto part_accum = [&](hipStream_t st) {
@@ -899,22 +945,22 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
       HIPCHK(ensure_side(h));
       HIPCHK(hipEventRecord(h->ev_fork, s));
       HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-      HIPCHK(launch_scatter_priv(h->ld, c, lp, h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(),
-                                 h->d_coords(), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, 0, 0,
+      HIPCHK(launch_scatter_priv(h->ld, c, lp, h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(set),
+                                 h->d_coords(set), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, 0, 0,
                                  h->side));
       HIPCHK(hipEventRecord(h->ev_join, h->side));
     }
     const int cls[3][3] = {{0, a, 1}, {a, c, 2}, {c, conc ? c : lp, 0}};
     for (const auto& r : cls)
       if (r[1] > r[0])
-        HIPCHK(launch_scatter_priv(h->ld, r[0], r[1], h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(),
-                                   h->d_coords(), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, 0, r[2],
+        HIPCHK(launch_scatter_priv(h->ld, r[0], r[1], h->sort_B, h->nb, h->d_meta(), h->d_plan(), h->d_binstart(set),
+                                   h->d_coords(set), h->d_dfeat(), h->max_batch * F, (float*)h->buf.grads, 0, r[2],
                                    s));
     if (conc && c < lp) HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
   }
   PROF(4);
   HIPCHK(launch_scatter(Prec::F32, h->ld, lp, lf, h->d_meta(), h->d_tiles(), h->n_tiles, 0, h->d_plan(),
-                        h->d_coords(), h->d_dfeat(), F, h->max_batch * F, h->buf.grads, h->scatter_grouped,
+                        h->d_coords(set), h->d_dfeat(), F, h->max_batch * F, h->buf.grads, h->scatter_grouped,
                         h->xcd_map, sorted ? h->scatter_strided : 0, s));
   PROF(5);
   if (lf < h->enc.n_levels && !pconc) HIPCHK(part_bucket(s));
@@ -925,6 +971,7 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s) {
   // weights' gradient: with the concurrent passes it runs before the join,
   // unless the slice pass still has to read the step counter it advances
   if (pconc && padam) HIPCHK(hipStreamWaitEvent(s, h->ev_join2, 0));
+  if (ahead) HIPCHK(hipStreamWaitEvent(s, h->ev_join4, 0));  // it read the counter before the advance
   HIPCHK(launch_reduce_slots(h->d_slots(), h->slot_stride, h->d_ranges(), h->nb, h->n_mlp, h->n_table, h->stride,
                              Prec::F32, h->buf.grads, h->d_ring(), h->d_ctr(), 1, s));
   if (pconc && !padam) HIPCHK(hipStreamWaitEvent(s, h->ev_join2, 0));
@@ -985,31 +1032,56 @@ static dvnr_status train_ready(dvnr_t* h) {
 // captured step (hipGraph, keyed by stream and `plan_key`) on a non-default
 // stream, else eager launches.  Losses of the steps go to loss_out (device
 // float [n_steps][n_blocks]) when given.
+// Capture one step as a graph (kernel arguments are fixed at capture).
+static dvnr_status capture_step(dvnr_t* h, hipStream_t s, int set, bool ahead, hipGraphExec_t* out) {
+  hipGraph_t g;
+  HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  dvnr_status st = enqueue_step(h, 1, s, set, ahead);
+  hipError_t ce = hipStreamEndCapture(s, &g);
+  if (st) return st;
+  if (ce != hipSuccess) return fail(DVNR_E_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+  ce = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ce != hipSuccess) return fail(DVNR_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ce));
+  return DVNR_OK;
+}
+
 static dvnr_status run_steps(dvnr_t* h, int64_t n_steps, int64_t plan_key, float* loss_out, hipStream_t s) {
   dvnr_status st = DVNR_OK;
   const int64_t s0 = h->host_step;
   int64_t done = 0;
-  while (done < n_steps) {
-    const int64_t chunk = std::min<int64_t>(n_steps - done, kLossRing);
-    const bool graph_ok = h->use_graph && !h->profile && s != nullptr;
-    if (graph_ok && (!h->graph || h->graph_stream != s || h->graph_total != plan_key)) {
-      if (h->graph) {
-        (void)hipGraphExecDestroy(h->graph);
-        h->graph = nullptr;
+  const bool graph_ok = h->use_graph && !h->profile && s != nullptr;
+  // sampler look-ahead: the first step's samples are drawn here into set 0;
+  // every replayed step trains on set p and draws the next step's into 1 - p
+  // (the last step's draw is not used).  No drawn samples outlive the call,
+  // so changes of the volumes or ranges between calls are always seen.
+  const bool ahead = graph_ok && h->sample_ahead && h->spatial_sort && h->n_groups > 0 && n_steps > 0;
+  if (ahead) {
+    if (!h->graph_ahead[0] || h->graph_stream != s || h->graph_total != plan_key) {
+      drop_graphs(h);
+      for (int p = 0; p < 2; ++p) {
+        st = capture_step(h, s, p, true, &h->graph_ahead[p]);
+        if (st) return st;
       }
-      hipGraph_t g;
-      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      st = enqueue_step(h, 1, s);
-      hipError_t ce = hipStreamEndCapture(s, &g);
-      if (st) return st;
-      if (ce != hipSuccess) return fail(DVNR_E_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
-      ce = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (ce != hipSuccess) return fail(DVNR_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ce));
       h->graph_stream = s;
       h->graph_total = plan_key;
     }
-    for (int64_t k = 0; k < chunk; ++k) {
+    st = enqueue_sorted_sample(h, 0, 0, s);
+    if (st) return st;
+  }
+  int set = 0;
+  while (done < n_steps) {
+    const int64_t chunk = std::min<int64_t>(n_steps - done, kLossRing);
+    if (ahead) {
+      for (int64_t k = 0; k < chunk; ++k, set ^= 1) HIPCHK(hipGraphLaunch(h->graph_ahead[set], s));
+    } else if (graph_ok && (!h->graph || h->graph_stream != s || h->graph_total != plan_key)) {
+      drop_graphs(h);
+      st = capture_step(h, s, 0, false, &h->graph);
+      if (st) return st;
+      h->graph_stream = s;
+      h->graph_total = plan_key;
+    }
+    for (int64_t k = 0; k < chunk && !ahead; ++k) {
       if (graph_ok) {
         HIPCHK(hipGraphLaunch(h->graph, s));
       } else {
@@ -1754,6 +1826,8 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
     h->decode_fused = value ? 1 : 0;
   } else if (n == "spatial_sort") {
     h->spatial_sort = value ? 1 : 0;
+  } else if (n == "sample_ahead") {
+    h->sample_ahead = value ? 1 : 0;
   } else if (n == "sort_bins") {
     if (value < 0 || value > 8) return fail(DVNR_E_INVALID, "sort_bins: 0 (automatic) or 1..8");
     h->sort_bins = (int)value;
@@ -1766,10 +1840,7 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
   } else {
     return fail(DVNR_E_INVALID, "unknown option " + n);
   }
-  if (h->graph) {
-    (void)hipGraphExecDestroy(h->graph);
-    h->graph = nullptr;
-  }
+  drop_graphs(h);
   return DVNR_OK;
 }
 
@@ -1782,10 +1853,7 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
   h->bnd_frac = boundary_frac;
   h->bnd_sigma = sigma;
   h->plan_total = -1;  // per-block boundary counts live in the plan
-  if (h->graph) {
-    (void)hipGraphExecDestroy(h->graph);
-    h->graph = nullptr;
-  }
+  drop_graphs(h);
   return DVNR_OK;
 }
 

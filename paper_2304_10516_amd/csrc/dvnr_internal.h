@@ -195,8 +195,10 @@ hipError_t launch_part_accum(const LevelDesc& ld, const PartDesc& pd, const Bloc
 // Spatially ordered sampler: Philox draws of every group (<= kSortGroup
 // samples of one block) stored grouped by B^3 spatial bins; bin_start
 // [n_blocks][kMaxBins + 1] receives each bin's first sample (within the block).
+// The draws are those of step ctr->step + step_off.
 hipError_t launch_sorted_sample(const Tile* groups, int n_groups, const int32_t* group_range, int n_blocks, int B,
-                                uint64_t seed, SampleDist dist, const Counters* ctr, uint32_t* counts, uint32_t* totals,
+                                uint64_t seed, SampleDist dist, const Counters* ctr, uint32_t step_off,
+                                uint32_t* counts, uint32_t* totals,
                                 int32_t* bin_start, const BlockMeta* meta, const BlockRange* range,
                                 const BlockPlan* plan, float* coords, float* target, hipStream_t s);
 // Bin-privatized encoding backward of levels [l0, l1) (needs the ordered

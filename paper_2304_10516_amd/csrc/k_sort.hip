@@ -26,13 +26,14 @@ namespace dvnrk {
 // workgroup of kSortGroup threads per group (one sample per thread).
 __global__ __launch_bounds__(kSortGroup) void k_sort_count(const Tile* __restrict__ groups, int B, uint64_t seed,
                                                     SampleDist dist, const BlockPlan* __restrict__ plan,
-                                                    const Counters* __restrict__ ctr, uint32_t* __restrict__ counts) {
+                                                    const Counters* __restrict__ ctr, uint32_t step_off,
+                                                    uint32_t* __restrict__ counts) {
   __shared__ uint32_t hist[kMaxBins];
   const int nbins = B * B * B;
   for (int i = threadIdx.x; i < nbins; i += blockDim.x) hist[i] = 0u;
   __syncthreads();
   const Tile gr = groups[blockIdx.x];
-  const uint32_t step = (uint32_t)ctr->step;
+  const uint32_t step = (uint32_t)ctr->step + step_off;
   const int n_uni = plan[gr.block].n_uni;
   for (int j = threadIdx.x; j < gr.count; j += blockDim.x) {
     float x, y, z;
@@ -113,7 +114,7 @@ __device__ __forceinline__ void cell_pos_s(float x, int n, int g, int N, int& i0
 // (bin_start[b][0..nbins], last = sample count) for the privatized scatter.
 __global__ __launch_bounds__(kSortGroup) void k_sort_place(const Tile* __restrict__ groups, const int32_t* __restrict__ grange,
                                                     int B, uint64_t seed, SampleDist dist,
-                                                    const Counters* __restrict__ ctr,
+                                                    const Counters* __restrict__ ctr, uint32_t step_off,
                                                     const uint32_t* __restrict__ prefix,
                                                     const uint32_t* __restrict__ totals,
                                                     int32_t* __restrict__ bin_start,
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(kSortGroup) void k_sort_place(const Tile* __restric
     if (first && t == 255) bs[nbins] = (int32_t)scan[255];
   }
   __syncthreads();
-  const uint32_t step = (uint32_t)ctr->step;
+  const uint32_t step = (uint32_t)ctr->step + step_off;
   const BlockMeta bm = meta[gr.block];
   const BlockRange br = range[gr.block];
   const int64_t base = plan[gr.block].sample_off;
@@ -197,16 +198,19 @@ __global__ __launch_bounds__(kSortGroup) void k_sort_place(const Tile* __restric
 }
 
 hipError_t launch_sorted_sample(const Tile* groups, int n_groups, const int32_t* group_range, int n_blocks, int B,
-                                uint64_t seed, SampleDist dist, const Counters* ctr, uint32_t* counts, uint32_t* totals,
+                                uint64_t seed, SampleDist dist, const Counters* ctr, uint32_t step_off,
+                                uint32_t* counts, uint32_t* totals,
                                 int32_t* bin_start, const BlockMeta* meta, const BlockRange* range,
                                 const BlockPlan* plan, float* coords, float* target, hipStream_t s) {
   if (n_groups <= 0) return hipSuccess;
   if (B < 1 || B * B * B > kMaxBins) return hipErrorInvalidValue;
   const int nbins = B * B * B;
-  hipLaunchKernelGGL(k_sort_count, dim3(n_groups), dim3(kSortGroup), 0, s, groups, B, seed, dist, plan, ctr, counts);
+  hipLaunchKernelGGL(k_sort_count, dim3(n_groups), dim3(kSortGroup), 0, s, groups, B, seed, dist, plan, ctr, step_off,
+                     counts);
   hipLaunchKernelGGL(k_sort_scan, dim3(n_blocks, (nbins + 63) / 64), dim3(1024), 0, s, group_range, B, counts,
                      totals);
-  hipLaunchKernelGGL(k_sort_place, dim3(n_groups), dim3(kSortGroup), 0, s, groups, group_range, B, seed, dist, ctr, counts,
+  hipLaunchKernelGGL(k_sort_place, dim3(n_groups), dim3(kSortGroup), 0, s, groups, group_range, B, seed, dist, ctr,
+                     step_off, counts,
                      totals, bin_start, meta, range, plan, coords, target);
   return hipGetLastError();
 }

@@ -687,6 +687,59 @@ def test_graph_replay_matches_eager_steps(precision, conc, part):
     np.testing.assert_allclose(losses[1], losses[0], rtol=2e-4 if precision == "fp32" else 1e-3, atol=0)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_sampler_lookahead_draws_the_same_samples(precision):
+    """With ordered sampling, replayed steps draw step i + 1's samples on a
+    third stream while step i trains (the other of two sample sets).  The
+    draws are those of the inline sampler: with explicit per-step sample
+    counts of two blocks, the first step's gradient (no update) is the
+    oracle's on the Philox draws of that step, and 6 steps in one call, in 6
+    calls of one step, and without look-ahead follow the same loss
+    trajectory (float atomics' order aside)."""
+    say(f"sampler look-ahead {precision}")
+    vol = gaussian_sum_field(32, seed=9)
+    lay = o.layout(*C1)
+    p0 = init_param_draws(lay.n_table_params, lay.mlp_shapes, seed=12).astype(np.float64)
+    p0[:lay.n_table_params] *= 1e3
+    blocks = [((32, 32, 32), 0), ((32, 32, 32), 0)]
+    runs = {}
+    for name, ahead, calls in (("ahead", 1, 1), ("ahead, one step per call", 1, 6), ("inline", 0, 1)):
+        model = make(C1, blocks, precision=precision, max_batch=4096, seed=5)
+        model.bind_volumes([dev(vol), dev(vol[::-1].copy())])
+        model.load_params([p0, p0])
+        model.set_option("spatial_sort", 1)
+        model.set_option("sample_ahead", ahead)
+        s = torch.cuda.Stream()
+        out = []
+        with torch.cuda.stream(s):
+            for _ in range(calls):
+                out.append(model.train(6 // calls, 2048, want_loss=True, stream=s).clone())
+        s.synchronize()
+        runs[name] = torch.cat(out).cpu().numpy()
+        model.sync(stream=s)
+    tol = 1e-5 if precision == "fp32" else 1e-3
+    np.testing.assert_allclose(runs["ahead"], runs["inline"], rtol=tol, atol=0)
+    np.testing.assert_allclose(runs["ahead, one step per call"], runs["inline"], rtol=tol, atol=0)
+    # the first step's draws are the oracle's (step 0, block b)
+    model = make(C1, blocks, precision="fp32", max_batch=4096, seed=5)
+    model.bind_volumes([dev(vol), dev(vol)])
+    model.load_params([p0, p0])
+    model.set_option("spatial_sort", 1)
+    model.set_option("apply_update", 0)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        loss = model.train(1, 2048, want_loss=True, stream=s)
+    s.synchronize()
+    n = o.apportion([32 ** 3, 32 ** 3], 2048)
+    for b in range(2):
+        x = o.training_coords(5, b, 0, int(n[b]))
+        L, g, _ = o.loss_and_grad(lay, model.block_params(b).cpu().numpy().astype(np.float64), x,
+                                  o.normalized_targets(vol, (32, 32, 32), 0, x))
+        assert abs(loss[0, b].item() - L) <= 1e-5 * L
+        assert normwise(model.block_grads(b).cpu().numpy(), g) <= 1e-5
+    model.sync(stream=s)
+
+
 def test_nonfinite_loss_is_reported_at_sync():
     """A NaN voxel in the input makes the loss non-finite; the library reports it
     at dvnr_sync (every kernel still runs to completion)."""
