@@ -50,6 +50,7 @@ struct dvnr {
   // workspace layout (byte offsets)
   int64_t o_meta = 0, o_range = 0, o_plan = 0, o_ctr = 0, o_vox = 0, o_tiles = 0, o_ranges = 0, o_coords = 0,
           o_target = 0, o_feat = 0, o_dfeat = 0, o_out = 0, o_slots = 0, o_ring = 0, o_mse = 0, ws_bytes = 0;
+  int64_t o_decop = 0;  // fused decode: the block's MLP operands in operand order
   // second set of a step's samples (coordinates, targets, bin starts): the
   // sampler of step i + 1 fills one set while step i trains on the other
   int64_t o_coords2 = 0, o_target2 = 0, o_binstart2 = 0;
@@ -361,6 +362,7 @@ dvnr_status dvnr_create(const dvnr_encoding* enc, const dvnr_mlp* mlp, const dvn
     h->o_slots = take(sizeof(float) * h->n_slots * h->slot_stride);
     h->o_ring = take(sizeof(float) * kLossRing * n_blocks);
     h->o_mse = take(sizeof(double) * 8);
+    h->o_decop = take(kDecOperandBytes);
     h->max_groups = max_batch / kSortGroup + n_blocks + 1;
     h->o_groups = take(sizeof(Tile) * h->max_groups);
     h->o_grange = take(sizeof(int32_t) * 2 * n_blocks);
@@ -1299,7 +1301,7 @@ static dvnr_status decode_impl(dvnr_t* h, int32_t block, float* out, hipStream_t
     const int64_t nvox = owned_voxels(h->blocks[b]);
     if (h->decode_fused) {
       HIPCHK(launch_decode_fused(h->prec, h->ld, h->md, h->d_meta(), src.range, b, h->blocks[b].dims, src.params,
-                                 src.params, h->n_table, out + out_off, s));
+                                 src.params, h->n_table, h->ws() + h->o_decop, out + out_off, s));
       out_off += nvox;
       continue;
     }

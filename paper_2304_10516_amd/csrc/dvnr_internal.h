@@ -246,7 +246,9 @@ hipError_t launch_mlp_simple_bwd(Prec p, const MlpDesc& md, int64_t n, const voi
 // space (fp16 / bf16 working copy for mixed precision, fp32 masters otherwise).
 hipError_t launch_decode_fused(Prec p, const LevelDesc& ld, const MlpDesc& md, const BlockMeta* meta,
                                const BlockRange* range, int block, const int32_t* dims, const void* table,
-                               const void* wsrc, int64_t n_table_params, float* out, hipStream_t s);
+                               const void* wsrc, int64_t n_table_params, void* opnd, float* out, hipStream_t s);
+// Device scratch of the fused decode: the block's MLP operands in operand order.
+constexpr int kDecOperandBytes = 1 << 16;
 
 // Direct volume rendering by sample streaming (one block's unit cube).
 struct RayCamera {

@@ -10,7 +10,10 @@
 // replaces ~128 scattered global gathers per voxel by ~10 global loads per
 // voxel plus LDS reads.  Boxes that do not fit (a level much finer than the
 // voxel grid) fall back to direct gathers.  The features (bf16 or fp32) stay
-// in LDS and feed the MFMA MLP forward.
+// in LDS and feed the MFMA MLP forward, whose weight operands a small kernel
+// arranges once per block in operand order (every brick then copies them with
+// 16-byte loads: staged element by element from the weights, they took most
+// of the decode's time).
 #include "dvnr_device.h"
 
 namespace dvnrk {
@@ -39,12 +42,57 @@ struct DecMlp {
   static __host__ __device__ constexpr int src_i(int s, int j) { return BF16 ? j % 4 : s % 4; }
 };
 
+// Forward operand e of the A side (slot e / 64, lane e % 64) from the block's
+// weights ws (W_1 .. W_out, row-major), in the MFMA operand order the
+// forward below consumes.
+template <bool BF16, int W, int NH, typename WT>
+__device__ __forceinline__ typename std::conditional<BF16, bf16x8d, float>::type dec_operand(const WT* __restrict__ ws,
+                                                                                         const MlpDesc& md, int e) {
+  using S = DecMlp<BF16, W, NH>;
+  using op_t = typename std::conditional<BF16, bf16x8d, float>::type;
+  const int slot = e / 64, lane = e % 64;
+  const int row = lane % 16, g = lane / 16;
+  const int in_dim = md.in_dim;
+  op_t v;
+  for (int j = 0; j < S::VPL; ++j) {
+    float x = 0.0f;
+    if (slot < S::N_A0) {
+      const int m = slot / S::KS_IN, s = slot % S::KS_IN;
+      const int f = 8 * g + s * S::VPL + j;
+      if (f < in_dim) x = (float)ws[md.off[0] + (16 * m + row) * in_dim + f];
+    } else {
+      const int r = slot - S::N_A0;
+      const int k = 1 + r / (S::MT * S::KS_H), m = (r / S::KS_H) % S::MT, s = r % S::KS_H;
+      const int n = 4 * g + S::src_i(s, j) + 16 * S::src_m(s, j);
+      if (S::src_m(s, j) < S::MT) x = (float)ws[md.off[k] + (16 * m + row) * W + n];
+    }
+    if constexpr (BF16) v[j] = (__bf16)x; else v = x;
+  }
+  return v;
+}
+
+// The block's forward operands in operand order (N_SLOTS * 64 entries), then
+// the output layer's W floats: written once per decode, copied by every brick
+// with 16-byte loads.
+template <bool BF16, int W, int NH, typename WT>
+__global__ __launch_bounds__(256) void k_dec_operands(MlpDesc md, const BlockMeta* __restrict__ meta, int block,
+                                                      const WT* __restrict__ wsrc_all, int64_t n_table_params,
+                                                      void* __restrict__ dst) {
+  using S = DecMlp<BF16, W, NH>;
+  using op_t = typename std::conditional<BF16, bf16x8d, float>::type;
+  const WT* ws = wsrc_all + meta[block].param_off + n_table_params;
+  op_t* A = reinterpret_cast<op_t*>(dst);
+  float* wout = reinterpret_cast<float*>(A + S::N_SLOTS * 64);
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e < S::N_SLOTS * 64) A[e] = dec_operand<BF16, W, NH, WT>(ws, md, e);
+  if (e < W) wout[e] = (float)ws[md.off[NH] + e];
+}
+
 template <bool BF16, int W, int NH, typename TT, typename WT, int F>
 __global__ __launch_bounds__(256) void k_decode_fused(LevelDesc ld, MlpDesc md, const BlockMeta* __restrict__ meta,
                                                       const BlockRange* __restrict__ range, int block,
                                                       const TT* __restrict__ table_all,
-                                                      const WT* __restrict__ wsrc_all, int64_t n_table_params,
-                                                      float* __restrict__ out) {
+                                                      const void* __restrict__ opnd, float* __restrict__ out) {
   using S = DecMlp<BF16, W, NH>;
   using op_t = typename std::conditional<BF16, bf16x8d, float>::type;
   using fe_t = typename std::conditional<BF16, __bf16, float>::type;
@@ -70,31 +118,12 @@ __global__ __launch_bounds__(256) void k_decode_fused(LevelDesc ld, MlpDesc md, 
   const float ay0 = center(y0, ny), ay1 = center(y1, ny);
   const float az0 = center(z0, nz), az1 = center(z1, nz);
 
-  // ---- weights (forward operands) of this block
+  // ---- forward operands of this block, arranged by k_dec_operands
   {
-    const WT* ws = wsrc_all + bm.param_off + n_table_params;
-    const int in_dim = md.in_dim;
-    for (int e = tid; e < S::N_SLOTS * 64; e += 256) {
-      const int slot = e / 64, lane = e % 64;
-      const int row = lane % 16, g = lane / 16;
-      op_t v;
-      for (int j = 0; j < S::VPL; ++j) {
-        float x = 0.0f;
-        if (slot < S::N_A0) {
-          const int m = slot / S::KS_IN, s = slot % S::KS_IN;
-          const int f = 8 * g + s * S::VPL + j;
-          if (f < in_dim) x = (float)ws[md.off[0] + (16 * m + row) * in_dim + f];
-        } else {
-          const int r = slot - S::N_A0;
-          const int k = 1 + r / (S::MT * S::KS_H), m = (r / S::KS_H) % S::MT, s = r % S::KS_H;
-          const int n = 4 * g + S::src_i(s, j) + 16 * S::src_m(s, j);
-          if (S::src_m(s, j) < S::MT) x = (float)ws[md.off[k] + (16 * m + row) * W + n];
-        }
-        if constexpr (BF16) v[j] = (__bf16)x; else v = x;
-      }
-      A[e] = v;
-    }
-    for (int e = tid; e < W; e += 256) wout[e] = (float)ws[md.off[NH] + e];
+    const op_t* src = reinterpret_cast<const op_t*>(opnd);
+    for (int e = tid; e < S::N_SLOTS * 64; e += 256) A[e] = src[e];
+    const float* wo = reinterpret_cast<const float*>(src + S::N_SLOTS * 64);
+    for (int e = tid; e < W; e += 256) wout[e] = wo[e];
   }
 
   // ---- encoding, level by level through the LDS box
@@ -232,16 +261,20 @@ __global__ __launch_bounds__(256) void k_decode_fused(LevelDesc ld, MlpDesc md, 
 template <bool BF16, int W, int NH, typename TT, typename WT>
 static hipError_t run_decode(const LevelDesc& ld, const MlpDesc& md, const BlockMeta* meta, const BlockRange* range,
                              int block, const int32_t* dims, const void* table, const void* wsrc, int64_t n_table,
-                             float* out, hipStream_t s) {
+                             void* opnd, float* out, hipStream_t s) {
+  using S = DecMlp<BF16, W, NH>;
   const int64_t bricks = (int64_t)((dims[0] + kBX - 1) / kBX) * ((dims[1] + kBY - 1) / kBY) *
                          ((dims[2] + kBZ - 1) / kBZ);
   if (bricks <= 0) return hipSuccess;
   if (bricks > 0x7fffffff) return hipErrorInvalidValue;
+  static_assert(S::N_SLOTS * 64 * (BF16 ? 16 : 4) + 4 * W <= kDecOperandBytes, "operand buffer too small");
+  hipLaunchKernelGGL((k_dec_operands<BF16, W, NH, WT>), dim3((S::N_SLOTS * 64 + 255) / 256), dim3(256), 0, s, md,
+                     meta, block, (const WT*)wsrc, n_table, opnd);
   switch (ld.F) {
-    case 1: hipLaunchKernelGGL((k_decode_fused<BF16, W, NH, TT, WT, 1>), dim3((unsigned)bricks), dim3(256), 0, s, ld, md, meta, range, block, (const TT*)table, (const WT*)wsrc, n_table, out); break;
-    case 2: hipLaunchKernelGGL((k_decode_fused<BF16, W, NH, TT, WT, 2>), dim3((unsigned)bricks), dim3(256), 0, s, ld, md, meta, range, block, (const TT*)table, (const WT*)wsrc, n_table, out); break;
-    case 4: hipLaunchKernelGGL((k_decode_fused<BF16, W, NH, TT, WT, 4>), dim3((unsigned)bricks), dim3(256), 0, s, ld, md, meta, range, block, (const TT*)table, (const WT*)wsrc, n_table, out); break;
-    case 8: hipLaunchKernelGGL((k_decode_fused<BF16, W, NH, TT, WT, 8>), dim3((unsigned)bricks), dim3(256), 0, s, ld, md, meta, range, block, (const TT*)table, (const WT*)wsrc, n_table, out); break;
+    case 1: hipLaunchKernelGGL((k_decode_fused<BF16, W, NH, TT, WT, 1>), dim3((unsigned)bricks), dim3(256), 0, s, ld, md, meta, range, block, (const TT*)table, opnd, out); break;
+    case 2: hipLaunchKernelGGL((k_decode_fused<BF16, W, NH, TT, WT, 2>), dim3((unsigned)bricks), dim3(256), 0, s, ld, md, meta, range, block, (const TT*)table, opnd, out); break;
+    case 4: hipLaunchKernelGGL((k_decode_fused<BF16, W, NH, TT, WT, 4>), dim3((unsigned)bricks), dim3(256), 0, s, ld, md, meta, range, block, (const TT*)table, opnd, out); break;
+    case 8: hipLaunchKernelGGL((k_decode_fused<BF16, W, NH, TT, WT, 8>), dim3((unsigned)bricks), dim3(256), 0, s, ld, md, meta, range, block, (const TT*)table, opnd, out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -249,14 +282,14 @@ static hipError_t run_decode(const LevelDesc& ld, const MlpDesc& md, const Block
 
 hipError_t launch_decode_fused(Prec p, const LevelDesc& ld, const MlpDesc& md, const BlockMeta* meta,
                                const BlockRange* range, int block, const int32_t* dims, const void* table,
-                               const void* wsrc, int64_t n_table_params, float* out, hipStream_t s) {
+                               const void* wsrc, int64_t n_table_params, void* opnd, float* out, hipStream_t s) {
 #define X(WW, NN)                                                                                                \
   if (md.width == WW && md.n_hidden == NN) {                                                                     \
     if (p == Prec::MIXED)                                                                                        \
       return run_decode<true, WW, NN, __half, __bf16>(ld, md, meta, range, block, dims, table, wsrc,             \
-                                                      n_table_params, out, s);                                    \
+                                                      n_table_params, opnd, out, s);                              \
     return run_decode<false, WW, NN, float, float>(ld, md, meta, range, block, dims, table, wsrc, n_table_params, \
-                                                   out, s);                                                       \
+                                                   opnd, out, s);                                                 \
   }
   X(16, 1) X(16, 2) X(16, 3) X(32, 1) X(32, 2) X(32, 3) X(64, 1) X(64, 2) X(64, 3)
 #undef X
