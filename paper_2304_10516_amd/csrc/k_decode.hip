@@ -11,9 +11,12 @@
 // voxel plus LDS reads.  Boxes that do not fit (a level much finer than the
 // voxel grid) fall back to direct gathers.  The features (bf16 or fp32) stay
 // in LDS and feed the MFMA MLP forward, whose weight operands a small kernel
-// arranges once per block in operand order (every brick then copies them with
-// 16-byte loads: staged element by element from the weights, they took most
-// of the decode's time).
+// arranges once per block in operand order (staged element by element from
+// the weights by every brick, they took most of the decode's time); with bf16
+// each lane loads its operands straight into registers.  The decode is bound
+// by the latency of the per-level box loads, so LDS is kept small (the box
+// in the table's own fp16 elements, no operand copy in LDS) for five
+// workgroups per CU.
 #include "dvnr_device.h"
 
 namespace dvnrk {
@@ -22,7 +25,7 @@ typedef __bf16 bf16x8d __attribute__((ext_vector_type(8)));
 typedef float f32x4d __attribute__((ext_vector_type(4)));
 
 constexpr int kBX = 16, kBY = 4, kBZ = 4;  // brick of 256 voxels
-constexpr int kBoxFloats = 4096;          // LDS box capacity (floats: entries x F)
+constexpr int kBoxElems = 4096;           // LDS box capacity (table elements: entries x F)
 
 template <typename TT> __device__ __forceinline__ float tload(const TT* p) { return (float)*p; }
 template <> __device__ __forceinline__ float tload<__half>(const __half* p) { return __half2float(*p); }
@@ -97,9 +100,13 @@ __global__ __launch_bounds__(256) void k_decode_fused(LevelDesc ld, MlpDesc md, 
   using op_t = typename std::conditional<BF16, bf16x8d, float>::type;
   using fe_t = typename std::conditional<BF16, __bf16, float>::type;
   constexpr int FROW = 32 + (BF16 ? 8 : 4);  // padded feature row (elements)
-  __shared__ __align__(16) op_t A[S::N_SLOTS * 64];
+  // bf16: each lane keeps its forward operands in registers (loaded from the
+  // arranged copy); fp32 (many more operands): staged in LDS
+  constexpr bool AREG = BF16;
+  __shared__ __align__(16) op_t A[AREG ? 1 : S::N_SLOTS * 64];
   __shared__ float wout[64];
-  __shared__ float boxv[kBoxFloats];
+  // the box in the table's own element type (fp16 halves the LDS of a box)
+  __shared__ TT boxv[kBoxElems];
   __shared__ __align__(16) fe_t feat[256 * FROW];
 
   const BlockMeta bm = meta[block];
@@ -121,7 +128,8 @@ __global__ __launch_bounds__(256) void k_decode_fused(LevelDesc ld, MlpDesc md, 
   // ---- forward operands of this block, arranged by k_dec_operands
   {
     const op_t* src = reinterpret_cast<const op_t*>(opnd);
-    for (int e = tid; e < S::N_SLOTS * 64; e += 256) A[e] = src[e];
+    if constexpr (!AREG)
+      for (int e = tid; e < S::N_SLOTS * 64; e += 256) A[e] = src[e];
     const float* wo = reinterpret_cast<const float*>(src + S::N_SLOTS * 64);
     for (int e = tid; e < W; e += 256) wout[e] = wo[e];
   }
@@ -152,14 +160,14 @@ __global__ __launch_bounds__(256) void k_decode_fused(LevelDesc ld, MlpDesc md, 
     float acc[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) acc[f] = 0.0f;
-    if (nv * F <= kBoxFloats) {
+    if (nv * F <= kBoxElems) {
       __syncthreads();  // previous level done with the box
       for (int v = tid; v < nv; v += 256) {
         const int lx = v % dx, ly = (v / dx) % dy, lz = v / (dx * dy);
         const uint32_t e = corner_index(dense, R, ld.T_mask, (uint32_t)(lo[0] + lx), (uint32_t)(lo[1] + ly),
                                         (uint32_t)(lo[2] + lz));
 #pragma unroll
-        for (int f = 0; f < F; ++f) boxv[v * F + f] = tload(tab + (int64_t)e * F + f);
+        for (int f = 0; f < F; ++f) boxv[v * F + f] = tab[(int64_t)e * F + f];
       }
       __syncthreads();
       const int bx = ix - lo[0], by = iy - lo[1], bz = iz - lo[2];
@@ -169,7 +177,7 @@ __global__ __launch_bounds__(256) void k_decode_fused(LevelDesc ld, MlpDesc md, 
         const float w = (cx ? tx : 1.0f - tx) * (cy ? ty : 1.0f - ty) * (cz ? tz : 1.0f - tz);
         const int v = (bx + cx) + dx * ((by + cy) + dy * (bz + cz));
 #pragma unroll
-        for (int f = 0; f < F; ++f) acc[f] += w * boxv[v * F + f];
+        for (int f = 0; f < F; ++f) acc[f] += w * tload(&boxv[v * F + f]);
       }
     } else {
 #pragma unroll
@@ -191,6 +199,18 @@ __global__ __launch_bounds__(256) void k_decode_fused(LevelDesc ld, MlpDesc md, 
   const int wave = tid / 64, lane = tid % 64;
   const int g = lane / 16, c = lane % 16;
   const BlockRange br = range[block];
+  op_t areg[AREG ? S::N_SLOTS : 1];
+  if constexpr (AREG) {
+    const op_t* src = reinterpret_cast<const op_t*>(opnd);
+#pragma unroll
+    for (int e = 0; e < S::N_SLOTS; ++e) areg[e] = src[e * 64 + lane];
+  }
+  auto opA = [&](int e) -> op_t {
+    if constexpr (AREG)
+      return areg[e];
+    else
+      return A[e * 64 + lane];
+  };
   for (int q = 0; q < 4; ++q) {
     const int vi = wave * 64 + q * 16 + c;  // voxel of the brick
     op_t xb[S::KS_IN];
@@ -208,9 +228,9 @@ __global__ __launch_bounds__(256) void k_decode_fused(LevelDesc ld, MlpDesc md, 
 #pragma unroll
       for (int s = 0; s < S::KS_IN; ++s) {
         if constexpr (BF16)
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[(m * S::KS_IN + s) * 64 + lane], xb[s], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opA(m * S::KS_IN + s), xb[s], acc, 0, 0, 0);
         else
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[(m * S::KS_IN + s) * 64 + lane], xb[s], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(opA(m * S::KS_IN + s), xb[s], acc, 0, 0, 0);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) h[m][i] = fmaxf(acc[i], 0.0f);
@@ -232,7 +252,7 @@ __global__ __launch_bounds__(256) void k_decode_fused(LevelDesc ld, MlpDesc md, 
         f32x4d acc = {0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < S::KS_H; ++s) {
-          const op_t a = A[(S::N_A0 + ((k - 1) * S::MT + m) * S::KS_H + s) * 64 + lane];
+          const op_t a = opA(S::N_A0 + ((k - 1) * S::MT + m) * S::KS_H + s);
           if constexpr (BF16)
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[s], acc, 0, 0, 0);
           else
