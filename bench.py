@@ -302,13 +302,16 @@ def speedups(results):
 PHASE_KERNEL = {"scatter_priv": "k_scatter_priv", "scatter": "k_scatter", "adam": "k_adam", "encode": "k_encode",
                 "mlp": "k_mlp_train", "sample": "k_sort_place", "reduce": "k_reduce_slots",
                 "part_bucket": "k_part_bucket", "part_accum": "k_part_accum"}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "train_step_256cube_hbm_counters.md")
+TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f"train_step_{n}_hbm_counters.md") for n in ("64blocks", "256cube")]
 
 
 KERNEL_SOURCES = {"k_scatter_priv": ["k_sort.hip", "dvnr_device.h", "dvnr_internal.h"],
                   "k_part_bucket": ["k_scatter_part.hip", "dvnr_device.h", "dvnr_internal.h"],
                   "k_part_accum": ["k_scatter_part.hip", "dvnr_device.h", "dvnr_internal.h"],
-                  "k_adam": ["k_core.hip", "dvnr_device.h", "dvnr_internal.h"]}
+                  "k_adam": ["k_core.hip", "dvnr_device.h", "dvnr_internal.h"],
+                  "k_encode": ["k_core.hip", "dvnr_device.h", "dvnr_internal.h"],
+                  "k_mlp_train": ["k_mlp.hip", "dvnr_device.h", "dvnr_internal.h"],
+                  "k_sort_place": ["k_sort.hip", "dvnr_device.h", "dvnr_internal.h"]}
 
 
 def sources_digest(kernel):
@@ -328,17 +331,18 @@ def measured_traffic(phase, workload):
     FETCH_SIZE / WRITE_SIZE summary, or None when the summary does not cover it,
     was taken on another workload, or the kernel sources changed since the
     counters were taken."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            for line in f:
-                if line.startswith("traffic-record:"):
-                    rec = json.loads(line.split(":", 1)[1])
-                    if (rec["kernel"] == PHASE_KERNEL.get(phase) and rec["kernel"] in KERNEL_SOURCES
-                            and rec.get("workload") == workload
-                            and rec["sources_sha256"] == sources_digest(rec["kernel"])):
-                        return rec["read_bytes"] + rec["write_bytes"]
-    except (OSError, ValueError, KeyError):
-        return None
+    for path in TRAFFIC_FILES:
+        try:
+            with open(path) as f:
+                for line in f:
+                    if line.startswith("traffic-record:"):
+                        rec = json.loads(line.split(":", 1)[1])
+                        if (rec["kernel"] == PHASE_KERNEL.get(phase) and rec["kernel"] in KERNEL_SOURCES
+                                and rec.get("workload") == workload
+                                and rec["sources_sha256"] == sources_digest(rec["kernel"])):
+                            return rec["read_bytes"] + rec["write_bytes"]
+        except (OSError, ValueError, KeyError):
+            continue
     return None
 
 

@@ -40,7 +40,7 @@ def test_traffic_record_scoped_to_workload_and_sources(tmp_path, monkeypatch):
     stale = dict(rec, kernel="k_part_bucket", sources_sha256="0" * 64)
     f = tmp_path / "counters.md"
     f.write_text("# counters\n\ntraffic-record: " + json.dumps(rec) + "\ntraffic-record: " + json.dumps(stale) + "\n")
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    monkeypatch.setattr(bench, "TRAFFIC_FILES", [str(tmp_path / "missing.md"), str(f)])
     assert bench.measured_traffic("part_accum", "c2") == 7
     assert bench.measured_traffic("part_accum", "c3") is None  # taken on another workload
     assert bench.measured_traffic("part_bucket", "c2") is None  # sources changed since
@@ -48,10 +48,11 @@ def test_traffic_record_scoped_to_workload_and_sources(tmp_path, monkeypatch):
 
 
 def test_committed_traffic_records_name_their_workload():
-    with open(bench.TRAFFIC_FILE) as fh:
-        recs = [json.loads(l.split(":", 1)[1]) for l in fh if l.startswith("traffic-record:")]
-    assert recs and all(r.get("workload") in ("c2", "c3", "c5") and r["kernel"] in bench.KERNEL_SOURCES
-                        for r in recs)
+    for path in bench.TRAFFIC_FILES:
+        with open(path) as fh:
+            recs = [json.loads(l.split(":", 1)[1]) for l in fh if l.startswith("traffic-record:")]
+        assert recs and all(r.get("workload") in ("c2", "c3", "c5") and r["kernel"] in bench.KERNEL_SOURCES
+                            for r in recs)
 
 
 def test_step_payload_of_the_batched_and_256cube_workloads():
