@@ -13,10 +13,13 @@
 // in LDS and feed the MFMA MLP forward, whose weight operands a small kernel
 // arranges once per block in operand order (staged element by element from
 // the weights by every brick, they took most of the decode's time); with bf16
-// each lane loads its operands straight into registers.  The decode is bound
-// by the latency of the per-level box loads, so LDS is kept small (the box
-// in the table's own fp16 elements, no operand copy in LDS) for five
-// workgroups per CU.
+// each lane loads its operands straight into registers.  LDS is kept small
+// (the box in the table's own fp16 elements, no operand copy in LDS) for five
+// workgroups per CU.  At that occupancy the kernel issues VALU instructions
+// on nearly every cycle, so the per-level work is kept lean: the box bounds
+// of all levels are computed once per brick, box vertices are split into
+// (x, y, z) with float reciprocals instead of integer division, and each lane
+// fills two box vertices per pass with both loads in flight.
 #include "dvnr_device.h"
 
 namespace dvnrk {
@@ -106,8 +109,10 @@ __global__ __launch_bounds__(256) void k_decode_fused(LevelDesc ld, MlpDesc md, 
   __shared__ __align__(16) op_t A[AREG ? 1 : S::N_SLOTS * 64];
   __shared__ float wout[64];
   // the box in the table's own element type (fp16 halves the LDS of a box)
-  __shared__ TT boxv[kBoxElems];
+  __shared__ __align__(16) TT boxv[kBoxElems + 8];  // + one spare vertex slot (F <= 8)
   __shared__ __align__(16) fe_t feat[256 * FROW];
+  __shared__ int lbox[kMaxLevels][6];  // per level: box origin (3), dx, dy, vertex count
+  __shared__ float lrcp[kMaxLevels][2];  // 1 / dx, 1 / dy
 
   const BlockMeta bm = meta[block];
   const int nx = bm.dims[0], ny = bm.dims[1], nz = bm.dims[2];
@@ -134,14 +139,12 @@ __global__ __launch_bounds__(256) void k_decode_fused(LevelDesc ld, MlpDesc md, 
     for (int e = tid; e < W; e += 256) wout[e] = wo[e];
   }
 
-  // ---- encoding, level by level through the LDS box
-  const TT* tab0 = table_all + bm.param_off;
-  for (int l = 0; l < ld.L; ++l) {
-    const int R = ld.R[l];
-    const float sc = ld.scale[l];
-    const int dense = ld.dense[l];
-    const TT* tab = tab0 + (int64_t)ld.off[l] * F;
-    int lo[3], hi[3], ii;
+  // ---- the brick's vertex box on every level, computed once: lane l of the
+  // first wave takes level l (the bounds are the same for every voxel)
+  if (tid < ld.L) {
+    const int R = ld.R[tid];
+    const float sc = ld.scale[tid];
+    int lo[3], hi[3];
     float tt;
     grid_pos(ax0, sc, R, lo[0], tt);
     grid_pos(ax1, sc, R, hi[0], tt);
@@ -149,9 +152,27 @@ __global__ __launch_bounds__(256) void k_decode_fused(LevelDesc ld, MlpDesc md, 
     grid_pos(ay1, sc, R, hi[1], tt);
     grid_pos(az0, sc, R, lo[2], tt);
     grid_pos(az1, sc, R, hi[2], tt);
-    (void)ii;
     const int dx = hi[0] - lo[0] + 2, dy = hi[1] - lo[1] + 2, dz = hi[2] - lo[2] + 2;
-    const int nv = dx * dy * dz;
+    lbox[tid][0] = lo[0];
+    lbox[tid][1] = lo[1];
+    lbox[tid][2] = lo[2];
+    lbox[tid][3] = dx;
+    lbox[tid][4] = dy;
+    lbox[tid][5] = dx * dy * dz;
+    lrcp[tid][0] = 1.0f / (float)dx;
+    lrcp[tid][1] = 1.0f / (float)dy;
+  }
+  __syncthreads();
+
+  // ---- encoding, level by level through the LDS box
+  const TT* tab0 = table_all + bm.param_off;
+  for (int l = 0; l < ld.L; ++l) {
+    const int R = ld.R[l];
+    const float sc = ld.scale[l];
+    const int dense = ld.dense[l];
+    const TT* tab = tab0 + (int64_t)ld.off[l] * F;
+    const int lo0 = lbox[l][0], lo1 = lbox[l][1], lo2 = lbox[l][2];
+    const int dx = lbox[l][3], dy = lbox[l][4], nv = lbox[l][5];
     int ix, iy, iz;
     float tx, ty, tz;
     grid_pos(px, sc, R, ix, tx);
@@ -161,21 +182,67 @@ __global__ __launch_bounds__(256) void k_decode_fused(LevelDesc ld, MlpDesc md, 
 #pragma unroll
     for (int f = 0; f < F; ++f) acc[f] = 0.0f;
     if (nv * F <= kBoxElems) {
+      const float rdx = lrcp[l][0], rdy = lrcp[l][1];
+      // box vertex v -> table entry.  v = lx + dx (ly + dy lz) is split with
+      // float reciprocals: for v < 2^22, (v + 1/2) / dx is at least 1/(2 dx)
+      // away from an integer and the two roundings move it by less, so the
+      // truncation is exactly floor(v / dx) (likewise for dy).
+      auto entry = [&](int v) -> uint32_t {
+        const int q = (int)(((float)v + 0.5f) * rdx);
+        const int lx = v - q * dx;
+        const int lz = (int)(((float)q + 0.5f) * rdy);
+        const int ly = q - lz * dy;
+        const uint32_t gx = (uint32_t)(lo0 + lx), gy = (uint32_t)(lo1 + ly), gz = (uint32_t)(lo2 + lz);
+        // dense levels have R^3 <= T <= 2^24 entries: 24-bit products suffice
+        if (dense) return gx + __umul24((uint32_t)R, gy + __umul24((uint32_t)R, gz));
+        return (gx ^ (gy * 2654435761u) ^ (gz * 805459861u)) & ld.T_mask;
+      };
       __syncthreads();  // previous level done with the box
-      for (int v = tid; v < nv; v += 256) {
-        const int lx = v % dx, ly = (v / dx) % dy, lz = v / (dx * dy);
-        const uint32_t e = corner_index(dense, R, ld.T_mask, (uint32_t)(lo[0] + lx), (uint32_t)(lo[1] + ly),
-                                        (uint32_t)(lo[2] + lz));
+      // two vertices per lane and pass, both loads in flight together: the
+      // second index is clamped into the box and, past its end, stored to a
+      // spare slot behind the box (never read), so nothing is conditional
+      for (int v0 = tid; v0 < nv; v0 += 512) {
+        const int v1 = v0 + 256;
+        const uint32_t e0 = entry(v0), e1 = entry(min(v1, nv - 1));
+        const int s1 = v1 < nv ? v1 : kBoxElems / F;
+        if constexpr (sizeof(TT) * F % 4 == 0) {
+          // an entry's F elements as 4-byte words (tables start 4-byte aligned)
+          constexpr int NW = sizeof(TT) * F / 4;
+          const uint32_t* tw = reinterpret_cast<const uint32_t*>(tab);
+          uint32_t* bw = reinterpret_cast<uint32_t*>(boxv);
+          uint32_t r0[NW], r1[NW];
 #pragma unroll
-        for (int f = 0; f < F; ++f) boxv[v * F + f] = tab[(int64_t)e * F + f];
+          for (int w = 0; w < NW; ++w) {
+            r0[w] = tw[(int64_t)e0 * NW + w];
+            r1[w] = tw[(int64_t)e1 * NW + w];
+          }
+#pragma unroll
+          for (int w = 0; w < NW; ++w) {
+            bw[v0 * NW + w] = r0[w];
+            bw[s1 * NW + w] = r1[w];
+          }
+        } else {
+          TT r0[F], r1[F];
+#pragma unroll
+          for (int f = 0; f < F; ++f) {
+            r0[f] = tab[(int64_t)e0 * F + f];
+            r1[f] = tab[(int64_t)e1 * F + f];
+          }
+#pragma unroll
+          for (int f = 0; f < F; ++f) {
+            boxv[v0 * F + f] = r0[f];
+            boxv[s1 * F + f] = r1[f];
+          }
+        }
       }
       __syncthreads();
-      const int bx = ix - lo[0], by = iy - lo[1], bz = iz - lo[2];
+      const int dxy = dx * dy;
+      const int base = (ix - lo0) + __mul24(dx, (iy - lo1) + __mul24(dy, iz - lo2));
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const int cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
         const float w = (cx ? tx : 1.0f - tx) * (cy ? ty : 1.0f - ty) * (cz ? tz : 1.0f - tz);
-        const int v = (bx + cx) + dx * ((by + cy) + dy * (bz + cz));
+        const int v = base + cx + (cy ? dx : 0) + (cz ? dxy : 0);
 #pragma unroll
         for (int f = 0; f < F; ++f) acc[f] += w * tload(&boxv[v * F + f]);
       }
