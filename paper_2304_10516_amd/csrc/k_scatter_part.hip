@@ -31,9 +31,15 @@
 namespace dvnrk {
 
 #ifndef DVNR_PART_ACCUM_THREADS
-#define DVNR_PART_ACCUM_THREADS 512
+#define DVNR_PART_ACCUM_THREADS 1024
 #endif
 constexpr int kPartAccumThreads = DVNR_PART_ACCUM_THREADS;  // threads of a slice-pass workgroup
+
+// Word 3 of a raw buffer resource on gfx9-family chips (32-bit data format,
+// no swizzle, stride 0): accesses are range-checked against the byte count
+// of word 2.
+constexpr int kBufferDword3 = 0x00020000;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // Exclusive prefix sum over the 256 lanes of a workgroup; `total` receives the sum.
 __device__ __forceinline__ int wg_exclusive_scan(int v, int* wsum, int& total) {
@@ -211,8 +217,16 @@ __global__ __launch_bounds__(256) void k_part_bucket(LevelDesc ld, PartDesc pd, 
   }
 }
 
+// 1024 threads with at most 64 VGPRs: two workgroups of an 8192-accumulator
+// slice (64 KB of LDS each) share a CU with 32 waves, enough loads in flight
+// to stream the Adam operands (512 threads at 98 VGPRs: 16 waves, the pass
+// 15 % slower on the 64-block workload).  Waves per SIMD to plan registers
+// for: two workgroups where the LDS allows two, one otherwise (and for F = 8,
+// whose records would not fit 64 registers without spilling).
+constexpr int part_accum_waves(int F, int SF, int NT) { return (SF <= 8192 && F <= 4 ? 2 : 1) * NT / 256; }
+
 template <int F, int SF, int NT>
-__global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, const BlockMeta* __restrict__ meta,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(part_accum_waves(F, SF, NT)))) void k_part_accum(LevelDesc ld, PartDesc pd, const BlockMeta* __restrict__ meta,
                                                     int n_tiles, const BlockPlan* __restrict__ plan,
                                                     const PartBlock* __restrict__ pb, int32_t* __restrict__ cursor,
                                                     const uint32_t* __restrict__ recs,
@@ -220,7 +234,7 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
                                                     PartAdam adam, int do_adam, uint8_t* __restrict__ ovf) {
   constexpr int RW = PartRec<F>::RW;
   constexpr bool PACK = F == 2;
-  constexpr int U = 8;  // records per lane and batch (two batches in flight)
+  constexpr int U = NT >= 1024 ? 4 : 8;  // records per lane and batch (two batches in flight)
   __shared__ unsigned long long acc[SF];
   __shared__ int sstart[kPartSub + 1];
   __shared__ float wmax[NT / 64];
@@ -303,20 +317,42 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
   constexpr int PT = SF / NT / VW, KB = PT < 4 ? PT : 4;
   typedef float fv __attribute__((ext_vector_type(VW)));
   const int nv = nf / VW;  // accesses covering the slice (nf is a multiple of F)
-  auto ldv = [&](const float* base, int a) {
+  auto ldv = [&](const float* base, uint32_t a) {
     fv x;
     __builtin_memcpy(&x, base + a * VW, sizeof(fv));
     return x;
   };
-  auto stv = [&](float* base, int a, fv x) { __builtin_memcpy(base + a * VW, &x, sizeof(fv)); };
+  // The Adam operands are accessed through buffer resources that span the
+  // slice exactly: the hardware range check turns loads past the slice's end
+  // into zeros and drops stores there, so the accesses need neither clamping
+  // nor branches, and all of them share one 32-bit offset register.
+  const uint32_t sbytes = (uint32_t)nv * VW * 4;
+  auto rsrc = [&](const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufferDword3);
+  };
+  auto bld = [&](__amdgpu_buffer_rsrc_t r, uint32_t a) -> fv {
+    if constexpr (VW == 2) {
+      const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, a * 8u, 0, 0);
+      return fv{__uint_as_float(x[0]), __uint_as_float(x[1])};
+    } else {
+      return fv(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, a * 4u, 0, 0)));
+    }
+  };
+  auto bst = [&](__amdgpu_buffer_rsrc_t r, uint32_t a, fv x) {
+    if constexpr (VW == 2)
+      __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(x[0]), __float_as_uint(x[1])}, r, a * 8u, 0, 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x[0]), r, a * 4u, 0, 0);
+  };
   fv th[KB], mm[KB], vv[KB];  // Adam operands of the batch in flight
   auto load_adam = [&](int k0) {
+    const auto rp = rsrc(adam.params + el0, sbytes), rm = rsrc(adam.m + el0, sbytes), rv = rsrc(adam.v + el0, sbytes);
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
-      const int a = min(tid + NT * (k0 + k), nv - 1);
-      th[k] = ldv(adam.params + el0, a);
-      mm[k] = ldv(adam.m + el0, a);
-      vv[k] = ldv(adam.v + el0, a);
+      const uint32_t a = (uint32_t)(tid + NT * (k0 + k));
+      th[k] = bld(rp, a);
+      mm[k] = bld(rm, a);
+      vv[k] = bld(rv, a);
     }
   };
   uint32_t vn[U][RW];
@@ -369,23 +405,12 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
   // conversion and an exact scaling by 2^-K
   float* g = grad + el0;
   // overflow records of this bucket went to the gradient by atomics
-  const bool rd_g = !do_adam || has_ovf;
-  if (do_adam) load_adam(0);
-  // read-add-write of the slice (or its Adam update) in batches of KB accesses
-  // per lane (clamped to the slice, so that a lane's loads overlap); with Adam
-  // the next batch's operands are loaded before this batch is updated.
-  // Addresses are 32-bit offsets from the slice's first element.
-  for (int k0 = 0; k0 < PT; k0 += KB) {
-    fv gv[KB];
+  if (!do_adam) {
+    // read-add-write of the slice's nonzero sums, KB accesses per lane at a time
+    for (int k0 = 0; k0 < PT; k0 += KB) {
+      fv gv[KB];
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      const int a = min(tid + NT * (k0 + k), nv - 1);
-      if (rd_g)
-        gv[k] = ldv(g, a);
-      else
-        gv[k] = fv(0.0f);
-    }
-    if (!do_adam) {
+      for (int k = 0; k < KB; ++k) gv[k] = ldv(g, min(tid + NT * (k0 + k), nv - 1));
 #pragma unroll
       for (int k = 0; k < KB; ++k) {
         const int a = tid + NT * (k0 + k);
@@ -397,45 +422,80 @@ __global__ __launch_bounds__(NT) void k_part_accum(LevelDesc ld, PartDesc pd, co
           }
         }
       }
-      continue;
     }
-    fv th0[KB], mm0[KB], vv0[KB];
+    return;
+  }
+  // The Adam update of the slice in batches of KB accesses per lane; the next
+  // batch's operands are loaded before this batch is updated.  No store is
+  // conditional (a branch around the stores made the compiler wait for the
+  // next batch's loads before each update).  OVF: the bucket overflowed and
+  // its excess records went to the gradient by atomics; W16: the 16-bit
+  // working copy is written too.
+  load_adam(0);
+  const float bc2 = hbc[1], lrbc1 = hbc[2] * hbc[0];
+  auto update = [&](auto ovf_tag, auto w16_tag) {
+    constexpr bool OVF = decltype(ovf_tag)::value, W16 = decltype(w16_tag)::value;
+    const auto rp = rsrc(adam.params + el0, sbytes), rm = rsrc(adam.m + el0, sbytes), rv = rsrc(adam.v + el0, sbytes);
+    const auto rg = rsrc(g, sbytes), rw = rsrc(adam.work16 + el0, sbytes / 2);
+    for (int k0 = 0; k0 < PT; k0 += KB) {
+      fv gv[KB];
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      th0[k] = th[k];
-      mm0[k] = mm[k];
-      vv0[k] = vv[k];
-    }
-    if (k0 + KB < PT) load_adam(k0 + KB);
-    const float bc2 = hbc[1], lrbc1 = hbc[2] * hbc[0];
-#pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      const int a = tid + NT * (k0 + k);
-      if (a >= nv) continue;
-      fv t1, m1, v1;
-#pragma unroll
-      for (int c = 0; c < VW; ++c) {
-        const float gg = gv[k][c] + ldexpf((float)(long long)acc[a * VW + c], -K) + adam.wd * th0[k][c];
-        m1[c] = adam.b1 * mm0[k][c] + adam.omb1 * gg;
-        v1[c] = adam.b2 * vv0[k][c] + adam.omb2 * gg * gg;
-        // hardware square root and reciprocal (about 1 ulp each): the step
-        // lr m_hat / (sqrt(v_hat) + eps) is within a few float roundings
-        t1[c] = th0[k][c] - lrbc1 * m1[c] * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(v1[c] * bc2) + adam.eps);
+      for (int k = 0; k < KB; ++k) {
+        if constexpr (OVF)
+          gv[k] = bld(rg, (uint32_t)(tid + NT * (k0 + k)));
+        else
+          gv[k] = fv(0.0f);
       }
-      stv(adam.params + el0, a, t1);
-      stv(adam.m + el0, a, m1);
-      stv(adam.v + el0, a, v1);
-      if (adam.work16) {
-        uint16_t h16[VW];
+      fv th0[KB], mm0[KB], vv0[KB];
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        th0[k] = th[k];
+        mm0[k] = mm[k];
+        vv0[k] = vv[k];
+      }
+      if (k0 + KB < PT) load_adam(k0 + KB);
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        const uint32_t a = (uint32_t)(tid + NT * (k0 + k));
+        fv t1, m1, v1;
 #pragma unroll
         for (int c = 0; c < VW; ++c) {
-          const __half hv = __float2half_rn(t1[c]);
-          h16[c] = *reinterpret_cast<const uint16_t*>(&hv);
+          const float gg = gv[k][c] + ldexpf((float)(long long)acc[a * VW + c], -K) + adam.wd * th0[k][c];
+          m1[c] = adam.b1 * mm0[k][c] + adam.omb1 * gg;
+          v1[c] = adam.b2 * vv0[k][c] + adam.omb2 * gg * gg;
+          // hardware square root and reciprocal (about 1 ulp each): the step
+          // lr m_hat / (sqrt(v_hat) + eps) is within a few float roundings
+          t1[c] = th0[k][c] - lrbc1 * m1[c] * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(v1[c] * bc2) + adam.eps);
         }
-        __builtin_memcpy(adam.work16 + el0 + a * VW, h16, sizeof(h16));
+        bst(rp, a, t1);
+        bst(rm, a, m1);
+        bst(rv, a, v1);
+        if constexpr (W16) {
+          uint32_t h = 0;
+#pragma unroll
+          for (int c = 0; c < VW; ++c) {
+            const __half hv = __float2half_rn(t1[c]);
+            h |= (uint32_t)(*reinterpret_cast<const uint16_t*>(&hv)) << (16 * c);
+          }
+          if constexpr (VW == 2)
+            __builtin_amdgcn_raw_buffer_store_b32(h, rw, a * 4u, 0, 0);
+          else
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)h, rw, a * 2u, 0, 0);
+        }
+        if constexpr (OVF) bst(rg, a, fv(0.0f));
       }
-      if (has_ovf) stv(g, a, fv(0.0f));
     }
+  };
+  if (has_ovf) {
+    if (adam.work16)
+      update(std::true_type{}, std::true_type{});
+    else
+      update(std::true_type{}, std::false_type{});
+  } else {
+    if (adam.work16)
+      update(std::false_type{}, std::true_type{});
+    else
+      update(std::false_type{}, std::false_type{});
   }
 }
 
