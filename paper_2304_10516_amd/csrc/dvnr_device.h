@@ -132,9 +132,11 @@ __device__ __forceinline__ void grid_pos(float x, float scale, int R, int& i0, f
 
 // Spatial hash of the multiresolution hash encoding: XOR of coordinate
 // times prime (1, 2654435761, 805459861) modulo 2^32, masked to the table.
+// A dense level has R^3 <= T <= 2^24 entries, so its index is formed with
+// 24-bit products (full-rate instructions; a 32-bit multiply is quarter rate).
 __device__ __forceinline__ uint32_t corner_index(int dense, int R, uint32_t mask, uint32_t vx, uint32_t vy,
                                                  uint32_t vz) {
-  if (dense) return vx + (uint32_t)R * (vy + (uint32_t)R * vz);
+  if (dense) return vx + __umul24((uint32_t)R, vy + __umul24((uint32_t)R, vz));
   return (vx ^ (vy * 2654435761u) ^ (vz * 805459861u)) & mask;
 }
 

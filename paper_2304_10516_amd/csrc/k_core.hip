@@ -136,62 +136,101 @@ hipError_t launch_sample(const BlockMeta* meta, const BlockRange* range, const B
 // four corners in the order (cy, cz) = (0,0), (1,0), (0,1), (1,1); the pair's
 // sums are added (cx = 0 first).
 // ===========================================================================
-template <typename TT, typename WT, typename OT, int F>
+// With LPW = 2 (a launch of more than 8 levels on the XCD-aware mapping) a
+// workgroup takes both levels that its XCD serves, x and x + 8, for one tile:
+// the sample's coordinates are read once and a lane has eight loads in
+// flight instead of four.  When level x + 8 is not in the launch the lane
+// repeats level x's loads and skips the second write.
+#ifndef DVNR_ENCODE_LEVELS_PER_WG
+#define DVNR_ENCODE_LEVELS_PER_WG 2
+#endif
+constexpr int kEncodeLevelsPerWg = DVNR_ENCODE_LEVELS_PER_WG;  // 1 or 2
+
+template <typename TT, typename WT, typename OT, int F, int LPW>
 __global__ __launch_bounds__(2 * kTile) void k_encode(LevelDesc ld, const BlockMeta* __restrict__ meta,
                                                       const Tile* __restrict__ tiles, int n_tiles, int64_t n_direct,
                                                       int direct_block, const BlockPlan* __restrict__ plan,
                                                       const float* __restrict__ coords, const TT* __restrict__ table,
                                                       OT* __restrict__ out, int64_t ss, int64_t ls, int xcd_map,
                                                       int l0, int nl) {
-  int tile, l;
-  if (!level_major_item(blockIdx.x, l0, nl, n_tiles, xcd_map, tile, l)) return;
+  int tile, lv[LPW];
+  bool second = false;
+  if constexpr (LPW == 1) {
+    if (!level_major_item(blockIdx.x, l0, nl, n_tiles, xcd_map, tile, lv[0])) return;
+  } else {
+    const int x = blockIdx.x & 7;
+    tile = blockIdx.x >> 3;
+    if (tile >= n_tiles || x >= nl) return;
+    second = x + 8 < nl;
+    lv[0] = l0 + x;
+    lv[1] = second ? l0 + x + 8 : l0 + x;
+  }
   const uint32_t cx = threadIdx.x & 1;
   // both lanes of a pair share the sample, so they leave together
   const SampleRef r = sample_ref(tiles, plan, tile, n_direct, direct_block, threadIdx.x >> 1);
   if (!r.valid) return;
   const float x = coords[3 * r.gi + 0], y = coords[3 * r.gi + 1], z = coords[3 * r.gi + 2];
-  int ix, iy, iz;
-  float tx, ty, tz;
-  const int R = ld.R[l];
-  grid_pos(x, ld.scale[l], R, ix, tx);
-  grid_pos(y, ld.scale[l], R, iy, ty);
-  grid_pos(z, ld.scale[l], R, iz, tz);
-  const TT* tab = table + (meta ? meta[r.block].param_off : 0) + (int64_t)ld.off[l] * F;
-  const int dense = ld.dense[l];
-  const WT wx = cx ? (WT)tx : (WT)1 - (WT)tx;
-  const WT wy[2] = {(WT)1 - (WT)ty, (WT)ty};
-  const WT wz[2] = {(WT)1 - (WT)tz, (WT)tz};
-  TT v[4][F];
+  const TT* tab0 = table + (meta ? meta[r.block].param_off : 0);
+  WT wx[LPW], wy[LPW][2], wz[LPW][2];
+  TT v[LPW][4][F];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {  // loads first, all in flight together
-    const uint32_t cy = k & 1, cz = k >> 1;
-    const uint32_t e = corner_index(dense, R, ld.T_mask, ix + cx, iy + cy, iz + cz);
+  for (int j = 0; j < LPW; ++j) {  // loads first, all in flight together
+    const int l = lv[j];
+    int ix, iy, iz;
+    float tx, ty, tz;
+    const int R = ld.R[l];
+    grid_pos(x, ld.scale[l], R, ix, tx);
+    grid_pos(y, ld.scale[l], R, iy, ty);
+    grid_pos(z, ld.scale[l], R, iz, tz);
+    const TT* tab = tab0 + (int64_t)ld.off[l] * F;
+    const int dense = ld.dense[l];
+    wx[j] = cx ? (WT)tx : (WT)1 - (WT)tx;
+    wy[j][0] = (WT)1 - (WT)ty;
+    wy[j][1] = (WT)ty;
+    wz[j][0] = (WT)1 - (WT)tz;
+    wz[j][1] = (WT)tz;
+    // the four indices first, branch-free (both forms, then a select), so
+    // that the four loads issue back to back from one basic block
+    uint32_t e[4];
 #pragma unroll
-    for (int f = 0; f < F; ++f) v[k][f] = tab[(int64_t)e * F + f];
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t cy = k & 1, cz = k >> 1;
+      const uint32_t gx = ix + cx, gy = iy + cy, gz = iz + cz;
+      const uint32_t ed = gx + __umul24((uint32_t)R, gy + __umul24((uint32_t)R, gz));
+      const uint32_t eh = (gx ^ (gy * 2654435761u) ^ (gz * 805459861u)) & ld.T_mask;
+      e[k] = dense ? ed : eh;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int f = 0; f < F; ++f) v[j][k][f] = tab[(int64_t)e[k] * F + f];
   }
-  WT acc[F];
 #pragma unroll
-  for (int f = 0; f < F; ++f) acc[f] = 0;
+  for (int j = 0; j < LPW; ++j) {
+    WT acc[F];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const WT w = wx * wy[k & 1] * wz[k >> 1];
+    for (int f = 0; f < F; ++f) acc[f] = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const WT w = wx[j] * wy[j][k & 1] * wz[j][k >> 1];
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        if constexpr (sizeof(WT) == 8)
+          acc[f] += w * to_d(v[j][k][f]);
+        else
+          acc[f] += w * to_f(v[j][k][f]);
+      }
+    }
 #pragma unroll
     for (int f = 0; f < F; ++f) {
-      if constexpr (sizeof(WT) == 8)
-        acc[f] += w * to_d(v[k][f]);
-      else
-        acc[f] += w * to_f(v[k][f]);
+      const WT o = __shfl_xor(acc[f], 1, 64);
+      acc[f] = cx ? o + acc[f] : acc[f] + o;  // (cx = 0 sum) + (cx = 1 sum) on both lanes
     }
-  }
+    if (cx == 0 && (j == 0 || second)) {
+      OT* o = out + r.gi * ss + (int64_t)lv[j] * ls;
 #pragma unroll
-  for (int f = 0; f < F; ++f) {
-    const WT o = __shfl_xor(acc[f], 1, 64);
-    acc[f] = cx ? o + acc[f] : acc[f] + o;  // (cx = 0 sum) + (cx = 1 sum) on both lanes
-  }
-  if (cx == 0) {
-    OT* o = out + r.gi * ss + (int64_t)l * ls;
-#pragma unroll
-    for (int f = 0; f < F; ++f) o[f] = (OT)acc[f];
+      for (int f = 0; f < F; ++f) o[f] = (OT)acc[f];
+    }
   }
 }
 
@@ -199,17 +238,33 @@ template <typename TT, typename WT, typename OT>
 static hipError_t enc_dispatch(const LevelDesc& ld, const BlockMeta* meta, const Tile* tiles, int n_tiles,
                                int64_t n_direct, int direct_block, const BlockPlan* plan, const float* coords, const void* table,
                                void* out, int64_t ss, int64_t ls, int xcd_map, int l0, int nl, hipStream_t s) {
-  const int grid = level_major_grid(nl, n_tiles, xcd_map);
+  // two levels per workgroup where the XCD-aware mapping gives an XCD two
+  // levels (9 to 16 levels in the launch)
+  const bool two = kEncodeLevelsPerWg == 2 && xcd_map && nl > 8 && nl <= 16;
+  const int64_t grid = two ? 8 * (int64_t)n_tiles : (int64_t)level_major_grid(nl, n_tiles, xcd_map);
   if (grid <= 0) return hipSuccess;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
   const TT* t = (const TT*)table;
   OT* o = (OT*)out;
+#define DVNR_ENC_LAUNCH(FF, LL)                                                                                  \
+  hipLaunchKernelGGL((k_encode<TT, WT, OT, FF, LL>), dim3((unsigned)grid), dim3(2 * kTile), 0, s, ld, meta, tiles, \
+                     n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl)
+#define DVNR_ENC_CASE(FF)       \
+  case FF:                      \
+    if (two)                    \
+      DVNR_ENC_LAUNCH(FF, 2);   \
+    else                        \
+      DVNR_ENC_LAUNCH(FF, 1);   \
+    break;
   switch (ld.F) {
-    case 1: hipLaunchKernelGGL((k_encode<TT, WT, OT, 1>), dim3(grid), dim3(2 * kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
-    case 2: hipLaunchKernelGGL((k_encode<TT, WT, OT, 2>), dim3(grid), dim3(2 * kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
-    case 4: hipLaunchKernelGGL((k_encode<TT, WT, OT, 4>), dim3(grid), dim3(2 * kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
-    case 8: hipLaunchKernelGGL((k_encode<TT, WT, OT, 8>), dim3(grid), dim3(2 * kTile), 0, s, ld, meta, tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl); break;
+    DVNR_ENC_CASE(1)
+    DVNR_ENC_CASE(2)
+    DVNR_ENC_CASE(4)
+    DVNR_ENC_CASE(8)
     default: return hipErrorInvalidValue;
   }
+#undef DVNR_ENC_CASE
+#undef DVNR_ENC_LAUNCH
   return hipGetLastError();
 }
 
