@@ -454,7 +454,9 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *                          concurrently with the others (default 0)
  *  "encode_binned"   0/1 : with ordered sampling, interpolate the coarse levels
  *                          (bin box within 16 KB and at most half the bin's
- *                          direct gathers) from LDS-staged boxes (default 1)
+ *                          direct gathers) from LDS-staged boxes (default 0:
+ *                          the tile encoding, two levels per workgroup, is
+ *                          faster on every level)
  *  "priv_classes"  -1/0/1 : launch the privatized levels in three LDS-size
  *                          classes (small boxes, large boxes, direct) instead
  *                          of one launch (-1, the default: by class when the

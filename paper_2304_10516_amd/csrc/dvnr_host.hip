@@ -92,7 +92,7 @@ struct dvnr {
   int sort_B = 0, priv_L = 0, n_groups = 0;
   int priv_small = 0, priv_direct = 0;  // LDS classes: small [0, priv_small), large up to priv_direct, then direct
   int priv_classes = -1;  // launch the privatized levels by LDS class (0: one launch; -1: one block, partitioned)
-  int encode_binned = 1;                // ordered samples: LDS-staged encoding of the levels whose box fits
+  int encode_binned = 0;                // ordered samples: LDS-staged encoding of the levels whose box fits
   int enc_binned = 0;                   // levels [0, enc_binned) of the current plan
   std::vector<Tile> hgroups;
   std::vector<int32_t> hgrange;
