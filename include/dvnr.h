@@ -442,10 +442,12 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *                          (default 1 for mixed, 0 for fp32); enables the
  *                          bin-privatized backward of the coarse levels
  *  "priv_levels"     n   : privatize levels [0, n) (-1: chosen per plan)
- *  "sample_ahead"    0/1 : with ordered sampling and graph replays, draw step
+ *  "sample_ahead"  0..3 : with ordered sampling and graph replays, draw step
  *                          i + 1's samples on a third stream while step i
- *                          trains (two sample sets; default 1).  The first
- *                          step of each training call draws its own.
+ *                          trains (two sample sets), forked at the start of
+ *                          step i (1), after its encoding (2, the default)
+ *                          or after its MLP (3); 0: off.  The first step of
+ *                          each training call draws its own.
  *  "sort_bins"       n   : spatial bins per axis of ordered sampling, 1..8
  *                          (0, the default: the most that keep at least 192
  *                          samples per bin in the block with the fewest)

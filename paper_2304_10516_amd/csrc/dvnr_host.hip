@@ -147,7 +147,7 @@ struct dvnr {
              ev_join3 = nullptr;
   // sampler look-ahead (option "sample_ahead", graph replays with ordered
   // sampling): a third stream draws step i + 1's samples while step i trains
-  int sample_ahead = 1;
+  int sample_ahead = 2;
   hipStream_t ahead = nullptr;
   hipEvent_t ev_fork4 = nullptr, ev_join4 = nullptr;
   hipGraphExec_t graph_ahead[2] = {nullptr, nullptr};  // the step on sample set p, drawing into 1 - p
@@ -833,7 +833,11 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s, int set = 0, 
   const bool sorted = gen && h->spatial_sort && h->n_groups > 0;
   if (ahead && !sorted) return fail(DVNR_E_STATE, "sampler look-ahead needs ordered sampling");
   PROF(0);
-  if (ahead) {
+  // the next step's sampler on the third stream, forked at the point of this
+  // step that option sample_ahead names (1: its start, 2: after the encoding,
+  // 3: after the MLP)
+  auto fork_ahead = [&](int at) -> dvnr_status {
+    if (!ahead || h->sample_ahead != at) return DVNR_OK;
     if (!h->ahead) {
       HIPCHK(hipStreamCreateWithFlags(&h->ahead, hipStreamNonBlocking));
       HIPCHK(hipEventCreateWithFlags(&h->ev_fork4, hipEventDisableTiming));
@@ -844,6 +848,11 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s, int set = 0, 
     dvnr_status st = enqueue_sorted_sample(h, 1 - set, 1, h->ahead);
     if (st) return st;
     HIPCHK(hipEventRecord(h->ev_join4, h->ahead));
+    return DVNR_OK;
+  };
+  if (ahead) {
+    dvnr_status st = fork_ahead(1);
+    if (st) return st;
   } else if (sorted) {
     dvnr_status st = enqueue_sorted_sample(h, set, 0, s);
     if (st) return st;
@@ -873,11 +882,19 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s, int set = 0, 
                        h->enc.n_levels));
   if (econc) HIPCHK(hipStreamWaitEvent(s, h->ev_join3, 0));
   PROF(2);
+  {
+    dvnr_status st = fork_ahead(2);
+    if (st) return st;
+  }
   const void* wsrc = mixed ? (const void*)((const uint16_t*)h->buf.work16 + h->n_table)
                            : (const void*)((const float*)h->buf.params + h->n_table);
   HIPCHK(launch_mlp_train(h->prec, h->md, h->ld, h->d_meta(), h->d_plan(), h->d_tiles(), h->n_tiles, h->d_feat(),
                           h->d_target(set), wsrc, h->d_dfeat(), h->max_batch, h->d_slots(), h->slot_stride, h->mlp_grid,
                           h->loss_l1, h->mlp_waves, s));
+  {
+    dvnr_status st = fork_ahead(3);
+    if (st) return st;
+  }
   PROF(3);
   const int lf = h->part_l0;  // levels [lf, L): destination-partitioned
   const int lp = std::min(sorted ? h->priv_L : 0, lf);
@@ -1829,7 +1846,8 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
   } else if (n == "spatial_sort") {
     h->spatial_sort = value ? 1 : 0;
   } else if (n == "sample_ahead") {
-    h->sample_ahead = value ? 1 : 0;
+    if (value < 0 || value > 3) return fail(DVNR_E_INVALID, "sample_ahead: 0 (off), 1, 2 or 3");
+    h->sample_ahead = (int)value;
   } else if (n == "sort_bins") {
     if (value < 0 || value > 8) return fail(DVNR_E_INVALID, "sort_bins: 0 (automatic) or 1..8");
     h->sort_bins = (int)value;

@@ -703,7 +703,8 @@ def test_sampler_lookahead_draws_the_same_samples(precision):
     p0[:lay.n_table_params] *= 1e3
     blocks = [((32, 32, 32), 0), ((32, 32, 32), 0)]
     runs = {}
-    for name, ahead, calls in (("ahead", 1, 1), ("ahead, one step per call", 1, 6), ("inline", 0, 1)):
+    for name, ahead, calls in (("ahead", 2, 1), ("ahead, one step per call", 2, 6), ("ahead at step start", 1, 1),
+                               ("ahead after the MLP", 3, 1), ("inline", 0, 1)):
         model = make(C1, blocks, precision=precision, max_batch=4096, seed=5)
         model.bind_volumes([dev(vol), dev(vol[::-1].copy())])
         model.load_params([p0, p0])
@@ -720,6 +721,8 @@ def test_sampler_lookahead_draws_the_same_samples(precision):
     tol = 1e-5 if precision == "fp32" else 1e-3
     np.testing.assert_allclose(runs["ahead"], runs["inline"], rtol=tol, atol=0)
     np.testing.assert_allclose(runs["ahead, one step per call"], runs["inline"], rtol=tol, atol=0)
+    np.testing.assert_allclose(runs["ahead at step start"], runs["inline"], rtol=tol, atol=0)
+    np.testing.assert_allclose(runs["ahead after the MLP"], runs["inline"], rtol=tol, atol=0)
     # the first step's draws are the oracle's (step 0, block b)
     model = make(C1, blocks, precision="fp32", max_batch=4096, seed=5)
     model.bind_volumes([dev(vol), dev(vol)])
