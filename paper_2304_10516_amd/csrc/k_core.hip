@@ -137,101 +137,133 @@ hipError_t launch_sample(const BlockMeta* meta, const BlockRange* range, const B
 // sums are added (cx = 0 first).
 // ===========================================================================
 // With LPW = 2 (a launch of more than 8 levels on the XCD-aware mapping) a
-// workgroup takes both levels that its XCD serves, x and x + 8, for one tile:
-// the sample's coordinates are read once and a lane has eight loads in
-// flight instead of four.  When level x + 8 is not in the launch the lane
-// repeats level x's loads and skips the second write.
+// workgroup takes both levels that its XCD serves, x and x + 8, for SPT
+// consecutive tiles: each sample's coordinates are read once and a lane has
+// 4 LPW SPT gathers in flight.  When level x + 8 is not in the launch the
+// lane repeats level x's loads and skips the second write; a sample past its
+// tile's end interpolates the cube's center and writes nothing.
 #ifndef DVNR_ENCODE_LEVELS_PER_WG
 #define DVNR_ENCODE_LEVELS_PER_WG 2
 #endif
 constexpr int kEncodeLevelsPerWg = DVNR_ENCODE_LEVELS_PER_WG;  // 1 or 2
+#ifndef DVNR_ENCODE_TILES_PER_WG
+#define DVNR_ENCODE_TILES_PER_WG 2
+#endif
+constexpr int kEncodeTilesPerWg = DVNR_ENCODE_TILES_PER_WG;  // tiles per workgroup with two levels (1 or 2)
 
-template <typename TT, typename WT, typename OT, int F, int LPW>
+template <typename TT, typename WT, typename OT, int F, int LPW, int SPT>
 __global__ __launch_bounds__(2 * kTile) void k_encode(LevelDesc ld, const BlockMeta* __restrict__ meta,
                                                       const Tile* __restrict__ tiles, int n_tiles, int64_t n_direct,
                                                       int direct_block, const BlockPlan* __restrict__ plan,
                                                       const float* __restrict__ coords, const TT* __restrict__ table,
                                                       OT* __restrict__ out, int64_t ss, int64_t ls, int xcd_map,
                                                       int l0, int nl) {
-  int tile, lv[LPW];
+  static_assert(LPW == 2 || SPT == 1, "several tiles per workgroup only with two levels");
+  int tile0, lv[LPW];
   bool second = false;
   if constexpr (LPW == 1) {
-    if (!level_major_item(blockIdx.x, l0, nl, n_tiles, xcd_map, tile, lv[0])) return;
+    if (!level_major_item(blockIdx.x, l0, nl, n_tiles, xcd_map, tile0, lv[0])) return;
   } else {
     const int x = blockIdx.x & 7;
-    tile = blockIdx.x >> 3;
-    if (tile >= n_tiles || x >= nl) return;
+    tile0 = (blockIdx.x >> 3) * SPT;
+    if (tile0 >= n_tiles || x >= nl) return;
     second = x + 8 < nl;
     lv[0] = l0 + x;
     lv[1] = second ? l0 + x + 8 : l0 + x;
   }
   const uint32_t cx = threadIdx.x & 1;
-  // both lanes of a pair share the sample, so they leave together
-  const SampleRef r = sample_ref(tiles, plan, tile, n_direct, direct_block, threadIdx.x >> 1);
-  if (!r.valid) return;
-  const float x = coords[3 * r.gi + 0], y = coords[3 * r.gi + 1], z = coords[3 * r.gi + 2];
-  const TT* tab0 = table + (meta ? meta[r.block].param_off : 0);
-  WT wx[LPW], wy[LPW][2], wz[LPW][2];
-  TT v[LPW][4][F];
+  // both lanes of a pair share the samples, so they leave together
+  SampleRef r[SPT];
+  bool any = false;
 #pragma unroll
-  for (int j = 0; j < LPW; ++j) {  // loads first, all in flight together
-    const int l = lv[j];
-    int ix, iy, iz;
-    float tx, ty, tz;
-    const int R = ld.R[l];
-    grid_pos(x, ld.scale[l], R, ix, tx);
-    grid_pos(y, ld.scale[l], R, iy, ty);
-    grid_pos(z, ld.scale[l], R, iz, tz);
-    const TT* tab = tab0 + (int64_t)ld.off[l] * F;
-    const int dense = ld.dense[l];
-    wx[j] = cx ? (WT)tx : (WT)1 - (WT)tx;
-    wy[j][0] = (WT)1 - (WT)ty;
-    wy[j][1] = (WT)ty;
-    wz[j][0] = (WT)1 - (WT)tz;
-    wz[j][1] = (WT)tz;
-    // the four indices first, branch-free (both forms, then a select), so
-    // that the four loads issue back to back from one basic block
-    uint32_t e[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t cy = k & 1, cz = k >> 1;
-      const uint32_t gx = ix + cx, gy = iy + cy, gz = iz + cz;
-      const uint32_t ed = gx + __umul24((uint32_t)R, gy + __umul24((uint32_t)R, gz));
-      const uint32_t eh = (gx ^ (gy * 2654435761u) ^ (gz * 805459861u)) & ld.T_mask;
-      e[k] = dense ? ed : eh;
+  for (int t = 0; t < SPT; ++t) {
+    if (tile0 + t < n_tiles) {
+      r[t] = sample_ref(tiles, plan, tile0 + t, n_direct, direct_block, threadIdx.x >> 1);
+    } else {
+      r[t] = r[0];
+      r[t].valid = false;
     }
+    any |= r[t].valid;
+  }
+  if (!any) return;
+  WT wx[SPT][LPW], wy[SPT][LPW][2], wz[SPT][LPW][2];
+  TT v[SPT][LPW][4][F];
+  // every sample's coordinates before any gather (a load issued after the
+  // gathers would make the wait for it wait for them too)
+  float px[SPT], py[SPT], pz[SPT];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int f = 0; f < F; ++f) v[j][k][f] = tab[(int64_t)e[k] * F + f];
+  for (int t = 0; t < SPT; ++t) {
+    const int64_t gi = r[t].valid ? r[t].gi : r[0].gi;
+    px[t] = coords[3 * gi + 0];
+    py[t] = coords[3 * gi + 1];
+    pz[t] = coords[3 * gi + 2];
   }
 #pragma unroll
-  for (int j = 0; j < LPW; ++j) {
-    WT acc[F];
+  for (int t = 0; t < SPT; ++t) {
+    const float x = r[t].valid ? px[t] : 0.5f, y = r[t].valid ? py[t] : 0.5f, z = r[t].valid ? pz[t] : 0.5f;
+    const TT* tab0 = table + (meta ? meta[r[t].block].param_off : 0);
 #pragma unroll
-    for (int f = 0; f < F; ++f) acc[f] = 0;
+    for (int j = 0; j < LPW; ++j) {  // loads first, all in flight together
+      const int l = lv[j];
+      int ix, iy, iz;
+      float tx, ty, tz;
+      const int R = ld.R[l];
+      grid_pos(x, ld.scale[l], R, ix, tx);
+      grid_pos(y, ld.scale[l], R, iy, ty);
+      grid_pos(z, ld.scale[l], R, iz, tz);
+      const TT* tab = tab0 + (int64_t)ld.off[l] * F;
+      const int dense = ld.dense[l];
+      wx[t][j] = cx ? (WT)tx : (WT)1 - (WT)tx;
+      wy[t][j][0] = (WT)1 - (WT)ty;
+      wy[t][j][1] = (WT)ty;
+      wz[t][j][0] = (WT)1 - (WT)tz;
+      wz[t][j][1] = (WT)tz;
+      // the four indices first, branch-free (both forms, then a select), so
+      // that the four loads issue back to back from one basic block
+      uint32_t e[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const WT w = wx[j] * wy[j][k & 1] * wz[j][k >> 1];
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t cy = k & 1, cz = k >> 1;
+        const uint32_t gx = ix + cx, gy = iy + cy, gz = iz + cz;
+        const uint32_t ed = gx + __umul24((uint32_t)R, gy + __umul24((uint32_t)R, gz));
+        const uint32_t eh = (gx ^ (gy * 2654435761u) ^ (gz * 805459861u)) & ld.T_mask;
+        e[k] = dense ? ed : eh;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int f = 0; f < F; ++f) v[t][j][k][f] = tab[(int64_t)e[k] * F + f];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < SPT; ++t)
+#pragma unroll
+    for (int j = 0; j < LPW; ++j) {
+      WT acc[F];
+#pragma unroll
+      for (int f = 0; f < F; ++f) acc[f] = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const WT w = wx[t][j] * wy[t][j][k & 1] * wz[t][j][k >> 1];
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          if constexpr (sizeof(WT) == 8)
+            acc[f] += w * to_d(v[t][j][k][f]);
+          else
+            acc[f] += w * to_f(v[t][j][k][f]);
+        }
+      }
 #pragma unroll
       for (int f = 0; f < F; ++f) {
-        if constexpr (sizeof(WT) == 8)
-          acc[f] += w * to_d(v[j][k][f]);
-        else
-          acc[f] += w * to_f(v[j][k][f]);
+        const WT o = __shfl_xor(acc[f], 1, 64);
+        acc[f] = cx ? o + acc[f] : acc[f] + o;  // (cx = 0 sum) + (cx = 1 sum) on both lanes
+      }
+      if (cx == 0 && r[t].valid && (j == 0 || second)) {
+        OT* o = out + r[t].gi * ss + (int64_t)lv[j] * ls;
+#pragma unroll
+        for (int f = 0; f < F; ++f) o[f] = (OT)acc[f];
       }
     }
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      const WT o = __shfl_xor(acc[f], 1, 64);
-      acc[f] = cx ? o + acc[f] : acc[f] + o;  // (cx = 0 sum) + (cx = 1 sum) on both lanes
-    }
-    if (cx == 0 && (j == 0 || second)) {
-      OT* o = out + r.gi * ss + (int64_t)lv[j] * ls;
-#pragma unroll
-      for (int f = 0; f < F; ++f) o[f] = (OT)acc[f];
-    }
-  }
 }
 
 template <typename TT, typename WT, typename OT>
@@ -241,20 +273,22 @@ static hipError_t enc_dispatch(const LevelDesc& ld, const BlockMeta* meta, const
   // two levels per workgroup where the XCD-aware mapping gives an XCD two
   // levels (9 to 16 levels in the launch)
   const bool two = kEncodeLevelsPerWg == 2 && xcd_map && nl > 8 && nl <= 16;
-  const int64_t grid = two ? 8 * (int64_t)n_tiles : (int64_t)level_major_grid(nl, n_tiles, xcd_map);
+  constexpr int SPT = kEncodeTilesPerWg;
+  const int64_t grid =
+      two ? 8 * (((int64_t)n_tiles + SPT - 1) / SPT) : (int64_t)level_major_grid(nl, n_tiles, xcd_map);
   if (grid <= 0) return hipSuccess;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
   const TT* t = (const TT*)table;
   OT* o = (OT*)out;
-#define DVNR_ENC_LAUNCH(FF, LL)                                                                                  \
-  hipLaunchKernelGGL((k_encode<TT, WT, OT, FF, LL>), dim3((unsigned)grid), dim3(2 * kTile), 0, s, ld, meta, tiles, \
-                     n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl)
-#define DVNR_ENC_CASE(FF)       \
-  case FF:                      \
-    if (two)                    \
-      DVNR_ENC_LAUNCH(FF, 2);   \
-    else                        \
-      DVNR_ENC_LAUNCH(FF, 1);   \
+#define DVNR_ENC_LAUNCH(FF, LL, SS)                                                                          \
+  hipLaunchKernelGGL((k_encode<TT, WT, OT, FF, LL, SS>), dim3((unsigned)grid), dim3(2 * kTile), 0, s, ld, meta, \
+                     tiles, n_tiles, n_direct, direct_block, plan, coords, t, o, ss, ls, xcd_map, l0, nl)
+#define DVNR_ENC_CASE(FF)          \
+  case FF:                         \
+    if (two)                       \
+      DVNR_ENC_LAUNCH(FF, 2, SPT); \
+    else                           \
+      DVNR_ENC_LAUNCH(FF, 1, 1);   \
     break;
   switch (ld.F) {
     DVNR_ENC_CASE(1)

@@ -223,7 +223,12 @@ __global__ __launch_bounds__(256) void k_part_bucket(LevelDesc ld, PartDesc pd, 
 // 15 % slower on the 64-block workload).  Waves per SIMD to plan registers
 // for: two workgroups where the LDS allows two, one otherwise (and for F = 8,
 // whose records would not fit 64 registers without spilling).
-constexpr int part_accum_waves(int F, int SF, int NT) { return (SF <= 8192 && F <= 4 ? 2 : 1) * NT / 256; }
+constexpr int part_accum_waves(int F, int SF, int NT) {
+  // workgroups per CU: the LDS (160 KB) holds 160 KB / (8 SF), the CU 32 waves
+  const int by_lds = 163840 / (8 * SF), by_waves = 2048 / NT;
+  const int wgs = F > 4 ? 1 : (by_lds < by_waves ? by_lds : by_waves);
+  return (wgs < 1 ? 1 : wgs) * NT / 256;
+}
 
 template <int F, int SF, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(part_accum_waves(F, SF, NT)))) void k_part_accum(LevelDesc ld, PartDesc pd, const BlockMeta* __restrict__ meta,
