@@ -317,20 +317,32 @@ __global__ __launch_bounds__(256) void k_scatter_priv(LevelDesc ld, int l0, int 
     const int cn = min(kPrivRecs, s1 - c0);
     for (int i = tid; i <= nc; i += 256) cstart[i] = 0;
     __syncthreads();
-    // ---- 2a. cell of each sample and its rank within the cell
+    // ---- 2a. cell of each sample and its rank within the cell.  All of the
+    // lane's coordinates and dL/dy are loaded first (indices clamped into the
+    // chunk), so that the loads are in flight together
     int mcell[PER], mrank[PER];
-    float mt[PER][3], md[PER][F];
+    float mt[PER][3], md[PER][F], mx[PER][3];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int64_t gi = base + c0 + min(tid + 256 * u, cn - 1);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) mx[u][a] = coords[3 * gi + a];
+#pragma unroll
+      for (int f = 0; f < F; ++f) md[u][f] = dfeat[(int64_t)l * ls + gi * F + f];
+    }
+    // cells of every sample (unconditionally, so that no load is sunk into
+    // a branch and waited for there), then the ranks
+    int mi[PER][3];
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) grid_pos(mx[u][a], sc, R, mi[u][a], mt[u][a]);
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int j = tid + 256 * u;
       mcell[u] = -1;
       if (j < cn) {
-        const int64_t gi = base + c0 + j;
-        int i0[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) grid_pos(coords[3 * gi + a], sc, R, i0[a], mt[u][a]);
-#pragma unroll
-        for (int f = 0; f < F; ++f) md[u][f] = dfeat[(int64_t)l * ls + gi * F + f];
+        const int* i0 = mi[u];
         const int lx = i0[0] - bx0, ly = i0[1] - by0, lz = i0[2] - bz0;
         if ((unsigned)lx < (unsigned)cx_n && (unsigned)ly < (unsigned)cy_n && (unsigned)lz < (unsigned)cz_n) {
           mcell[u] = lx + cx_n * (ly + cy_n * lz);
