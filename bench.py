@@ -562,9 +562,10 @@ def _cpu_block_step(task):
 
 def cpu_baseline(cfg, blocks, vols, max_workers=16):
     """The float64 oracle, untuned, on one training step of the workload's first
-    blocks (each with its own apportioned sample count), one block per task over
-    a pool of single-threaded worker processes (at most 16: the machine's CPU share
-    of one GPU)."""
+    blocks (each with its own apportioned sample count; up to four per worker,
+    so the whole 64-block step with 16 workers: about 13 s of compute), one
+    block per task over a pool of single-threaded worker processes (at most
+    16: the machine's CPU share of one GPU)."""
     import multiprocessing as mp
     import shutil
     import tempfile
@@ -575,7 +576,7 @@ def cpu_baseline(cfg, blocks, vols, max_workers=16):
     nb = len(blocks)
     n = [cfg["batch"]] if nb == 1 else [int(v) for v in o.apportion([d[0] * d[1] * d[2] for d, _ in blocks],
                                                                        cfg["batch"])]
-    k = nb if nb <= 2 * workers else 2 * workers
+    k = nb if nb <= 4 * workers else 4 * workers
     enc, mlp = cfg["enc"], cfg["mlp"]
     e = (enc.n_levels, enc.n_features, enc.log2_table_size, enc.base_resolution, enc.per_level_scale,
          enc.finest_resolution)
