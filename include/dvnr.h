@@ -474,9 +474,10 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *  "scatter_part"    n   : destination-partitioned encoding backward of the
  *                          levels [n, n_levels) (-1, the default: for mixed
  *                          precision, the longest suffix of levels with at
- *                          least 2^15 entries that get at least one
- *                          contribution per table entry per step; none for
- *                          fp32; >= n_levels: none).  Each step sorts the levels'
+ *                          least 2^15 entries that, unless "part_adam" is
+ *                          off, get at least one contribution per table
+ *                          entry per step; none for fp32; >= n_levels:
+ *                          none).  Each step sorts the levels'
  *                          (sample, corner) contributions into per-slice
  *                          buckets (slices of "part_slice" / F entries) and sums
  *                          each bucket in LDS, instead of one global atomic per

@@ -239,8 +239,13 @@ def test_sorted_sampling_gradient_parity(precision, priv, classes, binned):
 #  first partitioned level expected: scatter_part = 0 asks for every level, and every level of this
 #  encoding has at least the 2^12 entries a partitioned table needs)
 FINE_CASES = [("fp32", 0, 1, 0, 1, -1, 0, 8192, 16), ("fp32", 1, 1, 0, 1, -1, 0, 8192, 16),
-              ("fp32", 0, 1, 1, 1, -1, 0, 8192, 16), ("mixed", 0, 1, 0, 1, -1, 0, 8192, 16),
-              ("mixed", 0, 2, 0, 1, -1, 0, 8192, 16), ("mixed", 1, 1, 1, 1, -1, 0, 8192, 16),
+              ("fp32", 0, 1, 1, 1, -1, 0, 8192, 16),
+              # mixed, automatic: with Adam in the slice pass every level with at
+              # least 2^15 entries is partitioned (levels 4..15), however sparse
+              ("mixed", 0, 1, 0, 1, -1, 0, 8192, 4),
+              # mixed with every level privatized (the in-kernel direct atomics of
+              # the fine levels), two MLP waves per SIMD, LDS classes
+              ("mixed", 0, 2, 0, 1, 16, 0, 8192, 16), ("mixed", 1, 1, 1, 1, 16, 0, 8192, 16),
               # destination-partitioned levels: fine only, every eligible one (ordered and not),
               # tiny buckets (most records overflow into direct atomics), other slice sizes
               ("fp32", 0, 1, 0, 1, 9, 0, 8192, 9), ("fp32", 0, 1, 0, 1, 0, 0, 8192, 0),
