@@ -328,32 +328,47 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(part_accum_w
     return x;
   };
   // The Adam operands are accessed through buffer resources that span the
-  // slice exactly: the hardware range check turns loads past the slice's end
+  // slice's body exactly: the hardware range check turns loads past its end
   // into zeros and drops stores there, so the accesses need neither clamping
-  // nor branches, and all of them share one 32-bit offset register.
-  const uint32_t sbytes = (uint32_t)nv * VW * 4;
+  // nor branches, and all of them share one 32-bit offset register.  With
+  // even F the body is read and written in 16-byte accesses from the first
+  // 16-byte aligned element; an F = 2 slice can start 8 bytes past such an
+  // element, and then its first and last entry (the head and the tail pair)
+  // are updated apart by one lane each.
+  constexpr int AW = F % 2 == 0 ? 4 : 1;                    // elements per Adam access
+  constexpr int APT = SF / NT / AW, AKB = APT < 4 ? APT : 4;  // body accesses per lane, per batch
+  static_assert(APT >= 1 && APT * NT * AW == SF, "a slice's body is APT accesses per lane");
+  typedef float av __attribute__((ext_vector_type(AW)));
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const int head = (AW == 4 && (el0 & 3)) ? 2 : 0;  // el0 is even for even F
+  const int nb = (nf - head) / AW;                  // body accesses
+  const int tail = nf - head - nb * AW;             // 0, or 2 (F = 2)
+  const int64_t eb = el0 + head;                    // first body element
+  const uint32_t bbytes = (uint32_t)nb * AW * 4;
   auto rsrc = [&](const void* base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufferDword3);
   };
-  auto bld = [&](__amdgpu_buffer_rsrc_t r, uint32_t a) -> fv {
-    if constexpr (VW == 2) {
-      const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, a * 8u, 0, 0);
-      return fv{__uint_as_float(x[0]), __uint_as_float(x[1])};
+  auto bld = [&](__amdgpu_buffer_rsrc_t r, uint32_t a) -> av {
+    if constexpr (AW == 4) {
+      const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, a * 16u, 0, 0);
+      return av{__uint_as_float(x[0]), __uint_as_float(x[1]), __uint_as_float(x[2]), __uint_as_float(x[3])};
     } else {
-      return fv(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, a * 4u, 0, 0)));
+      return av(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, a * 4u, 0, 0)));
     }
   };
-  auto bst = [&](__amdgpu_buffer_rsrc_t r, uint32_t a, fv x) {
-    if constexpr (VW == 2)
-      __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(x[0]), __float_as_uint(x[1])}, r, a * 8u, 0, 0);
+  auto bst = [&](__amdgpu_buffer_rsrc_t r, uint32_t a, av x) {
+    if constexpr (AW == 4)
+      __builtin_amdgcn_raw_buffer_store_b128(
+          u32x4{__float_as_uint(x[0]), __float_as_uint(x[1]), __float_as_uint(x[2]), __float_as_uint(x[3])}, r,
+          a * 16u, 0, 0);
     else
       __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x[0]), r, a * 4u, 0, 0);
   };
-  fv th[KB], mm[KB], vv[KB];  // Adam operands of the batch in flight
+  av th[AKB], mm[AKB], vv[AKB];  // Adam operands of the batch in flight
   auto load_adam = [&](int k0) {
-    const auto rp = rsrc(adam.params + el0, sbytes), rm = rsrc(adam.m + el0, sbytes), rv = rsrc(adam.v + el0, sbytes);
+    const auto rp = rsrc(adam.params + eb, bbytes), rm = rsrc(adam.m + eb, bbytes), rv = rsrc(adam.v + eb, bbytes);
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
+    for (int k = 0; k < AKB; ++k) {
       const uint32_t a = (uint32_t)(tid + NT * (k0 + k));
       th[k] = bld(rp, a);
       mm[k] = bld(rm, a);
@@ -438,56 +453,94 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(part_accum_w
   // working copy is written too.
   load_adam(0);
   const float bc2 = hbc[1], lrbc1 = hbc[2] * hbc[0];
+  // Adam of one element from its fixed-point sum, its gradient-table value g0
+  // (nonzero only after an overflow) and its operands
+  auto adam1 = [&](int e, float g0, float th0, float m0, float v0) -> float3 {
+    const float gg = g0 + ldexpf((float)(long long)acc[e], -K) + adam.wd * th0;
+    const float m1 = adam.b1 * m0 + adam.omb1 * gg;
+    const float v1 = adam.b2 * v0 + adam.omb2 * gg * gg;
+    // hardware square root and reciprocal (about 1 ulp each): the step
+    // lr m_hat / (sqrt(v_hat) + eps) is within a few float roundings
+    const float t1 = th0 - lrbc1 * m1 * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(v1 * bc2) + adam.eps);
+    return make_float3(t1, m1, v1);
+  };
+  auto half_bits = [](float x) -> uint32_t {
+    const __half hv = __float2half_rn(x);
+    return (uint32_t)(*reinterpret_cast<const uint16_t*>(&hv));
+  };
   auto update = [&](auto ovf_tag, auto w16_tag) {
     constexpr bool OVF = decltype(ovf_tag)::value, W16 = decltype(w16_tag)::value;
-    const auto rp = rsrc(adam.params + el0, sbytes), rm = rsrc(adam.m + el0, sbytes), rv = rsrc(adam.v + el0, sbytes);
-    const auto rg = rsrc(g, sbytes), rw = rsrc(adam.work16 + el0, sbytes / 2);
-    for (int k0 = 0; k0 < PT; k0 += KB) {
-      fv gv[KB];
+    const auto rp = rsrc(adam.params + eb, bbytes), rm = rsrc(adam.m + eb, bbytes), rv = rsrc(adam.v + eb, bbytes);
+    const auto rg = rsrc(g + head, bbytes), rw = rsrc(adam.work16 + eb, bbytes / 2);
+    for (int k0 = 0; k0 < APT; k0 += AKB) {
+      av gv[AKB];
 #pragma unroll
-      for (int k = 0; k < KB; ++k) {
+      for (int k = 0; k < AKB; ++k) {
         if constexpr (OVF)
           gv[k] = bld(rg, (uint32_t)(tid + NT * (k0 + k)));
         else
-          gv[k] = fv(0.0f);
+          gv[k] = av(0.0f);
       }
-      fv th0[KB], mm0[KB], vv0[KB];
+      av th0[AKB], mm0[AKB], vv0[AKB];
 #pragma unroll
-      for (int k = 0; k < KB; ++k) {
+      for (int k = 0; k < AKB; ++k) {
         th0[k] = th[k];
         mm0[k] = mm[k];
         vv0[k] = vv[k];
       }
-      if (k0 + KB < PT) load_adam(k0 + KB);
+      if (k0 + AKB < APT) load_adam(k0 + AKB);
 #pragma unroll
-      for (int k = 0; k < KB; ++k) {
+      for (int k = 0; k < AKB; ++k) {
         const uint32_t a = (uint32_t)(tid + NT * (k0 + k));
-        fv t1, m1, v1;
+        // lanes past the body's end compute on zero operands (their stores are
+        // dropped) and read the accumulators at an index clamped into the slice
+        const int e0a = head + (int)min(a, (uint32_t)max(nb - 1, 0)) * AW;
+        av t1, m1, v1;
 #pragma unroll
-        for (int c = 0; c < VW; ++c) {
-          const float gg = gv[k][c] + ldexpf((float)(long long)acc[a * VW + c], -K) + adam.wd * th0[k][c];
-          m1[c] = adam.b1 * mm0[k][c] + adam.omb1 * gg;
-          v1[c] = adam.b2 * vv0[k][c] + adam.omb2 * gg * gg;
-          // hardware square root and reciprocal (about 1 ulp each): the step
-          // lr m_hat / (sqrt(v_hat) + eps) is within a few float roundings
-          t1[c] = th0[k][c] - lrbc1 * m1[c] * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(v1[c] * bc2) + adam.eps);
+        for (int c = 0; c < AW; ++c) {
+          const float3 r = adam1(e0a + c, gv[k][c], th0[k][c], mm0[k][c], vv0[k][c]);
+          t1[c] = r.x;
+          m1[c] = r.y;
+          v1[c] = r.z;
         }
         bst(rp, a, t1);
         bst(rm, a, m1);
         bst(rv, a, v1);
         if constexpr (W16) {
-          uint32_t h = 0;
-#pragma unroll
-          for (int c = 0; c < VW; ++c) {
-            const __half hv = __float2half_rn(t1[c]);
-            h |= (uint32_t)(*reinterpret_cast<const uint16_t*>(&hv)) << (16 * c);
-          }
-          if constexpr (VW == 2)
-            __builtin_amdgcn_raw_buffer_store_b32(h, rw, a * 4u, 0, 0);
+          if constexpr (AW == 4)
+            __builtin_amdgcn_raw_buffer_store_b64(
+                u32x2{half_bits(t1[0]) | half_bits(t1[1]) << 16, half_bits(t1[2]) | half_bits(t1[3]) << 16}, rw,
+                a * 8u, 0, 0);
           else
-            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)h, rw, a * 2u, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)half_bits(t1[0]), rw, a * 2u, 0, 0);
         }
-        if constexpr (OVF) bst(rg, a, fv(0.0f));
+        if constexpr (OVF) bst(rg, a, av(0.0f));
+      }
+    }
+    // the head pair of an F = 2 slice that starts 8 bytes past a 16-byte
+    // boundary (lane 0) and the tail pair of one whose body leaves two
+    // elements (lane 1), in 8-byte accesses
+    if (AW == 4 && tid < 2) {
+      const int e = tid == 0 ? 0 : nf - 2;
+      if (tid == 0 ? head != 0 : tail != 0) {
+        float2 tp, mp, vp, gp = make_float2(0.0f, 0.0f);
+        __builtin_memcpy(&tp, adam.params + el0 + e, 8);
+        __builtin_memcpy(&mp, adam.m + el0 + e, 8);
+        __builtin_memcpy(&vp, adam.v + el0 + e, 8);
+        if constexpr (OVF) __builtin_memcpy(&gp, g + e, 8);
+        const float3 r0 = adam1(e, gp.x, tp.x, mp.x, vp.x), r1 = adam1(e + 1, gp.y, tp.y, mp.y, vp.y);
+        const float2 t1 = make_float2(r0.x, r1.x), m1 = make_float2(r0.y, r1.y), v1 = make_float2(r0.z, r1.z);
+        __builtin_memcpy(adam.params + el0 + e, &t1, 8);
+        __builtin_memcpy(adam.m + el0 + e, &m1, 8);
+        __builtin_memcpy(adam.v + el0 + e, &v1, 8);
+        if constexpr (W16) {
+          const uint32_t hh = half_bits(t1.x) | half_bits(t1.y) << 16;
+          __builtin_memcpy(adam.work16 + el0 + e, &hh, 4);
+        }
+        if constexpr (OVF) {
+          const float2 z = make_float2(0.0f, 0.0f);
+          __builtin_memcpy(g + e, &z, 8);
+        }
       }
     }
   };
