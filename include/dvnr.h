@@ -467,8 +467,11 @@ dvnr_status dvnr_set_loss(dvnr_t* h, int32_t loss, double boundary_frac, double 
  *  "scatter_strided" 0/1 : direct backward over ordered samples takes each
  *                          tile's samples strided across the block (default 1)
  *  "decode_fused"    0/1 : decode with the fused brick kernel (default 1)
- *  "mlp_waves"       1/2 : register budget of the mixed-precision MLP training
- *                          kernel, in waves per SIMD (default 1)
+ *  "mlp_waves"       1/2 : register budget of the 4-wave mixed-precision MLP
+ *                          training kernel, in waves per SIMD (default 1)
+ *  "mlp_wg_waves"    4/8 : waves per workgroup of the mixed-precision MLP
+ *                          training kernel (8: two waves per SIMD, used where
+ *                          its LDS fits, else 4; default 8)
  *  "mlp_grid"        n   : workgroups of the persistent MLP training kernel
  *                          (1 .. 512, default 256; also set by dvnr_autotune)
  *  "scatter_part"    n   : destination-partitioned encoding backward of the

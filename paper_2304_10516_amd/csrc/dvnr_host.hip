@@ -74,6 +74,7 @@ struct dvnr {
   int xcd_map = 1;
   int mlp_cap = kMlpGrid;  // workgroups of the persistent MLP kernel (autotuned)
   int mlp_waves = 1;       // waves per SIMD the mixed-precision MLP kernel is compiled for (1 or 2)
+  int mlp_wg_waves = 8;    // waves per workgroup of the mixed-precision MLP kernel (4 or 8)
   int decode_fused = 1;    // decode with the fused brick kernel (else encode + MLP over chunks)
   int apply_update = 1;
   // sliding-window model cache: capacity snapshots of the inference parameters
@@ -895,7 +896,7 @@ static dvnr_status enqueue_step(dvnr_t* h, int gen, hipStream_t s, int set = 0, 
                            : (const void*)((const float*)h->buf.params + h->n_table);
   HIPCHK(launch_mlp_train(h->prec, h->md, h->ld, h->d_meta(), h->d_plan(), h->d_tiles(), h->n_tiles, h->d_feat(),
                           h->d_target(set), wsrc, h->d_dfeat(), h->max_batch, h->d_slots(), h->slot_stride, h->mlp_grid,
-                          h->loss_l1, h->mlp_waves, s));
+                          h->loss_l1, h->mlp_waves, h->mlp_wg_waves, s));
   {
     dvnr_status st = fork_ahead(3);
     if (st) return st;
@@ -1815,6 +1816,9 @@ dvnr_status dvnr_set_option(dvnr_t* h, const char* name, int64_t value) {
     h->use_graph = value ? 1 : 0;
   } else if (n == "mlp_waves") {
     h->mlp_waves = value >= 2 ? 2 : 1;
+  } else if (n == "mlp_wg_waves") {
+    if (value != 4 && value != 8) return fail(DVNR_E_INVALID, "mlp_wg_waves: 4 or 8");
+    h->mlp_wg_waves = (int)value;
   } else if (n == "mlp_grid") {
     h->mlp_cap = (int)std::max<int64_t>(1, std::min<int64_t>(value, 2 * kMlpGrid));
     h->plan_total = -1;

@@ -9,6 +9,7 @@ namespace dvnrk {
 
 constexpr int kMaxLevels = 16;
 constexpr int kTile = 256;        // samples per tile (work item of the training kernels)
+constexpr int kLdsBytes = 163840;  // LDS of one compute unit (the most one workgroup can take)
 constexpr int kMlpGrid = 256;     // workgroups of the persistent MLP kernel (one per CU)
 constexpr int kLossRing = 1024;   // steps of per-block loss history kept on the device
 constexpr int kMaxBins = 512;     // spatial bins per block (B^3, B <= 8) of the ordered sampler
@@ -209,11 +210,15 @@ hipError_t launch_scatter_priv(const LevelDesc& ld, int l0, int l1, int B, int n
                                hipStream_t s);
 
 // MLP training pass (forward, L2 loss, backward) on MFMA; writes dfeat
-// (level-major f32) and per-wave dW/loss partials into slots.
+// (level-major f32) and per-wave dW/loss partials into slots.  min_waves:
+// waves per SIMD the 4-wave kernel's registers allow (1 or 2); wg_waves: 8
+// runs the mixed-precision kernel with 8 waves per workgroup where its LDS
+// fits, else 4.
 hipError_t launch_mlp_train(Prec p, const MlpDesc& md, const LevelDesc& ld, const BlockMeta* meta,
                             const BlockPlan* plan, const Tile* tiles, int n_tiles, const void* feat,
                             const float* target, const void* weights_src, float* dfeat, int64_t plane,
-                            float* slots, int64_t slot_stride, int grid, int loss_l1, int min_waves, hipStream_t s);
+                            float* slots, int64_t slot_stride, int grid, int loss_l1, int min_waves, int wg_waves,
+                            hipStream_t s);
 // MLP inference: out[i] = INR output de-normalized with the block range.
 hipError_t launch_mlp_infer(Prec p, const MlpDesc& md, const LevelDesc& ld, const BlockMeta* meta,
                             const BlockRange* range, const BlockPlan* plan, const Tile* tiles, int n_tiles,

@@ -136,16 +136,19 @@ template <typename T> __device__ __forceinline__ float ldf(const T* p) { return 
 
 // ---------------------------------------------------------------------------
 // Training kernel.  Persistent: workgroup w processes tiles
-// [w*n_tiles/G, (w+1)*n_tiles/G).  Per pass every wave stages DWS samples;
-// after a barrier the 4 waves split the weight-gradient output tiles and
-// contract each over all 4*DWS staged samples.  At every block change the
+// [w*n_tiles/G, (w+1)*n_tiles/G) with NW waves (4 or 8), each taking
+// kTile/NW samples of a tile.  Per pass every wave stages DWS samples; after a
+// barrier the NW waves split the weight-gradient output tiles and contract
+// each over all NW*DWS staged samples.  With 8 waves the workgroup fills two
+// waves per SIMD, whose latencies overlap, and the staging rows lose their
+// padding so that it fits the LDS beside the weight operands.  At every block change the
 // workgroup writes its partial dW and loss of the finished block into slot
 // (w + block) and loads the new block's weights.
 // ---------------------------------------------------------------------------
 // MINW: waves per SIMD the register allocation must allow (2 trades spills
 // for latency hiding; selected at run time, measured by the autotuner).
-template <class TR, int W, int NH, typename FT, typename WSRC, int MINW>
-__global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, const BlockMeta* __restrict__ meta,
+template <class TR, int W, int NH, typename FT, typename WSRC, int MINW, int NW>
+__global__ __launch_bounds__(64 * NW, MINW) void k_mlp_train(MlpDesc md, int F, const BlockMeta* __restrict__ meta,
                                                    const BlockPlan* __restrict__ plan,
                                                    const Tile* __restrict__ tiles, int n_tiles,
                                                    const FT* __restrict__ feat, const float* __restrict__ target,
@@ -156,12 +159,15 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
   using op_t = typename TR::op_t;
   using st_t = typename TR::st_t;
   constexpr int T_ALL = 2 * S::MT + (NH - 1) * S::MT * S::MT;  // 16x16 output tiles of all dW
-  constexpr int U = (T_ALL + 3) / 4;                            // tiles per wave
+  constexpr int U = (T_ALL + NW - 1) / NW;                      // tiles per wave
+  static_assert(NW == 4 || NW == 8, "4 or 8 waves per workgroup");
+  constexpr int RS = NW == 4 ? S::RS : S::DWS;  // staging row stride (elements)
+  constexpr int STAGE = S::ROWS * RS;           // staging elements of one wave
   extern __shared__ __align__(16) unsigned char smem[];
   op_t* A = reinterpret_cast<op_t*>(smem);
   float* wout = reinterpret_cast<float*>(smem + sizeof(op_t) * S::N_SLOTS * 64);
-  float* red = wout + 64;  // 4 waves x (64 + 1) floats: output-layer gradient and loss
-  st_t* stage_all = reinterpret_cast<st_t*>(smem + sizeof(op_t) * S::N_SLOTS * 64 + sizeof(float) * (64 + 4 * 65 + 4));
+  float* red = wout + 64;  // NW waves x (64 + 1) floats: output-layer gradient and loss
+  st_t* stage_all = reinterpret_cast<st_t*>(smem + sizeof(op_t) * S::N_SLOTS * 64 + sizeof(float) * (64 + NW * 65 + 4));
 
   const int G = gridDim.x, w = blockIdx.x;
   const int t0 = (int)(((int64_t)w * n_tiles) / G), t1 = (int)(((int64_t)(w + 1) * n_tiles) / G);
@@ -169,9 +175,9 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int g = lane / 16, c = lane % 16;
   // staging rows of one wave: SZ[k] at k*W rows; SI[0] (32 rows) at NH*W; SI[k>=1] at NH*W + 32 + (k-1)*W
-  auto SZ = [&](int ws, int k) { return stage_all + ws * S::STAGE_ELEMS + (k * W) * S::RS; };
+  auto SZ = [&](int ws, int k) { return stage_all + ws * STAGE + (k * W) * RS; };
   auto SI = [&](int ws, int k) {
-    return stage_all + ws * S::STAGE_ELEMS + (k == 0 ? NH * W : NH * W + 32 + (k - 1) * W) * S::RS;
+    return stage_all + ws * STAGE + (k == 0 ? NH * W : NH * W + 32 + (k - 1) * W) * RS;
   };
 
   f32x4 dwt[U];
@@ -204,7 +210,7 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
     const int in_dim = md.in_dim;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int t = wave + 4 * u;
+      const int t = wave + NW * u;
       if (t < T_ALL) {
         int k, m, n;
         tile_kmn(t, k, m, n);
@@ -234,9 +240,17 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
     __syncthreads();
     if (threadIdx.x < W) {
       const int e = threadIdx.x;
-      out[md.off[NH] + e] = red[e] + red[65 + e] + red[130 + e] + red[195 + e];
+      float v = 0.0f;
+#pragma unroll
+      for (int ws = 0; ws < NW; ++ws) v += red[65 * ws + e];
+      out[md.off[NH] + e] = v;
     }
-    if (threadIdx.x == 0) out[md.n_mlp] = red[64] + red[65 + 64] + red[130 + 64] + red[195 + 64];
+    if (threadIdx.x == 0) {
+      float v = 0.0f;
+#pragma unroll
+      for (int ws = 0; ws < NW; ++ws) v += red[65 * ws + 64];
+      out[md.n_mlp] = v;
+    }
     __syncthreads();
   };
 
@@ -280,9 +294,11 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
       mySZ[k] = SZ(wave, k);
       mySI[k] = SI(wave, k);
     }
-    // this wave's 64 samples of the tile: 4 groups of 16, passes of DWS samples;
-    // the features and target of group k+1 are loaded while group k computes
-    constexpr int NG = 4;
+    // this wave's kTile/NW samples of the tile: groups of 16, passes of DWS
+    // samples; the features and target of group k+1 are loaded while group k
+    // computes
+    constexpr int SW = kTile / NW, NG = SW / 16;
+    static_assert(NG % S::GP == 0, "a wave's groups fill whole passes");
     // raw features and target of a group, prefetched one group ahead (at the
     // last group the first one is reloaded, unused); loads are unconditional (element 0
     // stands in for a missing sample or feature) and values are converted and
@@ -290,7 +306,7 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
     FT xr[8];
     float yr;
     auto load_group = [&](int k, FT (&x)[8], float& y) {
-      const int sl = wave * 64 + k * 16 + c;
+      const int sl = wave * SW + k * 16 + c;
       const bool ok = sl < tl.count;
       const int gF = ok ? (int)(base + sl) * F : 0;
 #pragma unroll
@@ -305,7 +321,7 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
       float yn;
       load_group(kg + 1 < NG ? kg + 1 : 0, xn, yn);
       {
-        const int sl = wave * 64 + kg * 16 + c;  // sample within the tile
+        const int sl = wave * SW + kg * 16 + c;  // sample within the tile
         const bool valid = sl < tl.count;
         const int64_t gi = base + sl;
         const int scol = q * 16 + c;              // staging column
@@ -318,7 +334,7 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
             const int f = 8 * g + s * TR::VPL + j;
             const float x = (valid && fo[s * TR::VPL + j] >= 0) ? (float)xr[s * TR::VPL + j] : 0.0f;
             TR::put(xb[s], j, x);
-            mySI[0][f * S::RS + scol] = (st_t)x;
+            mySI[0][f * RS + scol] = (st_t)x;
           }
         // ---- forward
         f32x4 h[NH][S::MT];
@@ -375,8 +391,8 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const int n = 16 * m + 4 * g + i;
-              mySZ[k][n * S::RS + scol] = (st_t)dz[m][i];
-              if (k >= 1) mySI[k][n * S::RS + scol] = (st_t)h[k - 1][m][i];
+              mySZ[k][n * RS + scol] = (st_t)dz[m][i];
+              if (k >= 1) mySI[k][n * RS + scol] = (st_t)h[k - 1][m][i];
             }
           if (k >= 1) {
             op_t db[S::KS_H];
@@ -421,14 +437,14 @@ __global__ __launch_bounds__(256, MINW) void k_mlp_train(MlpDesc md, int F, cons
       // ---- weight gradients: this wave's output tiles over the 4 waves' staged samples
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int t = wave + 4 * u;
+        const int t = wave + NW * u;
         if (t < T_ALL) {
           int k, m, n;
           tile_kmn(t, k, m, n);
 #pragma unroll 1
-          for (int ws = 0; ws < 4; ++ws) {
-            const st_t* za = SZ(ws, k) + (16 * m + c) * S::RS + g * TR::VPL;
-            const st_t* ib = SI(ws, k) + (16 * n + c) * S::RS + g * TR::VPL;
+          for (int ws = 0; ws < NW; ++ws) {
+            const st_t* za = SZ(ws, k) + (16 * m + c) * RS + g * TR::VPL;
+            const st_t* ib = SI(ws, k) + (16 * n + c) * RS + g * TR::VPL;
 #pragma unroll
             for (int ks = 0; ks < S::KS_DW; ++ks)
               dwt[u] = TR::mma(TR::ld(za + ks * TR::KN), TR::ld(ib + ks * TR::KN), dwt[u]);
@@ -531,11 +547,11 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpDesc md, int F, const Bloc
   }
 }
 
-template <class TR, int W, int NH>
+template <class TR, int W, int NH, int NW>
 static size_t train_smem() {
   using S = MlpShape<TR, W, NH>;
-  return sizeof(typename TR::op_t) * S::N_SLOTS * 64 + sizeof(float) * (64 + 4 * 65 + 4) +
-         sizeof(typename TR::st_t) * S::STAGE_ELEMS * 4;
+  return sizeof(typename TR::op_t) * S::N_SLOTS * 64 + sizeof(float) * (64 + NW * 65 + 4) +
+         sizeof(typename TR::st_t) * S::ROWS * (NW == 4 ? S::RS : S::DWS) * NW;
 }
 template <class TR, int W, int NH>
 static size_t infer_smem() {
@@ -543,17 +559,17 @@ static size_t infer_smem() {
   return sizeof(typename TR::op_t) * S::N_SLOTS * 64 + sizeof(float) * 64;
 }
 
-template <class TR, int W, int NH, typename FT, typename WSRC, int MINW = 1>
+template <class TR, int W, int NH, typename FT, typename WSRC, int MINW = 1, int NW = 4>
 static hipError_t run_train(const MlpDesc& md, int F, const BlockMeta* meta, const BlockPlan* plan, const Tile* tiles,
                             int n_tiles, const void* feat, const float* target, const void* wsrc, float* dfeat,
                             int64_t plane, float* slots, int64_t slot_stride, int grid, int64_t n_table, int l1,
                             hipStream_t s) {
-  const size_t sm = train_smem<TR, W, NH>();
-  auto kern = k_mlp_train<TR, W, NH, FT, WSRC, MINW>;
+  const size_t sm = train_smem<TR, W, NH, NW>();
+  auto kern = k_mlp_train<TR, W, NH, FT, WSRC, MINW, NW>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), sm, s, md, F, meta, plan, tiles, n_tiles, (const FT*)feat, target,
-                     (const WSRC*)wsrc, dfeat, plane, slots, slot_stride, n_table, l1);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), sm, s, md, F, meta, plan, tiles, n_tiles, (const FT*)feat,
+                     target, (const WSRC*)wsrc, dfeat, plane, slots, slot_stride, n_table, l1);
   return hipGetLastError();
 }
 
@@ -578,12 +594,17 @@ static hipError_t run_infer(const MlpDesc& md, int F, const BlockMeta* meta, con
 hipError_t launch_mlp_train(Prec p, const MlpDesc& md, const LevelDesc& ld, const BlockMeta* meta,
                             const BlockPlan* plan, const Tile* tiles, int n_tiles, const void* feat,
                             const float* target, const void* weights_src, float* dfeat, int64_t plane,
-                            float* slots, int64_t slot_stride, int grid, int loss_l1, int min_waves, hipStream_t s) {
+                            float* slots, int64_t slot_stride, int grid, int loss_l1, int min_waves, int wg_waves,
+                            hipStream_t s) {
   // weights_src points at the MLP weights of block 0 (element n_table_params);
   // the kernel adds each block's parameter offset.  Feature offsets are 32-bit.
   if ((int64_t)md.in_dim * plane >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
 #define X(WW, NN)                                                                                                   \
   if (md.width == WW && md.n_hidden == NN) {                                                                        \
+    if (p == Prec::MIXED && wg_waves == 8 && train_smem<TrBF16, WW, NN, 8>() <= (size_t)kLdsBytes)                  \
+      return run_train<TrBF16, WW, NN, __bf16, __bf16, 1, 8>(md, ld.F, meta, plan, tiles, n_tiles, feat, target,    \
+                                                              weights_src, dfeat, plane, slots, slot_stride, grid,  \
+                                                              (int64_t)0, loss_l1, s);                              \
     if (p == Prec::MIXED && min_waves >= 2)                                                                         \
       return run_train<TrBF16, WW, NN, __bf16, __bf16, 2>(md, ld.F, meta, plan, tiles, n_tiles, feat, target,       \
                                                            weights_src, dfeat, plane, slots, slot_stride, grid,     \

@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void k_part_bucket(LevelDesc ld, PartDesc pd, 
 // whose records would not fit 64 registers without spilling).
 constexpr int part_accum_waves(int F, int SF, int NT) {
   // workgroups per CU: the LDS (160 KB) holds 160 KB / (8 SF), the CU 32 waves
-  const int by_lds = 163840 / (8 * SF), by_waves = 2048 / NT;
+  const int by_lds = kLdsBytes / (8 * SF), by_waves = 2048 / NT;
   const int wgs = F > 4 ? 1 : (by_lds < by_waves ? by_lds : by_waves);
   return (wgs < 1 ? 1 : wgs) * NT / 256;
 }

@@ -43,6 +43,16 @@ def make(cfg, blocks, precision="fp32", max_batch=1 << 14, seed=0):
                 max_batch=max_batch, seed=seed)
 
 
+def set_waves(model, waves):
+    """MLP training kernel variant: 1 or 2 waves per SIMD of the 4-wave kernel,
+    or 8, the 8-wave workgroup (the default)."""
+    if waves == 8:
+        model.set_option("mlp_wg_waves", 8)
+    else:
+        model.set_option("mlp_wg_waves", 4)
+        model.set_option("mlp_waves", waves)
+
+
 def dev(x, dtype=torch.float32):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
 
@@ -174,11 +184,11 @@ def _setup_c1_block(precision, n=64, seed=0, blocks=None):
 
 
 @pytest.mark.parametrize("precision,grouped,waves", [("fp32", 0, 1), ("fp32", 1, 1), ("mixed", 1, 1),
-                                                     ("mixed", 1, 2)])
+                                                     ("mixed", 1, 2), ("mixed", 1, 8)])
 def test_one_step_gradient_parity_c1(precision, grouped, waves):
     say(f"one-step gradient c1 {precision} grouped={grouped} mlp_waves={waves}")
     vol, lay, p0, model = _setup_c1_block(precision)
-    model.set_option("mlp_waves", waves)
+    set_waves(model, waves)
     model.bind_volumes([dev(vol)])
     p = p0.astype(np.float64).copy()
     p[:lay.n_table_params] *= 1e3  # table values O(0.1) so that the encoding matters
@@ -199,6 +209,40 @@ def test_one_step_gradient_parity_c1(precision, grouped, waves):
     assert abs(loss.item() - L) <= 1e-5 * L
     assert normwise(gg[:nt], g[:nt]) <= 1e-5, "table gradient"
     assert normwise(gg[nt:], g[nt:]) <= 1e-5, "weight gradient"
+
+
+@pytest.mark.parametrize("nh,width", [(1, 16), (3, 32), (2, 64), (3, 64)])
+def test_mlp_workgroup_waves_parity(nh, width):
+    """The 8-wave MLP training kernel (taken where its LDS fits; the 3 x 64
+    network falls back to 4 waves) against the oracle under the bf16 rounding
+    model, and against the 4-wave kernel on the same draws: the two differ only
+    in the order of the fp32 weight-gradient sums."""
+    say(f"mlp 8-wave workgroup parity {nh}x{width}")
+    cfg = (C1[0], o.MLP(nh, width))
+    vol = gaussian_sum_field(64, seed=1)
+    lay = o.layout(*cfg)
+    p = init_param_draws(lay.n_table_params, lay.mlp_shapes, seed=4).astype(np.float64)
+    p[:lay.n_table_params] *= 1e3
+    x = o.training_coords(78, 0, 0, 4096)
+    grads = {}
+    for wg in (4, 8):
+        model = make(cfg, [((64, 64, 64), 0)], precision="mixed", max_batch=1 << 14, seed=77)
+        model.set_option("mlp_wg_waves", wg)
+        model.bind_volumes([dev(vol)])
+        model.load_params([p])
+        model.set_option("apply_update", 0)
+        loss = model.train_step_coords(dev(x), [4096])
+        torch.cuda.synchronize()
+        grads[wg] = (model.block_grads(0).cpu().numpy().astype(np.float64), loss.item())
+        del model
+    tgt = o.normalized_targets(vol, (64, 64, 64), 0, x)
+    gg, L8 = grads[8]
+    check_mixed(gg.astype(np.float32), L8, lay, p, x, tgt, f"mlp {nh}x{width} 8 waves")
+    g4, L4 = grads[4]
+    assert abs(L8 - L4) <= 1e-6 * abs(L4)
+    nt = lay.n_table_params
+    assert normwise(gg[:nt], g4[:nt]) <= 1e-5, "table gradient, 8 against 4 waves"
+    assert normwise(gg[nt:], g4[nt:]) <= 1e-5, "weight gradient, 8 against 4 waves"
 
 
 @pytest.mark.parametrize("precision,priv,classes,binned", [("fp32", -1, 0, 1), ("fp32", -1, 1, 1), ("fp32", 0, 0, 0),
@@ -242,7 +286,7 @@ FINE_CASES = [("fp32", 0, 1, 0, 1, -1, 0, 8192, 16), ("fp32", 1, 1, 0, 1, -1, 0,
               ("fp32", 0, 1, 1, 1, -1, 0, 8192, 16),
               # mixed, automatic: with Adam in the slice pass every level with at
               # least 2^15 entries is partitioned (levels 4..15), however sparse
-              ("mixed", 0, 1, 0, 1, -1, 0, 8192, 4),
+              ("mixed", 0, 1, 0, 1, -1, 0, 8192, 4), ("mixed", 0, 8, 0, 1, -1, 0, 8192, 4),
               # mixed with every level privatized (the in-kernel direct atomics of
               # the fine levels), two MLP waves per SIMD, LDS classes
               ("mixed", 0, 2, 0, 1, 16, 0, 8192, 16), ("mixed", 1, 1, 1, 1, 16, 0, 8192, 16),
@@ -254,7 +298,8 @@ FINE_CASES = [("fp32", 0, 1, 0, 1, -1, 0, 8192, 16), ("fp32", 1, 1, 0, 1, -1, 0,
               # 16384 samples, 64 slices per level: 4 sub-buckets per bucket
               ("fp32", 0, 1, 0, 1, 9, 0, 16384, 9, 16384),
               # ragged sample counts: a partial last tile and uneven bins
-              ("fp32", 0, 1, 0, 1, 9, 0, 8192, 9, 10000), ("mixed", 0, 1, 0, 1, 4, 0, 8192, 4, 9999)]
+              ("fp32", 0, 1, 0, 1, 9, 0, 8192, 9, 10000), ("mixed", 0, 1, 0, 1, 4, 0, 8192, 4, 9999),
+              ("mixed", 0, 8, 0, 1, 4, 0, 8192, 4, 9999)]
 FINE_CASES = [c if len(c) == 10 else c + (8192,) for c in FINE_CASES]
 
 
@@ -284,7 +329,7 @@ def test_sorted_sampling_gradient_parity_fine_levels(precision, classes, waves, 
     model.set_option("spatial_sort", sort)
     model.set_option("priv_levels", -1)
     model.set_option("priv_classes", classes)
-    model.set_option("mlp_waves", waves)
+    set_waves(model, waves)
     model.set_option("scatter_concurrent", conc)
     model.set_option("scatter_part", part)
     model.set_option("part_capacity", cap)
