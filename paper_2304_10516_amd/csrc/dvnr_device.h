@@ -116,6 +116,17 @@ __device__ __forceinline__ float fsub_nc(float a, float b) {
   return a - b;
 }
 
+// fp16 bits (round to nearest even) of the fp32 value x itself.  The empty asm
+// keeps the compiler from fusing the conversion into the FMA that produced x:
+// the fused form (v_fma_mix) rounds the unrounded result straight to fp16,
+// which differs from rounding the stored fp32 value where that value is a
+// tie between two fp16 neighbours.
+__device__ __forceinline__ uint32_t half_bits_of(float x) {
+  asm volatile("" : "+v"(x));
+  const __half h = __float2half_rn(x);
+  return (uint32_t)(*reinterpret_cast<const uint16_t*>(&h));
+}
+
 // ---------------------------------------------------------------------------
 // Grid position on a level of R vertices per axis.  x is clamped to [0,1];
 // p = x*(R-1) is a single round-to-nearest float multiply (never contracted

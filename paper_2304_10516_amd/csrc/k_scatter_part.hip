@@ -464,10 +464,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(part_accum_w
     const float t1 = th0 - lrbc1 * m1 * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(v1 * bc2) + adam.eps);
     return make_float3(t1, m1, v1);
   };
-  auto half_bits = [](float x) -> uint32_t {
-    const __half hv = __float2half_rn(x);
-    return (uint32_t)(*reinterpret_cast<const uint16_t*>(&hv));
-  };
+  auto half_bits = [](float x) -> uint32_t { return half_bits_of(x); };
   auto update = [&](auto ovf_tag, auto w16_tag) {
     constexpr bool OVF = decltype(ovf_tag)::value, W16 = decltype(w16_tag)::value;
     const auto rp = rsrc(adam.params + eb, bbytes), rm = rsrc(adam.m + eb, bbytes), rv = rsrc(adam.v + eb, bbytes);

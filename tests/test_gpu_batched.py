@@ -182,3 +182,31 @@ def test_batched_default_plan_512_block_subset(c5_blocks, precision):
     bins, priv = model.plan_info()
     say(f"plan: {bins}^3 bins, privatized levels [0, {priv}), partitioned from {model.partitioned_levels()}")
     _check_blocks(lay, model, ps, loss.cpu().numpy()[0], c5_blocks, precision, total, seed, "c5 subset")
+
+
+def test_working_copy_is_rounded_master(c3_blocks):
+    """Mixed precision keeps a 16-bit working copy of every parameter: after
+    training steps (default plan: Adam in the slice pass for levels 5-15, the
+    Adam kernel for the rest) each table entry of the copy is the fp16
+    rounding (to nearest even) of the stored fp32 parameter and each MLP
+    weight its bf16 rounding, bit for bit, also where the fp32 value is a tie
+    between two 16-bit neighbours."""
+    total, seed = 8 * 16384, 35
+    lay = o.layout(*C3)
+    blocks = [(b["dims"], b["ghost"]) for b in c3_blocks]
+    model = _model(C3, blocks, "mixed", total, seed)
+    model.bind_volumes([torch.as_tensor(b["data"], device="cuda") for b in c3_blocks])
+    model.load_params(_params(lay, len(blocks), 70, positive=False))
+    model.train(3, total)
+    torch.cuda.synchronize()
+    assert model.partitioned_levels() == 5
+    S, nt = model.block_stride, lay.n_table_params
+    nm = lay.n_params - nt
+    bad = 0
+    for b in range(len(blocks)):
+        p = model.params[b * S:b * S + nt + nm]
+        w = model.work16[b * S:b * S + nt + nm]
+        bad += int((w[:nt] != p[:nt].half().view(torch.int16)).sum())
+        bad += int((w[nt:] != p[nt:].bfloat16().view(torch.int16)).sum())
+    say(f"working copy against the rounded master parameters: {bad} mismatches")
+    assert bad == 0
