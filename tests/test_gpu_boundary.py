@@ -111,6 +111,42 @@ def test_l1_boundary_gradient_parity(sort):
     assert normwise(gg[nt:], g[nt:]) <= tol, "weight gradient"
 
 
+@pytest.mark.parametrize("sort", [0, 1])
+def test_l1_boundary_gradient_parity_mixed(sort):
+    """Mixed precision under the L1 loss with boundary samples: one step's loss
+    and gradient against the bf16 rounding model of the oracle (the bars of the
+    L2 tests), plus, per sample whose model residual lies within float32
+    reach of zero (its sign, and so its whole dL/do = +-1/n, may come out
+    either way on the GPU), that sample's full gradient contribution as
+    slack."""
+    from tests import precision_model as pm
+    say(f"one-step L1 + boundary gradient mixed spatial_sort={sort}")
+    vol, lay, p0, model = _c1_setup("mixed")
+    p = p0.astype(np.float64).copy()
+    p[:lay.n_table_params] *= 1e3
+    model.load_params([p])
+    model.set_loss("l1", LAM, SIGMA)
+    model.set_option("spatial_sort", sort)
+    model.set_option("apply_update", 0)
+    model.set_option("use_graph", 0)
+    loss = model.train(1, 4096, want_loss=True)
+    torch.cuda.synchronize()
+    x = o.step_coords(77, 0, 0, 4096, o.boundary_count(4096, LAM), SIGMA)
+    tgt = o.normalized_targets(vol, (64, 64, 64), 0, x)
+    wc = pm.working_copy(lay, p)
+    r = pm.infer(lay, wc, x) - tgt
+    close = np.nonzero(np.abs(r) < 1e-5)[0]
+    gg = model.block_grads(0).cpu().numpy()
+    # a sign flip of sample i changes the gradient by twice its contribution
+    flips = [2.0 * pm.loss_and_grad(lay, wc, x[i:i + 1], tgt[i:i + 1], "l1", n_scale=len(x))[1] for i in close]
+    ge = o.loss_and_grad(lay, p, x, tgt, "l1")[1]
+    slack = max([0.0] + [float(np.linalg.norm(f[a:b]) / max(np.linalg.norm(ge[a:b]), 1e-300))
+                         for f in flips for a, b in pm.level_spans(lay) + [(lay.n_table_params, lay.n_params)]])
+    say(f"loss gpu {loss[0, 0].item():.6e}; {len(close)} residuals within 1e-5 of zero, slack {slack:.1e}")
+    res = pm.check_mixed_gradient(gg, lay, wc, x, tgt, "l1", floor=1e-4 + len(close) * slack)
+    assert abs(loss[0, 0].item() - res["loss_model"]) <= 1e-5 * res["loss_model"]
+
+
 def test_l1_boundary_end_to_end_psnr_within_03db():
     """Under the L1 loss the trajectory is chaotic after ~50 steps (a residual
     that changes sign moves the gradient by 2/n against a sum of +-1/n terms),
