@@ -145,8 +145,9 @@ template <typename T> __device__ __forceinline__ float ldf(const T* p) { return 
 // workgroup writes its partial dW and loss of the finished block into slot
 // (w + block) and loads the new block's weights.
 // ---------------------------------------------------------------------------
-// MINW: waves per SIMD the register allocation must allow (2 trades spills
-// for latency hiding; selected at run time, measured by the autotuner).
+// MINW: waves per SIMD the 4-wave kernel's register allocation must allow
+// (2 trades spills for latency hiding; option mlp_waves).  The 8-wave kernel
+// runs two waves per SIMD by its workgroup size.
 template <class TR, int W, int NH, typename FT, typename WSRC, int MINW, int NW>
 __global__ __launch_bounds__(64 * NW, MINW) void k_mlp_train(MlpDesc md, int F, const BlockMeta* __restrict__ meta,
                                                    const BlockPlan* __restrict__ plan,
@@ -434,7 +435,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void k_mlp_train(MlpDesc md, int F, 
       yr = yn;
       if (q != S::GP - 1) continue;
       __syncthreads();  // all waves' staging of this pass is complete
-      // ---- weight gradients: this wave's output tiles over the 4 waves' staged samples
+      // ---- weight gradients: this wave's output tiles over all NW waves' staged samples
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int t = wave + NW * u;
