@@ -195,3 +195,20 @@ def test_partitioned_backward_options():
             assert lib.dvnr_set_option(h, b"priv_classes", v) == 0
     finally:
         lib.dvnr_destroy(h)
+
+
+def test_mlp_and_sampler_options():
+    """Option validation of the MLP kernel variants (waves per workgroup 4 or
+    8; register budget of the 4-wave kernel) and of the sampler look-ahead's
+    fork point (0 .. 3)."""
+    lib, code, h = _make(o.Encoding(16, 2, 19, 16, 0.0, 256), o.MLP(2, 64), precision="mixed")
+    assert code == 0
+    try:
+        for v, ok in ((4, 0), (8, 0), (0, 1), (2, 1), (6, 1), (16, 1)):
+            assert lib.dvnr_set_option(h, b"mlp_wg_waves", v) == ok, v
+        for v in (1, 2):
+            assert lib.dvnr_set_option(h, b"mlp_waves", v) == 0
+        for v, ok in ((0, 0), (1, 0), (2, 0), (3, 0), (4, 1), (-1, 1)):
+            assert lib.dvnr_set_option(h, b"sample_ahead", v) == ok, v
+    finally:
+        lib.dvnr_destroy(h)
